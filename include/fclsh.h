@@ -1,0 +1,214 @@
+/*
+ * fclsh.h -- C ABI of the MI355X (gfx950) Fast CoveringLSH library.
+ *
+ * Fast CoveringLSH (Pham & Pagh, "Scalability and Total Recall with Fast
+ * CoveringLSH", arXiv:1602.02620) answers r-near-neighbour *reporting* in
+ * Hamming space exactly (Def. 2 with delta = 0): a query returns every data
+ * point within Hamming distance r, with no false negatives.  The index holds
+ * L = t * (2^(r'+1) - 1) hash tables; a point's L bucket keys are computed in
+ * O(d + L log L) with the fast Hadamard transform (Alg. 2) instead of the
+ * O(d L) of the basic CoveringLSH masks (Eq. (2), Eq. (1)).
+ *
+ * Conventions shared by every call:
+ *  - Points and queries are bit vectors of d coordinates, packed row-major as
+ *    W = ceil(d/64) uint64 words per vector; coordinate c is bit (c & 63) of
+ *    word (c >> 6).  Bits beyond d in the last word are ignored.
+ *  - Pointers named d_* are DEVICE pointers (HIP device memory of the current
+ *    device); all others are host pointers.  Input buffers stay owned by the
+ *    caller and are only read during the call (and, for asynchronous calls,
+ *    until the work on `stream` has finished).  The index copies what it
+ *    keeps.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    enqueue their kernels on it and return; a call that must read a size
+ *    back to the host (query result sizes, oversize-bucket detection in the
+ *    build) synchronises that stream.
+ *  - Every call returns FCLSH_OK (0) or a negative status; the thread-local
+ *    fclsh_last_error() then describes the failure.  On failure no output is
+ *    valid and no index is created.
+ *  - The keys use the Mersenne prime P = 2^31 - 1 (a reading of the paper's
+ *    "sufficiently large prime"; P affects only false bucket merges, never
+ *    recall).
+ */
+#ifndef FCLSH_H
+#define FCLSH_H
+
+#include <stdint.h>
+
+/* The library is built with hidden visibility; only these calls are exported. */
+#define FCLSH_API __attribute__((visibility("default")))
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fclsh_status;
+
+#define FCLSH_OK 0
+#define FCLSH_EINVAL (-1)      /* bad argument (size, radius, pointer)          */
+#define FCLSH_ERADIUS (-2)     /* query radius larger than the index radius    */
+#define FCLSH_ENOMEM (-3)      /* device allocation failed or over the budget  */
+#define FCLSH_ECAPACITY (-4)   /* output buffer too small; *total_out is set   */
+#define FCLSH_EDEVICE (-5)     /* HIP runtime error                            */
+#define FCLSH_EUNSUPPORTED (-6)/* parameters the GPU kernels do not cover      */
+
+/* Opaque, immutable once built; may be queried from several streams. */
+typedef struct fclsh_index_s *fclsh_index;
+
+/* Build options (all-zero = the paper's defaults). */
+typedef struct {
+    int32_t partitions;        /* t; 0 = the experiments' rule: 1 if r < 10 else 2
+                                  (Sec. 4.1 parameter settings, Sec. 4.3)          */
+    int32_t reserved;          /* must be 0                                        */
+    uint64_t prime;            /* 0 or 2^31-1 (the only prime the kernels support) */
+    uint64_t mem_budget_bytes; /* 0 = no limit; else the build fails with
+                                  FCLSH_ENOMEM if the index and its build scratch
+                                  would exceed it                                  */
+} fclsh_build_opts;
+
+/* ---------------------------------------------------------------------------
+ * Index parameters (host only, no device work).
+ *
+ * Alg. 1 (pre-processing) with the experiments' choice of t, and the random
+ * draws of Alg. 2: per part a mapping m into the 2^(r'+1) Hadamard columns
+ * (general construction, Eq. (5), when the part has more than 2^(r'+1)
+ * coordinates) or a random permutation of the columns (specific construction,
+ * 0-padded), and the seed vector b in [P]^d of Eq. (1).  r' = floor(r/t).
+ *
+ * Draws come from SplitMix64 seeded with `seed` (counter-based: output k is
+ * the finaliser applied to seed + (k+1) * 0x9E3779B97F4A7C15), unbiased
+ * bounded draws by rejection, in the order: the coordinate permutation
+ * (only if t > 1; Fisher-Yates from the last position down), then per part
+ * its column permutation (Fisher-Yates of [0, 2^(r'+1))) or its i.i.d.
+ * columns in permuted-coordinate order, then b[0..d).  Part p is positions
+ * [p*floor(d/t), (p+1)*floor(d/t)) of the permutation, the last part taking
+ * the remainder.
+ *
+ * Outputs (host arrays of d entries): part[c] in [0,t), col[c] in
+ * [0, 2^(r'+1)), b[c] in [0, P).  *t_out and *r_part_out receive t and r'.
+ * Errors: FCLSH_EINVAL (d <= 0, r < 0, null pointer), FCLSH_EUNSUPPORTED
+ * (r' > 11, t > 64 or t > d, prime other than 2^31-1).
+ * ------------------------------------------------------------------------- */
+FCLSH_API fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed,
+                                 const fclsh_build_opts *opts, int32_t *t_out,
+                                 int32_t *r_part_out, int32_t *part, int32_t *col,
+                                 uint64_t *b);
+
+/* ---------------------------------------------------------------------------
+ * Build an index over n points (Def. 2: the data structure over S).
+ *
+ * d_points: device, n*W uint64 (layout above).  n in [1, 2^31-1].
+ * d in [1, 4096], r >= 0; parameters from fclsh_derive_params(d, r, seed);
+ * at most 65535 tables.
+ * The build hashes every point into its L keys (Alg. 2), then buckets each
+ * table (hash tables of non-empty buckets, Sec. 2.2): every table is stored
+ * as its n (key, id) pairs sorted by key then id, with a directory over the
+ * top key bits.  The index keeps a copy of the points for the distance
+ * checks of queries.  Index memory is allocated by the library on the current
+ * device and released by fclsh_index_free.
+ * Errors: FCLSH_EINVAL, FCLSH_EUNSUPPORTED, FCLSH_ENOMEM, FCLSH_EDEVICE.
+ * ------------------------------------------------------------------------- */
+FCLSH_API fclsh_status fclsh_build_index(const uint64_t *d_points, int64_t n, int32_t d,
+                               int32_t r, uint64_t seed,
+                               const fclsh_build_opts *opts, void *stream,
+                               fclsh_index *out);
+
+/* Same, with explicit parameters instead of a seed: t parts, per-part radius
+ * r_part, host arrays part[d] (every part non-empty), col[d] < 2^(r_part+1)
+ * and b[d] < prime.  Covering (Theorem 1) holds for every mapping and Lemma 3
+ * for every b, so any such arrays index radius r as long as the pigeonhole
+ * split of Sec. 3.1.2 leaves some part with at most r_part differences:
+ * floor(r/t) <= r_part (else FCLSH_EINVAL).  prime must be 0 or 2^31-1.
+ * Errors as fclsh_build_index. */
+FCLSH_API fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, int64_t n,
+                                           int32_t d, int32_t r, int32_t t,
+                                           int32_t r_part, const int32_t *part,
+                                           const int32_t *col, const uint64_t *b,
+                                           uint64_t prime, void *stream,
+                                           fclsh_index *out);
+
+/* ---------------------------------------------------------------------------
+ * Exact r-NN reporting for a batch of queries (Def. 2, Strategy 2 of
+ * Sec. 2.2 with Steps S1-S3 of Sec. 4.1): for each query, every data point id
+ * at Hamming distance <= r_query, ids ascending.
+ *
+ * d_queries: device, nq*W uint64.  nq >= 0.  0 <= r_query <= the index's r
+ * (an r-covering family covers every smaller radius); larger r_query gives
+ * FCLSH_ERADIUS.
+ * Output (device, caller-owned): d_offsets[nq+1] uint64 CSR offsets and
+ * d_ids[ids_capacity] uint32; query i's neighbours are
+ * d_ids[d_offsets[i] .. d_offsets[i+1]).  *total_out (host) receives the
+ * total number of reported ids.  If it exceeds ids_capacity the call returns
+ * FCLSH_ECAPACITY with *total_out set and d_ids untouched (d_offsets is
+ * written); retry with a larger buffer.
+ * The call synchronises `stream` once, to read the result size.
+ * Duplicate elimination: a verified near point is reported only from the
+ * first table (in (part, v) order) whose mask it shares with the query;
+ * covering guarantees that table exists and that the point lies in the
+ * query's bucket there, so each neighbour is reported exactly once.
+ * ------------------------------------------------------------------------- */
+FCLSH_API fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries,
+                               int64_t nq, int32_t r_query, void *stream,
+                               uint64_t *d_offsets, uint32_t *d_ids,
+                               int64_t ids_capacity, int64_t *total_out);
+
+/* Release an index (NULL is ignored).  The caller must make sure no work using
+ * it is still queued. */
+FCLSH_API void fclsh_index_free(fclsh_index idx);
+
+/* Thread-local description of the last failure ("" if none). */
+FCLSH_API const char *fclsh_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Hot-path pieces, exported for tests and measurement.
+ * ------------------------------------------------------------------------- */
+
+/* Shape of a built index. Any output pointer may be NULL. */
+FCLSH_API fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r,
+                              int32_t *t, int32_t *r_part, int64_t *n,
+                              int32_t *L, int32_t *dir_bits);
+
+/* The parameters an index was built with (host arrays of d entries). */
+FCLSH_API fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col,
+                                uint64_t *b);
+
+/* Alg. 2 on a batch: the L keys of m points under the index's hash family.
+ * d_pts: device m*W uint64; d_keys: device [L][m] uint32, key of point i in
+ * table T = p*(2^(r'+1)-1) + (v-1) at d_keys[T*m + i] (v = 1..2^(r'+1)-1:
+ * the all-zero first Hadamard row is dropped).  Asynchronous on `stream`. */
+FCLSH_API fclsh_status fclsh_hash(fclsh_index idx, const uint64_t *d_pts, int64_t m,
+                        uint32_t *d_keys, void *stream);
+
+/* Device pointers of the index's tables: keys and ids [L][n] uint32 (table T
+ * at offset T*n, sorted by key then id), directory [L][2^dir_bits + 1] uint32
+ * (start of the entries whose key has the given top dir_bits bits of 31) and
+ * the point copy [n][W] uint64.  Owned by the index; read only. */
+FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys,
+                                const uint32_t **d_tids, const uint32_t **d_dir,
+                                const uint64_t **d_points);
+
+/* Rebuild the tables of an existing index from its own points (the bucketing
+ * step alone: hash + table build), for timing.  Asynchronous except for the
+ * oversize-bucket check. */
+FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
+
+/* Per-query diagnostics of Sec. 4.1: #Collisions (summed sizes of the query's
+ * L buckets) for each query, written to device d_collisions[nq] (uint64).
+ * Asynchronous. */
+FCLSH_API fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries,
+                                    int64_t nq, void *stream,
+                                    uint64_t *d_collisions);
+
+/* The plain path: one query at a time, each answered by its own launch
+ * sequence (hash, lookup and verify, compaction) and a synchronisation; the
+ * baseline the batched path is measured against.  Same outputs and errors as
+ * fclsh_query_batch. */
+FCLSH_API fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_queries,
+                               int64_t nq, int32_t r_query, void *stream,
+                               uint64_t *d_offsets, uint32_t *d_ids,
+                               int64_t ids_capacity, int64_t *total_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCLSH_H */

@@ -1,0 +1,300 @@
+"""Python binding of the gfx950 Fast CoveringLSH library (libfclsh.so).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and the stream.  There
+is no CPU fallback: if the library is not built, importing works but every
+call raises.
+
+    idx = Index(points, d=256, r=8, seed=3002)       # points: int64 [n, W] on the GPU
+    offsets, ids = idx.query(queries, r=8)           # CSR: ids of query i in ids[offsets[i]:offsets[i+1]]
+    keys = idx.hash(points)                          # [L, n] uint32 keys (as int32 storage)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfclsh.so")
+
+FCLSH_OK = 0
+FCLSH_EINVAL = -1
+FCLSH_ERADIUS = -2
+FCLSH_ENOMEM = -3
+FCLSH_ECAPACITY = -4
+FCLSH_EDEVICE = -5
+FCLSH_EUNSUPPORTED = -6
+
+# Every C-ABI entry point declared in include/fclsh.h.
+EXPORTS = [
+    "fclsh_derive_params", "fclsh_build_index", "fclsh_build_index_with_params", "fclsh_query_batch",
+    "fclsh_index_free", "fclsh_last_error", "fclsh_index_info", "fclsh_index_params", "fclsh_hash",
+    "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_query_collisions", "fclsh_query_plain",
+]
+
+
+class FclshError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fclsh status {status}: {msg}")
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("partitions", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prime", ctypes.c_uint64), ("mem_budget_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfclsh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1602_02620_amd/build.py` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+        P = ctypes.POINTER
+        sig = {
+            "fclsh_derive_params": [i32, i32, u64, P(BuildOpts), P(i32), P(i32), vp, vp, vp],
+            "fclsh_build_index": [vp, i64, i32, i32, u64, P(BuildOpts), vp, P(vp)],
+            "fclsh_build_index_with_params": [vp, i64, i32, i32, i32, i32, vp, vp, vp, u64, vp, P(vp)],
+            "fclsh_query_batch": [vp, vp, i64, i32, vp, vp, vp, i64, P(i64)],
+            "fclsh_query_plain": [vp, vp, i64, i32, vp, vp, vp, i64, P(i64)],
+            "fclsh_index_info": [vp, P(i32), P(i32), P(i32), P(i32), P(i64), P(i32), P(i32)],
+            "fclsh_index_params": [vp, vp, vp, vp],
+            "fclsh_hash": [vp, vp, i64, vp, vp],
+            "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
+            "fclsh_index_rebuild": [vp, vp],
+            "fclsh_query_collisions": [vp, vp, i64, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.fclsh_index_free.argtypes = [vp]
+        L.fclsh_index_free.restype = None
+        L.fclsh_last_error.argtypes = []
+        L.fclsh_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != FCLSH_OK:
+        raise FclshError(status, lib().fclsh_last_error().decode())
+
+
+def words(d: int) -> int:
+    return (d + 63) // 64
+
+
+def derive_params(d: int, r: int, seed: int, partitions: int = 0):
+    """Host-only parameter draw: returns dict(t, r_part, part, col, b)."""
+    part = np.zeros(d, np.int32)
+    col = np.zeros(d, np.int32)
+    b = np.zeros(d, np.uint64)
+    t = ctypes.c_int32()
+    rp = ctypes.c_int32()
+    opts = BuildOpts(partitions, 0, 0, 0)
+    _check(lib().fclsh_derive_params(d, r, seed & (2**64 - 1), ctypes.byref(opts), ctypes.byref(t),
+                                     ctypes.byref(rp), part.ctypes.data, col.ctypes.data, b.ctypes.data))
+    return {"t": t.value, "r_part": rp.value, "part": part, "col": col, "b": b}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_words(x, d: int, what: str):
+    """A contiguous int64 [m, W] CUDA tensor holding packed bit vectors."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if x.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"{what} must hold 64-bit words")
+    x = x.contiguous()
+    if x.dim() != 2 or x.shape[1] != words(d):
+        raise ValueError(f"{what} must have shape [m, {words(d)}]")
+    return x
+
+
+def to_device_words(arr: np.ndarray, device="cuda"):
+    """numpy uint64 [m, W] -> int64 CUDA tensor with the same bits."""
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(arr, np.uint64).view(np.int64)).to(device)
+
+
+class Index:
+    """An exact r-NN index (Def. 2) built on the GPU.  Immutable."""
+
+    def __init__(self, points, d: int, r: int, seed: int = 0, partitions: int = 0,
+                 mem_budget_bytes: int = 0, stream=None, *, _params=None):
+        torch = _torch()
+        pts = _dev_words(points, d, "points")
+        n = pts.shape[0]
+        h = ctypes.c_void_p()
+        st = _stream_ptr(stream)
+        if _params is None:
+            opts = BuildOpts(partitions, 0, 0, mem_budget_bytes)
+            _check(lib().fclsh_build_index(ctypes.c_void_p(pts.data_ptr()), n, d, r, seed & (2**64 - 1),
+                                           ctypes.byref(opts), st, ctypes.byref(h)))
+        else:
+            t, rp, part, col, b = _params
+            part = np.ascontiguousarray(part, np.int32)
+            col = np.ascontiguousarray(col, np.int32)
+            b = np.ascontiguousarray(b, np.uint64)
+            _check(lib().fclsh_build_index_with_params(ctypes.c_void_p(pts.data_ptr()), n, d, r, t, rp,
+                                                       part.ctypes.data, col.ctypes.data, b.ctypes.data,
+                                                       0, st, ctypes.byref(h)))
+        self._h = h
+        self.d = d
+        self.device = pts.device
+        del torch
+
+    @classmethod
+    def with_params(cls, points, d: int, r: int, t: int, r_part: int, part, col, b, stream=None):
+        return cls(points, d, r, stream=stream, _params=(t, r_part, part, col, b))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().fclsh_index_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> dict:
+        d, r, t, rp, L, db = (ctypes.c_int32() for _ in range(6))
+        n = ctypes.c_int64()
+        _check(lib().fclsh_index_info(self._h, ctypes.byref(d), ctypes.byref(r), ctypes.byref(t),
+                                      ctypes.byref(rp), ctypes.byref(n), ctypes.byref(L), ctypes.byref(db)))
+        return {"d": d.value, "r": r.value, "t": t.value, "r_part": rp.value, "n": n.value, "L": L.value,
+                "dir_bits": db.value}
+
+    def params(self) -> dict:
+        d = self.d
+        part = np.zeros(d, np.int32)
+        col = np.zeros(d, np.int32)
+        b = np.zeros(d, np.uint64)
+        _check(lib().fclsh_index_params(self._h, part.ctypes.data, col.ctypes.data, b.ctypes.data))
+        return {"part": part, "col": col, "b": b}
+
+    def hash(self, points, out=None, stream=None):
+        """[L, m] keys (int32 storage of the uint32 keys) of m points."""
+        torch = _torch()
+        pts = _dev_words(points, self.d, "points")
+        m = pts.shape[0]
+        L = self.info["L"]
+        if out is None:
+            out = torch.empty((L, m), dtype=torch.int32, device=pts.device)
+        _check(lib().fclsh_hash(self._h, ctypes.c_void_p(pts.data_ptr()), m, ctypes.c_void_p(out.data_ptr()),
+                                _stream_ptr(stream)))
+        return out
+
+    def rebuild(self, stream=None):
+        _check(lib().fclsh_index_rebuild(self._h, _stream_ptr(stream)))
+
+    def table_pointers(self):
+        k, i, dr, p = (ctypes.c_void_p() for _ in range(4))
+        _check(lib().fclsh_index_tables(self._h, ctypes.byref(k), ctypes.byref(i), ctypes.byref(dr),
+                                        ctypes.byref(p)))
+        return k.value, i.value, dr.value, p.value
+
+    def tables(self, T0: int = 0, T1: int | None = None):
+        """Copies of tables [T0, T1): (keys, ids) as int32 CUDA tensors [T1-T0, n]."""
+        torch = _torch()
+        inf = self.info
+        n, L = inf["n"], inf["L"]
+        T1 = L if T1 is None else T1
+        kp, ip, _, _ = self.table_pointers()
+        keys = torch.empty((T1 - T0, n), dtype=torch.int32, device=self.device)
+        ids = torch.empty_like(keys)
+        _memcpy_d2d(keys.data_ptr(), kp + T0 * n * 4, (T1 - T0) * n * 4)
+        _memcpy_d2d(ids.data_ptr(), ip + T0 * n * 4, (T1 - T0) * n * 4)
+        return keys, ids
+
+    def directory(self):
+        torch = _torch()
+        inf = self.info
+        nb = (1 << inf["dir_bits"]) + 1
+        _, _, dp, _ = self.table_pointers()
+        out = torch.empty((inf["L"], nb), dtype=torch.int32, device=self.device)
+        _memcpy_d2d(out.data_ptr(), dp, inf["L"] * nb * 4)
+        return out
+
+    def _run_query(self, fn, queries, r: int, ids_capacity=None, stream=None):
+        torch = _torch()
+        q = _dev_words(queries, self.d, "queries")
+        nq = q.shape[0]
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=q.device)
+        cap = int(ids_capacity) if ids_capacity is not None else max(1024, 64 * nq)
+        total = ctypes.c_int64()
+        for _ in range(2):
+            ids = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
+            st = fn(self._h, ctypes.c_void_p(q.data_ptr()), nq, r, _stream_ptr(stream),
+                    ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(ids.data_ptr()), cap,
+                    ctypes.byref(total))
+            if st == FCLSH_ECAPACITY and ids_capacity is None:
+                cap = total.value
+                continue
+            _check(st)
+            return offsets, ids[:total.value]
+        raise FclshError(FCLSH_ECAPACITY, "result did not fit after resizing")
+
+    def query(self, queries, r: int, ids_capacity=None, stream=None):
+        """Exact r-NN reporting for a batch: (offsets int64 [nq+1], ids int32 [total])."""
+        return self._run_query(lib().fclsh_query_batch, queries, r, ids_capacity, stream)
+
+    def query_plain(self, queries, r: int, ids_capacity=None, stream=None):
+        """Same answers via one launch sequence per query (the unbatched baseline)."""
+        return self._run_query(lib().fclsh_query_plain, queries, r, ids_capacity, stream)
+
+    def collisions(self, queries, stream=None):
+        """#Collisions (Sec. 4.1) per query, int64 [nq]."""
+        torch = _torch()
+        q = _dev_words(queries, self.d, "queries")
+        out = torch.empty(q.shape[0], dtype=torch.int64, device=q.device)
+        _check(lib().fclsh_query_collisions(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0],
+                                            _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    """Device-to-device copy on torch's current stream, through the HIP runtime."""
+    global _hip
+    torch = _torch()
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                        ctypes.c_void_p]
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+    rc = _hip.hipMemcpyAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3,
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
+def split_csr(offsets, ids):
+    """CSR (torch tensors) -> list of numpy uint32 arrays."""
+    o = offsets.cpu().numpy()
+    v = ids.cpu().numpy().view(np.uint32)
+    return [v[o[i]:o[i + 1]] for i in range(len(o) - 1)]

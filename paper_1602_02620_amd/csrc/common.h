@@ -1,0 +1,158 @@
+// Shared definitions of the gfx950 Fast CoveringLSH library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fclsh.h"
+
+namespace fclsh {
+
+// Mersenne prime 2^31 - 1: the modulus of the Eq. (1) universal hash.
+constexpr uint32_t kPrime = 0x7FFFFFFFu;
+// Largest per-part Hadamard order handled by the kernels: D = 2^(r'+1) <= 4096.
+constexpr int kMaxLogD = 12;
+constexpr int kMaxParts = 64;
+constexpr int kMaxDims = 4096;
+
+void set_error(const char *fmt, ...);
+fclsh_status fail(fclsh_status st, const char *fmt, ...);
+
+#define FCLSH_HIP(expr)                                                        \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return ::fclsh::fail(FCLSH_EDEVICE, "%s failed: %s (%s:%d)", #expr, \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);   \
+    } while (0)
+
+#define FCLSH_TRY(expr)                                                        \
+    do {                                                                       \
+        fclsh_status s_ = (expr);                                              \
+        if (s_ != FCLSH_OK)                                                    \
+            return s_;                                                         \
+    } while (0)
+
+inline int words_of(int d) { return (d + 63) / 64; }
+
+inline int ilog2_ceil(uint64_t x) {
+    int k = 0;
+    while ((uint64_t(1) << k) < x) ++k;
+    return k;
+}
+
+// Host-side parameters of one index (Alg. 1 + Alg. 2 draws).
+struct Params {
+    int d = 0, r = 0, t = 1, rp = 0;
+    std::vector<int32_t> part, col;
+    std::vector<uint64_t> b;
+    int D() const { return 1 << (rp + 1); }
+    int Lp() const { return D() - 1; }
+    int L() const { return t * Lp(); }
+};
+
+fclsh_status derive_params(int d, int r, uint64_t seed, const fclsh_build_opts *opts,
+                           Params *out);
+fclsh_status check_params(const Params &p);
+
+// ----------------------------------------------------------------------------
+// Device allocation with a byte budget.
+// ----------------------------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Per-part gather plan of the hash kernel (see hash.hip).
+struct HashPlan {
+    int logD = 1, G = 1, V = 2, U = 64, t = 1, E = 0, W = 1;
+    int32_t *seg = nullptr;    // [t][V+1] entry ranges per in-lane column k
+    int32_t *coord = nullptr;  // [t][E][G] coordinate of each entry (or the zero slot)
+    double *bval = nullptr;    // [t][E][G] even representative of b mod P, as double
+};
+
+struct Index {
+    Params prm;
+    int W = 1;
+    int64_t n = 0;
+    int dir_bits = 1;
+    int device = 0;
+    uint64_t budget = 0;
+    HashPlan plan;
+    uint64_t *pts = nullptr;   // [n][W]
+    uint32_t *tkeys = nullptr; // [L][n]
+    uint32_t *tids = nullptr;  // [L][n]
+    uint32_t *dir = nullptr;   // [L][2^dir_bits + 1]
+    // per-index device copies of part/col for the duplicate-elimination rule
+    int32_t *dpart = nullptr;
+    int32_t *dcol = nullptr;
+    std::vector<DevBuf> owned;
+    size_t bytes_owned = 0;
+};
+
+fclsh_status dev_alloc(Index *ix, void **p, size_t bytes, const char *what);
+void dev_free_all(Index *ix);
+
+// Scratch memory that lives for one call.
+struct Scratch {
+    std::vector<void *> ptrs;
+    ~Scratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    fclsh_status get(void **p, size_t bytes, const char *what);
+    template <class T>
+    fclsh_status get(T **p, size_t count, const char *what) {
+        return get(reinterpret_cast<void **>(p), count * sizeof(T), what);
+    }
+};
+
+// ----------------------------------------------------------------------------
+// Kernels (launchers)
+// ----------------------------------------------------------------------------
+fclsh_status build_hash_plan(Index *ix);
+fclsh_status launch_hash(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys,
+                         int64_t key_stride, hipStream_t st);
+
+// Stable LSD radix sort of nseg equal-length segments of (key, value) pairs by
+// key bits [begin_bit, end_bit).  vals_in may be null: values are then the
+// element's index within its segment.  The result lands in keys_out/vals_out;
+// the two tmp buffers must hold nseg*len entries each.
+fclsh_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in,
+                              uint32_t *keys_out, uint32_t *vals_out, uint32_t *tmp_keys,
+                              uint32_t *tmp_vals, int64_t nseg, int64_t len, int begin_bit,
+                              int end_bit, Scratch &scr, hipStream_t st);
+
+// Exclusive scan of n uint64 values (in place allowed); *total (device,
+// optional) receives the sum.
+fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *total,
+                                Scratch &scr, hipStream_t st);
+
+fclsh_status build_directory(const uint32_t *tkeys, int64_t nseg, int64_t n, int dir_bits,
+                             uint32_t *dir, hipStream_t st);
+
+fclsh_status build_tables(Index *ix, const uint32_t *keys, Scratch &scr, hipStream_t st);
+
+// Scratch of the query path for one index and stream, grown on demand.
+struct QueryWorkspace {
+    uint32_t *qkeys = nullptr, *rstart = nullptr, *rcount = nullptr, *qcount = nullptr;
+    uint64_t *qcount64 = nullptr, *offs1 = nullptr;
+    unsigned long long *cursor = nullptr;
+    uint32_t *pq = nullptr, *pid = nullptr, *sk = nullptr, *sv = nullptr, *tk = nullptr, *tv = nullptr;
+    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0;
+};
+
+fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs);
+void ws_release(QueryWorkspace &ws);
+fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
+                         hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
+fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
+                         hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
+fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq,
+                              uint64_t *coll, hipStream_t st);
+const char *last_error_cstr();
+
+}  // namespace fclsh

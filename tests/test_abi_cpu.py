@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol include/fclsh.h declares, and its host-only parameter draw
+(Alg. 1 + Alg. 2 random choices) agrees with the oracle's independent
+implementation of the same SplitMix64 recipe."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1602_02620_amd as fc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fclsh.h")
+
+
+def header_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fclsh_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_exports():
+    assert header_symbols() == sorted(fc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", fc.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (fclsh_[a-z_]+)\b", out))
+    missing = [s for s in header_symbols() if s not in exported]
+    assert not missing, missing
+    lib = fc.lib()
+    for s in header_symbols():
+        getattr(lib, s)
+
+
+def test_exports_are_plain_c():
+    # extern "C": no mangled fclsh symbols leak through
+    out = subprocess.run(["nm", "-D", "--defined-only", fc.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    assert "fclsh_" in out
+    mangled = [ln for ln in out.splitlines() if re.search(r"\b_Z\S*fclsh", ln)]
+    assert not mangled, mangled[:3]
+
+
+@pytest.mark.parametrize("d,r,seed,t", [(128, 4, 3001, 0), (256, 8, 3002, 0), (64, 6, 3003, 0),
+                                        (512, 12, 3004, 0), (256, 10, 3005, 0), (1024, 20, 3006, 0),
+                                        (101, 13, 7, 0), (300, 9, 8, 3), (5, 2, 9, 0), (64, 22, 10, 2)])
+def test_params_match_oracle(d, r, seed, t):
+    p = fc.derive_params(d, r, seed, partitions=t)
+    o = oracle.derive_params(d, r, seed, override_t=t)
+    assert p["t"] == o.t and p["r_part"] == o.rpart
+    assert np.array_equal(p["part"], o.part)
+    assert np.array_equal(p["col"], o.col)
+    assert np.array_equal(p["b"], o.b)
+
+
+@pytest.mark.parametrize("d,r,t,status", [(0, 3, 0, fc.FCLSH_EINVAL), (10, -1, 0, fc.FCLSH_EINVAL),
+                                          (64, 24, 0, fc.FCLSH_EUNSUPPORTED),  # r' = 12: 2^13 columns
+                                          (4, 2, 5, fc.FCLSH_EUNSUPPORTED),    # more parts than coordinates
+                                          (5000, 2, 0, fc.FCLSH_EUNSUPPORTED)])
+def test_param_errors(d, r, t, status):
+    with pytest.raises(fc.FclshError) as e:
+        fc.derive_params(d, r, 1, partitions=t)
+    assert e.value.status == status
+    assert fc.lib().fclsh_last_error().decode()
+
+
+def test_largest_supported_family():
+    p = fc.derive_params(64, 11, 1, partitions=1)  # r' = 11: D = 4096 columns
+    assert p["r_part"] == 11 and int(p["col"].max()) < 4096

@@ -1,0 +1,256 @@
+"""GPU parity at sizes the oracle finishes in seconds: every key, every table
+entry, the directory, every query answer and the #Collisions counters of the
+HIP path against the CPU oracle, plus the edge cases (ragged sizes, d not a
+multiple of 64, a single point, no queries, duplicate points, radius limits,
+output capacity, 3 parts, the largest Hadamard order)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._helpers import OracleIndex, as_u32, assert_same_lists, csr_lists
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1602_02620_amd as fc  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return fc.to_device_words(a)
+
+
+def build(w: synth.Workload, seed: int, partitions: int = 0):
+    _say(f"[build] {w.name} n={w.n} d={w.d} r={w.r} seed={seed} t={partitions}")
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=seed, partitions=partitions)
+    pr = oracle.derive_params(w.d, w.r, seed, override_t=partitions)
+    return idx, pr
+
+
+CASES = {
+    # name: (workload factory, index seed, partitions)
+    "small": (lambda: synth.small(0.2), 3001, 0),                       # general, D=32
+    "mid": (lambda: synth.uniform_with_planted(4099, 256, 8, 8, 10, 1102, "mid"), 3002, 0),  # specific, D=512
+    "learned": (lambda: synth.mixture(5003, 64, 6, 6, 0.05, 12, 1103, "learned"), 3003, 0),  # specific, D=128
+    "batched": (lambda: synth.mixture(4001, 512, 12, 8, 0.01, 24, 1104, "batched"), 3004, 0),  # t=2 general D=128
+    "served_a": (lambda: synth.uniform_with_planted(3001, 256, 10, 10, 5, 1105, "served_a"), 3005, 0),  # t=2, D=64
+    "served_b": (lambda: synth.uniform_with_planted(701, 1024, 20, 6, 5, 1106, "served_b"), 3006, 0),  # t=2, D=2048
+    "ragged_d": (lambda: synth.uniform_with_planted(1237, 100, 5, 9, 6, 1107, "ragged_d"), 3007, 0),
+    "three_parts": (lambda: synth.uniform_with_planted(1500, 96, 9, 6, 6, 1108, "three_parts"), 3008, 3),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    make, seed, t = CASES[request.param]
+    w = make()
+    idx, pr = build(w, seed, t)
+    orc = OracleIndex(w.points, pr)
+    yield request.param, w, idx, orc
+    idx.close()
+
+
+def test_params_agree(case):
+    name, w, idx, orc = case
+    p = idx.params()
+    assert np.array_equal(p["part"], orc.pr.part) and np.array_equal(p["col"], orc.pr.col)
+    assert np.array_equal(p["b"], orc.pr.b)
+    assert idx.info["L"] == orc.pr.L
+
+
+def test_keys_bit_exact(case):
+    """Lemma 3: the FHT keys equal the Eq. (1) keys of the basic masks."""
+    name, w, idx, orc = case
+    _say(f"[keys] {name}")
+    got = as_u32(idx.hash(dev(w.points)))
+    assert got.shape == orc.keys.shape
+    bad = np.argwhere(got != orc.keys)
+    assert bad.size == 0, f"{len(bad)} keys differ, first (table, point) {bad[:5].tolist()}"
+    # queries through the same kernel
+    qk = as_u32(idx.hash(dev(w.queries)))
+    assert np.array_equal(qk, orc.query_keys(w.queries))
+
+
+def test_tables_bit_exact(case):
+    name, w, idx, orc = case
+    _say(f"[tables] {name}")
+    tk, ti = idx.tables()
+    assert np.array_equal(as_u32(tk), orc.tk)
+    assert np.array_equal(as_u32(ti), orc.ti)
+
+
+def test_directory(case):
+    name, w, idx, orc = case
+    db = idx.info["dir_bits"]
+    dr = as_u32(idx.directory())
+    bins = orc.tk >> np.uint32(31 - db)
+    for T in range(0, orc.pr.L, max(1, orc.pr.L // 17)):
+        want = np.searchsorted(bins[T], np.arange((1 << db) + 1), side="left")
+        assert np.array_equal(dr[T], want.astype(np.uint32))
+
+
+def test_queries_exact(case):
+    """Def. 2 with delta = 0: every point within r, nothing else."""
+    name, w, idx, orc = case
+    _say(f"[query] {name} nq={w.nq}")
+    bf = oracle.brute_force(w.points, w.d, w.queries, w.r)
+    assert sum(len(x) for x in bf.ids) > 0
+    got = csr_lists(*idx.query(dev(w.queries), w.r))
+    assert_same_lists(got, bf.ids)
+    s2 = orc.strategy2(w.queries, w.r)  # the paper's bitmap Strategy 2 agrees too
+    assert_same_lists(s2.ids, bf.ids)
+
+
+def test_collisions_counter(case):
+    name, w, idx, orc = case
+    s2 = orc.strategy2(w.queries, w.r)
+    got = idx.collisions(dev(w.queries)).cpu().numpy()
+    assert np.array_equal(got, s2.collisions)
+
+
+def test_smaller_radii(case):
+    name, w, idx, orc = case
+    for rq in sorted({0, 1, w.r // 2, w.r - 1}):
+        if rq < 0:
+            continue
+        bf = oracle.brute_force(w.points, w.d, w.queries, rq)
+        assert_same_lists(csr_lists(*idx.query(dev(w.queries), rq)), bf.ids)
+
+
+def test_plain_path_matches(case):
+    name, w, idx, orc = case
+    q = w.queries[:4]
+    bf = oracle.brute_force(w.points, w.d, q, w.r)
+    assert_same_lists(csr_lists(*idx.query_plain(dev(q), w.r)), bf.ids)
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+
+def _p2_params(d, rp, cols):
+    return dict(t=1, r_part=rp, part=np.zeros(d, np.int32), col=np.asarray(cols, np.int32),
+                b=np.array([1 << c for c in range(d)], np.uint64))
+
+
+def _str_point(s):
+    w = np.zeros(1, np.uint64)
+    for k, ch in enumerate(s):
+        if ch == "1":
+            w[0] |= np.uint64(1) << np.uint64(k)
+    return w
+
+
+def test_worked_example_2_1(golden):
+    g = {ln.split()[0]: ln.split()[1:] for ln in golden("example_2_1.txt")}
+    p = _p2_params(4, 2, [int(s, 2) for s in g["m"]])
+    pts = np.stack([_str_point(g["x"][0]), _str_point(g["q"][0])])
+    idx = fc.Index.with_params(dev(pts), 4, 2, p["t"], p["r_part"], p["part"], p["col"], p["b"])
+    k = as_u32(idx.hash(dev(pts)))
+    v = int(g["collide"][0])
+    assert list(np.nonzero(k[:, 0] == k[:, 1])[0]) == [v - 1]
+    assert int(k[v - 1, 0]) == sum(1 << i for i, ch in enumerate(g["collide"][1]) if ch == "1")
+    idx.close()
+
+
+def test_worked_example_3_1(golden):
+    g = {ln.split()[0]: ln.split()[1:] for ln in golden("example_3_1.txt")}
+    p = _p2_params(8, 2, list(range(8)))
+    pts = np.stack([_str_point(g[k][0]) for k in ("x", "y", "q")])
+    idx = fc.Index.with_params(dev(pts), 8, 2, p["t"], p["r_part"], p["part"], p["col"], p["b"])
+    k = as_u32(idx.hash(dev(pts)))
+    row = int(g["collide_x"][0])
+    assert list(np.nonzero(k[:, 0] == k[:, 2])[0]) == [row - 1]
+    assert not np.any(k[:, 1] == k[:, 2])
+    # x (distance 2) is reported for q at r = 2, y (distance 3) is not
+    offs, ids = idx.query(dev(pts[2:3]), 2)
+    assert sorted(csr_lists(offs, ids)[0].tolist()) == [0, 2]
+    idx.close()
+
+
+def test_single_point_and_empty_batch():
+    rng = np.random.default_rng(5)
+    x = synth.uniform_points(1, 128, rng)
+    idx = fc.Index(dev(x), 128, 4, seed=11)
+    offs, ids = idx.query(dev(x), 4)
+    assert csr_lists(offs, ids)[0].tolist() == [0]
+    empty = torch.zeros((0, 2), dtype=torch.int64, device="cuda")
+    offs, ids = idx.query(empty, 4)
+    assert offs.shape[0] == 1 and int(offs[0]) == 0 and ids.numel() == 0
+    idx.close()
+
+
+def test_duplicates_and_heavy_buckets():
+    # many identical points: one bucket holds them in every table
+    rng = np.random.default_rng(6)
+    base = synth.uniform_points(1, 256, rng)
+    pts = synth.uniform_points(3000, 256, rng)
+    pts[::3] = base  # 1000 copies
+    qs = np.vstack([base, synth.flip_distinct(base[0], 256, 3, rng)[None], pts[1:3]])
+    pr = oracle.derive_params(256, 8, 77)
+    orc = OracleIndex(pts, pr)
+    idx = fc.Index(dev(pts), 256, 8, seed=77)
+    tk, ti = idx.tables()
+    assert np.array_equal(as_u32(tk), orc.tk) and np.array_equal(as_u32(ti), orc.ti)
+    bf = oracle.brute_force(pts, 256, qs, 8)
+    assert len(bf.ids[0]) >= 1000
+    assert_same_lists(csr_lists(*idx.query(dev(qs), 8)), bf.ids)
+    assert np.array_equal(idx.collisions(dev(qs)).cpu().numpy(), orc.strategy2(qs, 8).collisions)
+    idx.close()
+
+
+def test_radius_and_capacity_errors():
+    w = synth.small(0.05)
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=3)
+    with pytest.raises(fc.FclshError) as e:
+        idx.query(dev(w.queries), w.r + 1)
+    assert e.value.status == fc.FCLSH_ERADIUS
+    bf = oracle.brute_force(w.points, w.d, w.queries, w.r)
+    total = sum(len(x) for x in bf.ids)
+    assert total > 2
+    with pytest.raises(fc.FclshError) as e:
+        idx.query(dev(w.queries), w.r, ids_capacity=total - 1)
+    assert e.value.status == fc.FCLSH_ECAPACITY
+    # exact capacity is enough
+    offs, ids = idx.query(dev(w.queries), w.r, ids_capacity=total)
+    assert_same_lists(csr_lists(offs, ids), bf.ids)
+    idx.close()
+
+
+def test_bad_build_arguments():
+    x = dev(synth.uniform_points(10, 64, np.random.default_rng(1)))
+    with pytest.raises(fc.FclshError) as e:
+        fc.Index(x, 64, 24, seed=1, partitions=1)  # 2^13 columns
+    assert e.value.status == fc.FCLSH_EUNSUPPORTED
+    with pytest.raises(fc.FclshError) as e:
+        fc.Index(x, 64, 4, seed=1, mem_budget_bytes=1024)
+    assert e.value.status == fc.FCLSH_ENOMEM
+
+
+def test_largest_hadamard_order():
+    # r' = 11: D = 4096 columns, 64 lanes per point
+    w = synth.uniform_with_planted(300, 128, 11, 3, 4, 1109, "big_D")
+    idx, pr = build(w, 3009, partitions=1)
+    assert pr.D == 4096
+    orc = OracleIndex(w.points, pr)
+    assert np.array_equal(as_u32(idx.hash(dev(w.points))), orc.keys)
+    bf = oracle.brute_force(w.points, w.d, w.queries, w.r)
+    assert_same_lists(csr_lists(*idx.query(dev(w.queries), w.r)), bf.ids)
+    idx.close()
+
+
+def test_rebuild_is_deterministic():
+    w = synth.small(0.1)
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=5)
+    tk0, ti0 = (as_u32(t) for t in idx.tables())
+    idx.rebuild()
+    tk1, ti1 = (as_u32(t) for t in idx.tables())
+    assert np.array_equal(tk0, tk1) and np.array_equal(ti0, ti1)
+    idx.close()
