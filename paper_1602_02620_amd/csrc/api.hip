@@ -51,16 +51,6 @@ __global__ void copy_points_kernel(const uint64_t *__restrict__ src, uint64_t *_
 
 uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 1) : ~uint64_t(0); }
 
-int pick_dir_bits(int64_t n) {
-    // about 4-8 entries per directory bin
-    int b = 0;
-    while ((int64_t(1) << (b + 1)) <= n) ++b;  // floor(log2 n)
-    b -= 2;
-    if (b < 1) b = 1;
-    if (b > 24) b = 24;
-    return b;
-}
-
 }  // namespace
 
 struct IndexHandle {
@@ -70,6 +60,7 @@ struct IndexHandle {
     uint32_t *keys = nullptr;  // build scratch, kept for rebuilds
     uint32_t *tk = nullptr;
     uint32_t *tv = nullptr;
+    uint32_t *aux = nullptr;
     QueryWorkspace *workspace(hipStream_t st) {
         std::lock_guard<std::mutex> g(mu);
         auto it = ws.find(st);
@@ -85,8 +76,8 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
     size_t b = size_t(n) * W * 8;                        // point copy
     b += 2 * L * size_t(n) * 4;                          // table keys + ids
     b += L * ((size_t(1) << dir_bits) + 1) * 4;          // directories
-    b += 3 * L * size_t(n) * 4;                          // build scratch: keys + 2 sort buffers
-    b += L * 256 * ((size_t(n) + 4095) / 4096) * 4;      // radix histograms
+    b += 3 * L * size_t(n) * 4;                          // build scratch: keys + 2 partition buffers
+    b += table_build_scratch_bytes(int64_t(L), n);       // histograms
     return b;
 }
 
@@ -97,11 +88,12 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st) {
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->keys), size_t(L * ix.n) * 4, "build keys"));
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->tk), size_t(L * ix.n) * 4, "sort buffer"));
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->tv), size_t(L * ix.n) * 4, "sort buffer"));
+        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n),
+                            "table histograms"));
     }
     FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
-    Scratch scr;
-    FCLSH_TRY(radix_sort_pairs(h->keys, nullptr, ix.tkeys, ix.tids, h->tk, h->tv, L, ix.n, 0, 31, scr, st));
-    FCLSH_TRY(build_directory(ix.tkeys, L, ix.n, ix.dir_bits, ix.dir, st));
+    FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
+                                 st));
     FCLSH_HIP(hipStreamSynchronize(st));
     return FCLSH_OK;
 }
@@ -119,7 +111,7 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
     ix.prm = std::move(prm);
     ix.W = words_of(ix.prm.d);
     ix.n = n;
-    ix.dir_bits = pick_dir_bits(n);
+    ix.dir_bits = table_dir_bits(n);
     ix.budget = budget;
     (void)hipGetDevice(&ix.device);
     auto bail = [&](fclsh_status s) {

@@ -131,14 +131,17 @@ fclsh_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in,
 fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *total,
                                 Scratch &scr, hipStream_t st);
 
-fclsh_status build_directory(const uint32_t *tkeys, int64_t nseg, int64_t n, int dir_bits,
-                             uint32_t *dir, hipStream_t st);
-
-fclsh_status build_tables(Index *ix, const uint32_t *keys, Scratch &scr, hipStream_t st);
+// Table build (tables.hip): keys [L][n] -> tables grouped by the top dir_bits
+// key bits, ids ascending per bin, plus the directory [L][2^dir_bits + 1].
+int table_dir_bits(int64_t n);
+size_t table_build_scratch_bytes(int64_t L, int64_t n);
+fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
+                                uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
+                                uint32_t *dir, hipStream_t st);
 
 // Scratch of the query path for one index and stream, grown on demand.
 struct QueryWorkspace {
-    uint32_t *qkeys = nullptr, *rstart = nullptr, *rcount = nullptr, *qcount = nullptr;
+    uint32_t *qkeys = nullptr, *rstart = nullptr, *rcount = nullptr, *rmatch = nullptr, *qcount = nullptr;
     uint64_t *qcount64 = nullptr, *offs1 = nullptr;
     unsigned long long *cursor = nullptr;
     uint32_t *pq = nullptr, *pid = nullptr, *sk = nullptr, *sv = nullptr, *tk = nullptr, *tv = nullptr;

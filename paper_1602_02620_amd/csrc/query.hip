@@ -70,10 +70,13 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
     return -1;
 }
 
-// S2: per (query, table) the bucket range [start, start+count) in table T.
+// S2: per (query, table) the query's directory bin [start, start+len) in
+// table T and the number of entries in it whose key equals the query's key
+// (the bucket size, i.e. this table's share of #Collisions).
 __global__ void lookup_kernel(const uint32_t *__restrict__ qkeys, int64_t nq, int L,
                               const uint32_t *__restrict__ tkeys, const uint32_t *__restrict__ dir, int64_t n,
-                              int dir_bits, uint32_t *__restrict__ rstart, uint32_t *__restrict__ rcount) {
+                              int dir_bits, uint32_t *__restrict__ rstart, uint32_t *__restrict__ rlen,
+                              uint32_t *__restrict__ rmatch) {
     const int64_t total = nq * L;
     const int64_t nb = int64_t(1) << dir_bits;
     for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
@@ -84,41 +87,33 @@ __global__ void lookup_kernel(const uint32_t *__restrict__ qkeys, int64_t nq, in
         const uint32_t *tk = tkeys + int64_t(T) * n;
         const uint32_t *dr = dir + int64_t(T) * (nb + 1);
         const uint32_t bin = key >> (31 - dir_bits);
-        uint32_t lo = dr[bin], hi = dr[bin + 1];
-        // lower bound of key in [lo, hi)
-        uint32_t a = lo, b = hi;
-        while (a < b) {
-            const uint32_t mid = a + (b - a) / 2;
-            if (tk[mid] < key) a = mid + 1; else b = mid;
-        }
-        const uint32_t first = a;
-        b = hi;
-        while (a < b) {
-            const uint32_t mid = a + (b - a) / 2;
-            if (tk[mid] <= key) a = mid + 1; else b = mid;
-        }
-        rstart[qi * L + T] = first;
-        rcount[qi * L + T] = a - first;
+        const uint32_t lo = dr[bin], hi = dr[bin + 1];
+        uint32_t m = 0;
+        for (uint32_t j = lo; j < hi; ++j) m += tk[j] == key;
+        rstart[qi * L + T] = lo;
+        rlen[qi * L + T] = hi - lo;
+        rmatch[qi * L + T] = m;
     }
 }
 
-__global__ void collisions_kernel(const uint32_t *__restrict__ rcount, int64_t nq, int L,
+__global__ void collisions_kernel(const uint32_t *__restrict__ rmatch, int64_t nq, int L,
                                   uint64_t *__restrict__ coll) {
     const int64_t qi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (qi >= nq) return;
     uint64_t s = 0;
-    for (int T = 0; T < L; ++T) s += rcount[qi * L + T];
+    for (int T = 0; T < L; ++T) s += rmatch[qi * L + T];
     coll[qi] = s;
 }
 
 // S3 + emission.  One wave per (query, table) item; lanes stride over the
-// bucket.  Each reported (query, id) pair takes a slot from a global cursor
+// query's directory bin and keep the entries of its bucket (equal key).  Each reported (query, id) pair takes a slot from a global cursor
 // (one atomic per wave); slots past `cap` are dropped and recounted by the
 // host with a larger buffer.
 __global__ __launch_bounds__(256) void verify_kernel(
     const uint64_t *__restrict__ pts, int W, int d, const uint64_t *__restrict__ queries, int64_t nq,
-    int L, const uint32_t *__restrict__ tids, int64_t n, const uint32_t *__restrict__ rstart,
-    const uint32_t *__restrict__ rcount, int rq, const int32_t *__restrict__ part,
+    int L, const uint32_t *__restrict__ tkeys, const uint32_t *__restrict__ tids, int64_t n,
+    const uint32_t *__restrict__ qkeys, const uint32_t *__restrict__ rstart, const uint32_t *__restrict__ rmatch,
+    const uint32_t *__restrict__ rlen, int rq, const int32_t *__restrict__ part,
     const int32_t *__restrict__ col, int t, int mbits, int Lp, uint64_t last_mask,
     unsigned long long *__restrict__ cursor, uint32_t *__restrict__ out_q, uint32_t *__restrict__ out_id,
     int64_t cap, uint32_t *__restrict__ qcount) {
@@ -128,18 +123,20 @@ __global__ __launch_bounds__(256) void verify_kernel(
     const int64_t items = nq * L;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (int64_t it = __builtin_amdgcn_readfirstlane(wave0); it < items; it += nwaves) {
-        const uint32_t cnt = rcount[it];
-        if (cnt == 0) continue;
+        if (rmatch[it] == 0) continue;
+        const uint32_t cnt = rlen[it];
         const int64_t qi = it / L;
         const int T = int(it - qi * L);
         const uint32_t st = rstart[it];
+        const uint32_t qkey = qkeys[int64_t(T) * nq + qi];
         const uint64_t *qp = queries + qi * W;
         const uint32_t *ids = tids + int64_t(T) * n + st;
+        const uint32_t *bk = tkeys + int64_t(T) * n + st;
         for (uint32_t j0 = 0; j0 < cnt; j0 += 64) {
             const uint32_t j = j0 + lane;
             bool emit = false;
             uint32_t id = 0;
-            if (j < cnt) {
+            if (j < cnt && bk[j] == qkey) {
                 id = ids[j];
                 const uint64_t *xp = pts + int64_t(id) * W;
                 int dist = 0;
@@ -209,6 +206,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs) {
         FCLSH_TRY(regrow(&ws.qkeys, 0, items, "query keys"));
         FCLSH_TRY(regrow(&ws.rstart, 0, items, "query ranges"));
         FCLSH_TRY(regrow(&ws.rcount, 0, items, "query ranges"));
+        FCLSH_TRY(regrow(&ws.rmatch, 0, items, "query ranges"));
         ws.cap_items = items;
     }
     if (nq + 1 > ws.cap_q) {
@@ -231,7 +229,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs) {
 }
 
 void ws_release(QueryWorkspace &ws) {
-    void *ps[] = {ws.qkeys, ws.rstart, ws.rcount, ws.qcount, ws.qcount64, ws.offs1, ws.cursor,
+    void *ps[] = {ws.qkeys, ws.rstart, ws.rcount, ws.rmatch, ws.qcount, ws.qcount64, ws.offs1, ws.cursor,
                   ws.pq, ws.pid, ws.sk, ws.sv, ws.tk, ws.tv};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -247,7 +245,7 @@ fclsh_status query_lookup(Index &ix, QueryWorkspace &ws, const uint64_t *queries
     const int L = ix.prm.L();
     FCLSH_TRY(launch_hash(ix, queries, nq, ws.qkeys, nq, st));
     hipLaunchKernelGGL(lookup_kernel, dim3(grid_for(nq * L, 256)), dim3(256), 0, st, ws.qkeys, nq, L,
-                       ix.tkeys, ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rcount);
+                       ix.tkeys, ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rcount, ws.rmatch);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
@@ -256,7 +254,7 @@ fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *que
                               uint64_t *coll, hipStream_t st) {
     FCLSH_TRY(ws_reserve(ws, nq, ix.prm.L(), 0));
     FCLSH_TRY(query_lookup(ix, ws, queries, nq, st));
-    hipLaunchKernelGGL(collisions_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.rcount, nq,
+    hipLaunchKernelGGL(collisions_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.rmatch, nq,
                        ix.prm.L(), coll);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
@@ -283,7 +281,8 @@ fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
         FCLSH_HIP(hipMemsetAsync(ws.qcount, 0, size_t(nq) * 4, st));
         const int64_t items = nq * L;
         hipLaunchKernelGGL(verify_kernel, dim3(grid_for(items, 4, 65536)), dim3(256), 0, st, ix.pts, ix.W,
-                           ix.prm.d, queries, nq, L, ix.tids, ix.n, ws.rstart, ws.rcount, rq, ix.dpart, ix.dcol,
+                           ix.prm.d, queries, nq, L, ix.tkeys, ix.tids, ix.n, ws.qkeys, ws.rstart, ws.rmatch,
+                           ws.rcount, rq, ix.dpart, ix.dcol,
                            ix.prm.t, ix.prm.rp + 1, ix.prm.Lp(), lm, ws.cursor, ws.pq, ws.pid, ws.cap_pairs,
                            ws.qcount);
         FCLSH_HIP(hipGetLastError());

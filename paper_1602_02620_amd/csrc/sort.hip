@@ -1,16 +1,15 @@
-// Bucketing the L tables (hash tables of non-empty buckets, Sec. 2.2): each
-// table becomes its n (key, id) pairs sorted by key then id, plus a directory
-// over the top key bits.
-//
-// The sort is a stable least-significant-digit radix sort over 8-bit digits,
-// batched over equal-length segments (one per table).  Each pass is
+// Generic device-wide primitives: a stable least-significant-digit radix sort
+// of (uint32 key, uint32 value) pairs over 8-bit digits, batched over
+// equal-length segments, and an exclusive scan of uint64 values.  They put the
+// query results in canonical order (by query, ids ascending) and build CSR
+// offsets.  Each radix pass is
 //   histogram  per (segment, tile) digit counts, in LDS
 //   scan       per segment, exclusive scan in digit-major, tile-minor order
 //   scatter    per tile: stable ranks from wave ballots (each lane learns the
 //              lanes holding its digit from 8 ballots), per-wave running
 //              counts in LDS, a block-local reorder in LDS so that each
 //              digit's run is written out contiguously.
-// The first pass of a table takes ids implicitly (element index).
+// Without input values, the first pass takes each element's index as value.
 #include "common.h"
 
 namespace fclsh {
@@ -230,25 +229,6 @@ __global__ void scan_total_kernel(const uint64_t *in, const uint64_t *excl, int6
     *total = n ? excl[n - 1] + in[n - 1] : 0;
 }
 
-// ---------------------------------------------------------------------------
-// Directory: dir[T][b] = first position of table T whose key has top bits >= b.
-// ---------------------------------------------------------------------------
-__global__ void directory_kernel(const uint32_t *__restrict__ tkeys, int64_t n, int dir_bits,
-                                 uint32_t *__restrict__ dir) {
-    const int T = blockIdx.y;
-    const uint32_t *k = tkeys + int64_t(T) * n;
-    const int64_t nb = int64_t(1) << dir_bits;
-    uint32_t *dr = dir + int64_t(T) * (nb + 1);
-    const int sh = 31 - dir_bits;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i <= n;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        // bins (prev, cur] start at i
-        const int64_t prev = i == 0 ? -1 : int64_t(k[i - 1] >> sh);
-        const int64_t cur = i == n ? nb : int64_t(k[i] >> sh);
-        for (int64_t b = prev + 1; b <= cur; ++b) dr[b] = uint32_t(i);
-    }
-}
-
 }  // namespace
 
 fclsh_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
@@ -324,26 +304,6 @@ fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, ui
                            total);
         FCLSH_HIP(hipGetLastError());
     }
-    return FCLSH_OK;
-}
-
-fclsh_status build_directory(const uint32_t *tkeys, int64_t nseg, int64_t n, int dir_bits, uint32_t *dir,
-                             hipStream_t st) {
-    const int64_t work = n + 1;
-    unsigned gx = unsigned(std::min<int64_t>((work + 255) / 256, 4096));
-    hipLaunchKernelGGL(directory_kernel, dim3(gx, unsigned(nseg)), dim3(256), 0, st, tkeys, n, dir_bits, dir);
-    FCLSH_HIP(hipGetLastError());
-    return FCLSH_OK;
-}
-
-fclsh_status build_tables(Index *ix, const uint32_t *keys, Scratch &scr, hipStream_t st) {
-    const int64_t L = ix->prm.L();
-    const int64_t n = ix->n;
-    uint32_t *tk, *tv;
-    FCLSH_TRY(scr.get(&tk, size_t(L * n), "sort scratch"));
-    FCLSH_TRY(scr.get(&tv, size_t(L * n), "sort scratch"));
-    FCLSH_TRY(radix_sort_pairs(keys, nullptr, ix->tkeys, ix->tids, tk, tv, L, n, 0, 31, scr, st));
-    FCLSH_TRY(build_directory(ix->tkeys, L, n, ix->dir_bits, ix->dir, st));
     return FCLSH_OK;
 }
 

@@ -1,0 +1,388 @@
+// The L hash tables (hash tables of non-empty buckets, Sec. 2.2).
+//
+// A table is its n (key, id) pairs grouped by directory bin -- the top B bits
+// of the 31-bit key -- with ids ascending inside a bin, plus the directory
+// dir[b] = first position of bin b (dir[2^B] = n).  A lookup of key k scans
+// bin k >> (31 - B) and keeps the entries whose key equals k: that is the
+// bucket of k.  B is about log2(n) - 2, so a bin holds a handful of entries
+// besides the bucket itself.
+//
+// Built in two stable passes per table:
+//   pass 1  global partition by the top 8 key bits into 256 "super-bins":
+//           per-tile digit histograms, a per-table scan, and a scatter that
+//           ranks each tile's keys stably with wave ballots and writes every
+//           digit's run contiguously through an LDS reorder buffer;
+//   pass 2  one workgroup per (table, super-bin): a stable reorder by the
+//           next B - 8 key bits in LDS, written back contiguously, which also
+//           yields the directory entries of the super-bin's bins.
+// Scattered 4-byte stores are far slower than coalesced ones on this GPU, so
+// both passes stage their output in LDS first.
+// Ids are implicit in pass 1 (a point's index), so the keys written by the
+// hash kernel are read twice and each table entry is written twice.
+#include "common.h"
+
+namespace fclsh {
+
+namespace {
+
+constexpr int kNT = 512;                 // threads of the ranking kernels
+constexpr int kWaves = kNT / 64;
+constexpr int kItems = 16;               // entries per thread
+constexpr int kTile = kNT * kItems;      // 8192 entries per tile / chunk
+constexpr int kHistNT = 256;
+constexpr int kHiBits = 8;
+constexpr int kHiBins = 1 << kHiBits;
+constexpr int kMaxLoBits = 11;
+
+// A wave's LDS operations execute in issue order; this keeps the compiler from
+// moving plain LDS accesses across the atomics between phases.
+__device__ inline void wave_lds_order() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Lanes of the wave holding the same `bits`-bit digit as this lane (among the
+// lanes with ok set), from one ballot per digit bit.
+__device__ inline uint64_t same_digit_lanes(uint32_t dg, int bits, bool ok) {
+    uint64_t same = __ballot(ok);
+    for (int b = 0; b < bits; ++b) {
+        const bool on = (dg >> b) & 1u;
+        const uint64_t bb = __ballot(on);
+        same &= on ? bb : ~bb;
+    }
+    return same;
+}
+
+// Stable ranks of a wave's ITEMS rounds of 64 digits (round-major, then lane
+// order): rank = number of earlier entries of this wave with the same digit.
+// The lowest lane of each digit group adds the group size to the wave's
+// counter with an LDS atomic that returns the previous value; the atomics of
+// one wave execute in program order, so no round waits for the previous one.
+// wcw must hold zeros for all digits on entry and ends as the wave histogram.
+template <int ITEMS>
+__device__ inline void wave_stable_ranks(const uint32_t (&dg)[ITEMS], const bool (&ok)[ITEMS], int bits,
+                                         uint32_t *wcw, uint32_t (&rank)[ITEMS]) {
+    constexpr int GRP = ITEMS < 8 ? ITEMS : 8;  // rounds whose atomics are in flight together
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int g0 = 0; g0 < ITEMS; g0 += GRP) {
+        uint32_t before[GRP], lead[GRP], old[GRP];
+#pragma unroll
+        for (int k = 0; k < GRP; ++k) {
+            const int it = g0 + k;
+            const uint64_t same = same_digit_lanes(dg[it], bits, ok[it]);
+            before[k] = uint32_t(__popcll(same & lt));
+            lead[k] = same ? uint32_t(__builtin_ctzll(same)) : 0u;
+            old[k] = (ok[it] && before[k] == 0) ? atomicAdd(&wcw[dg[it]], uint32_t(__popcll(same))) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < GRP; ++k) rank[g0 + k] = __shfl(old[k], int(lead[k]), 64) + before[k];
+    }
+}
+
+// Block-wide exclusive scan; *total gets the sum.
+__device__ inline uint32_t block_scan_u32(uint32_t v, uint32_t *sh, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nw; ++w) {
+            const uint32_t c = sh[w];
+            sh[w] = run;
+            run += c;
+        }
+        sh[nw] = run;
+    }
+    __syncthreads();
+    const uint32_t res = x - v + sh[wave];
+    if (total) *total = sh[nw];
+    __syncthreads();
+    return res;
+}
+
+// Turns the per-wave digit histograms wc[w][d] into per-wave exclusive
+// offsets and returns the per-digit totals in tot[d].
+__device__ inline void wave_offsets(uint32_t *wc, int R, uint32_t *tot) {
+    for (int d = threadIdx.x; d < R; d += kNT) {
+        uint32_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = wc[w * R + d];
+            wc[w * R + d] = run;
+            run += c;
+        }
+        tot[d] = run;
+    }
+}
+
+// In place: cnt[d] := base + exclusive prefix of cnt over d < R.
+__device__ inline void digit_starts(uint32_t *cnt, int R, uint32_t base, uint32_t *sh) {
+    const int per = (R + kNT - 1) / kNT;
+    const int d0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int k = 0; k < per; ++k)
+        if (d0 + k < R) s += cnt[d0 + k];
+    uint32_t run = block_scan_u32(s, sh, nullptr) + base;
+    for (int k = 0; k < per; ++k)
+        if (d0 + k < R) {
+            const uint32_t c = cnt[d0 + k];
+            cnt[d0 + k] = run;
+            run += c;
+        }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kHistNT) void p1_hist_kernel(const uint32_t *__restrict__ keys, int64_t n,
+                                                          uint32_t *__restrict__ hist, int nblk) {
+    constexpr int HW = kHistNT / 64;
+    __shared__ uint32_t h[HW][kHiBins];
+    const int T = blockIdx.y, blk = blockIdx.x, wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < HW * kHiBins; i += kHistNT) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t *kp = keys + int64_t(T) * n;
+    const int64_t beg = int64_t(blk) * kTile;
+    const int64_t end = min(n, beg + kTile);
+    for (int64_t e = beg + threadIdx.x; e < end; e += kHistNT)
+        atomicAdd(&h[wave][kp[e] >> (31 - kHiBits)], 1u);
+    __syncthreads();
+    uint32_t c = 0;
+    for (int w = 0; w < HW; ++w) c += h[w][threadIdx.x];
+    hist[(int64_t(T) * nblk + blk) * kHiBins + threadIdx.x] = c;  // tile-major
+}
+
+// Per table: hist[T][blk][d] := start (within the table) of tile blk's run of
+// digit d; bstart[T][d] = start of super-bin d, bstart[T][256] = n.
+__global__ __launch_bounds__(kHiBins) void p1_scan_kernel(uint32_t *__restrict__ hist, int nblk, int64_t n,
+                                                          uint32_t *__restrict__ bstart) {
+    __shared__ uint32_t sh[kHiBins / 64 + 1];
+    const int T = blockIdx.x, d = threadIdx.x;
+    uint32_t *h = hist + int64_t(T) * nblk * kHiBins;
+    uint32_t run = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const uint32_t c = h[int64_t(b) * kHiBins + d];
+        h[int64_t(b) * kHiBins + d] = run;
+        run += c;
+    }
+    const uint32_t base = block_scan_u32(run, sh, nullptr);
+    for (int b = 0; b < nblk; ++b) h[int64_t(b) * kHiBins + d] += base;
+    bstart[int64_t(T) * (kHiBins + 1) + d] = base;
+    if (d == 0) bstart[int64_t(T) * (kHiBins + 1) + kHiBins] = uint32_t(n);
+}
+
+__global__ __launch_bounds__(kNT) void p1_scatter_kernel(const uint32_t *__restrict__ keys, int64_t n,
+                                                         const uint32_t *__restrict__ offs, int nblk,
+                                                         uint32_t *__restrict__ okeys,
+                                                         uint32_t *__restrict__ oids) {
+    __shared__ uint32_t wc[kWaves * kHiBins];
+    __shared__ uint32_t tot[kHiBins];
+    __shared__ uint32_t gpos[kHiBins];
+    __shared__ uint32_t sk[kTile];
+    __shared__ uint16_t si[kTile];
+    __shared__ uint32_t sh[kWaves + 1];
+
+    const int T = blockIdx.y, blk = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t toff = int64_t(T) * n;
+    const int64_t beg = int64_t(blk) * kTile;
+    const int cnt = int(min<int64_t>(kTile, n - beg));
+    for (int i = threadIdx.x; i < kWaves * kHiBins; i += kNT) wc[i] = 0;
+    for (int d = threadIdx.x; d < kHiBins; d += kNT) gpos[d] = offs[(int64_t(T) * nblk + blk) * kHiBins + d];
+    __syncthreads();
+
+    uint32_t rk[kItems], dg[kItems], rank[kItems];
+    bool ok[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int e = wave * (64 * kItems) + it * 64 + lane;
+        ok[it] = e < cnt;
+        rk[it] = ok[it] ? keys[toff + beg + e] : 0u;
+        dg[it] = rk[it] >> (31 - kHiBits);
+    }
+    wave_stable_ranks<kItems>(dg, ok, kHiBits, wc + wave * kHiBins, rank);
+    __syncthreads();
+    wave_offsets(wc, kHiBins, tot);
+    __syncthreads();
+    digit_starts(tot, kHiBins, 0u, sh);  // tot := block-local start of each digit
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (ok[it]) {
+            const uint32_t lp = tot[dg[it]] + wc[wave * kHiBins + dg[it]] + rank[it];
+            sk[lp] = rk[it];
+            si[lp] = uint16_t(wave * (64 * kItems) + it * 64 + lane);
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kNT) {
+        const uint32_t key = sk[j];
+        const uint32_t d = key >> (31 - kHiBits);
+        const int64_t dst = toff + int64_t(gpos[d]) + (j - int64_t(tot[d]));
+        okeys[dst] = key;
+        oids[dst] = uint32_t(beg + si[j]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: one workgroup per (table, super-bin).  A super-bin of at most
+// kTile entries (the usual case) is read once, ranked, reordered in LDS and
+// written out contiguously.  A larger one gets a histogram read first and is
+// then scattered chunk by chunk with running digit starts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT) void p2_bucket_kernel(const uint32_t *__restrict__ ikeys,
+                                                        const uint32_t *__restrict__ iids, int64_t n,
+                                                        const uint32_t *__restrict__ bstart, int lo_bits,
+                                                        uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
+                                                        uint32_t *__restrict__ dir) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t sh[kWaves + 1];
+    const int R = 1 << lo_bits;
+    // region A (kTile*2 words): first the per-wave counters [kWaves][R], then
+    // the reordered keys and ids; region B: start[R], tot[R]
+    uint32_t *wc = lds;
+    uint32_t *rkey = lds;
+    uint32_t *rid = lds + kTile;
+    uint32_t *start = lds + 2 * kTile;
+    uint32_t *tot = start + R;
+
+    const int T = blockIdx.y, sb = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int shift = 31 - kHiBits - lo_bits;
+    const uint32_t mask = uint32_t(R - 1);
+    const int64_t toff = int64_t(T) * n;
+    const uint32_t bs = bstart[int64_t(T) * (kHiBins + 1) + sb];
+    const uint32_t be = bstart[int64_t(T) * (kHiBins + 1) + sb + 1];
+    const uint32_t *kin = ikeys + toff;
+    const uint32_t *vin = iids + toff;
+    uint32_t *dr = dir + int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1);
+    const bool single = (be - bs) <= uint32_t(kTile);
+    if (sb == kHiBins - 1 && threadIdx.x == 0) dr[int64_t(kHiBins) << lo_bits] = uint32_t(n);
+
+    if (single) {
+        for (int i = threadIdx.x; i < kWaves * R; i += kNT) wc[i] = 0;
+        __syncthreads();
+        uint32_t rk[kItems], rv[kItems], dg[kItems], rank[kItems];
+        bool ok[kItems];
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t e = bs + uint32_t(wave * (64 * kItems) + it * 64 + lane);
+            ok[it] = e < be;
+            rk[it] = ok[it] ? kin[e] : 0u;
+            rv[it] = ok[it] ? vin[e] : 0u;
+            dg[it] = (rk[it] >> shift) & mask;
+        }
+        wave_stable_ranks<kItems>(dg, ok, lo_bits, wc + wave * R, rank);
+        __syncthreads();
+        wave_offsets(wc, R, tot);
+        __syncthreads();
+        for (int i = threadIdx.x; i < R; i += kNT) start[i] = tot[i];
+        __syncthreads();
+        digit_starts(start, R, 0u, sh);
+        for (int i = threadIdx.x; i < R; i += kNT) dr[(int64_t(sb) << lo_bits) + i] = bs + start[i];
+#pragma unroll
+        for (int it = 0; it < kItems; ++it)
+            if (ok[it]) rank[it] += start[dg[it]] + wc[wave * R + dg[it]];
+        __syncthreads();  // the counters' space becomes the reorder buffer
+#pragma unroll
+        for (int it = 0; it < kItems; ++it)
+            if (ok[it]) {
+                rkey[rank[it]] = rk[it];
+                rid[rank[it]] = rv[it];
+            }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < be - bs; j += kNT) {
+            tkeys[toff + bs + j] = rkey[j];
+            tids[toff + bs + j] = rid[j];
+        }
+        return;
+    }
+
+    for (int i = threadIdx.x; i < R; i += kNT) start[i] = 0;
+    __syncthreads();
+    for (uint32_t e = bs + threadIdx.x; e < be; e += kNT) atomicAdd(&start[(kin[e] >> shift) & mask], 1u);
+    __syncthreads();
+    digit_starts(start, R, bs, sh);
+    for (int i = threadIdx.x; i < R; i += kNT) dr[(int64_t(sb) << lo_bits) + i] = start[i];
+    for (uint32_t c0 = bs; c0 < be; c0 += kTile) {
+        for (int i = threadIdx.x; i < kWaves * R; i += kNT) wc[i] = 0;
+        __syncthreads();
+        uint32_t dg[kItems], rank[kItems];
+        bool ok[kItems];
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
+            ok[it] = e < be;
+            dg[it] = ok[it] ? (kin[e] >> shift) & mask : 0u;
+        }
+        wave_stable_ranks<kItems>(dg, ok, lo_bits, wc + wave * R, rank);
+        __syncthreads();
+        wave_offsets(wc, R, tot);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kItems; ++it)
+            if (ok[it]) {
+                const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
+                const int64_t dst = toff + int64_t(start[dg[it]]) + wc[wave * R + dg[it]] + rank[it];
+                tkeys[dst] = kin[e];
+                tids[dst] = vin[e];
+            }
+        __syncthreads();
+        for (int d = threadIdx.x; d < R; d += kNT) start[d] += tot[d];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int table_dir_bits(int64_t n) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n) ++b;  // floor(log2 n)
+    b -= 2;
+    if (b < kHiBits) b = kHiBits;
+    if (b > kHiBits + kMaxLoBits) b = kHiBits + kMaxLoBits;
+    return b;
+}
+
+size_t table_build_scratch_bytes(int64_t L, int64_t n) {
+    const int64_t nblk = (n + kTile - 1) / kTile;
+    return size_t(L) * nblk * kHiBins * 4 + size_t(L) * (kHiBins + 1) * 4;
+}
+
+fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
+                                uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
+                                uint32_t *dir, hipStream_t st) {
+    if (L == 0 || n == 0) return FCLSH_OK;
+    if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
+    if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
+    const int nblk = int((n + kTile - 1) / kTile);
+    uint32_t *hist = scratch;
+    uint32_t *bstart = scratch + size_t(L) * nblk * kHiBins;
+    hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
+    FCLSH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins), 0, st, hist, nblk, n, bstart);
+    FCLSH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(p1_scatter_kernel, dim3(nblk, unsigned(L)), dim3(kNT), 0, st, keys, n, hist, nblk, tmpk,
+                       tmpv);
+    FCLSH_HIP(hipGetLastError());
+    const int lo_bits = dir_bits - kHiBits;
+    const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
+    hipLaunchKernelGGL(p2_bucket_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
+                       lo_bits, tkeys, tids, dir);
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
+}
+
+}  // namespace fclsh

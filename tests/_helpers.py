@@ -26,6 +26,20 @@ class OracleIndex:
         if with_tables:
             self.tk, self.ti = oracle.tables(self.keys)
 
+    def binned_tables(self, dir_bits: int):
+        """The table layout of the index: per table the oracle's (key, id)
+        pairs ordered by directory bin (top dir_bits of the 31-bit key), ids
+        ascending inside a bin."""
+        L, n = self.keys.shape
+        ids = np.arange(n, dtype=np.uint32)
+        tk = np.empty_like(self.keys)
+        ti = np.empty((L, n), np.uint32)
+        for T in range(L):
+            order = np.lexsort((ids, self.keys[T] >> np.uint32(31 - dir_bits)))
+            tk[T] = self.keys[T][order]
+            ti[T] = ids[order]
+        return tk, ti
+
     def query_keys(self, queries):
         return oracle.keys(queries, self.pr, mask=self.mask)
 

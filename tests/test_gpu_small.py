@@ -82,18 +82,19 @@ def test_tables_bit_exact(case):
     name, w, idx, orc = case
     _say(f"[tables] {name}")
     tk, ti = idx.tables()
-    assert np.array_equal(as_u32(tk), orc.tk)
-    assert np.array_equal(as_u32(ti), orc.ti)
+    wk, wi = orc.binned_tables(idx.info["dir_bits"])
+    assert np.array_equal(as_u32(tk), wk)
+    assert np.array_equal(as_u32(ti), wi)
 
 
 def test_directory(case):
     name, w, idx, orc = case
     db = idx.info["dir_bits"]
     dr = as_u32(idx.directory())
-    bins = orc.tk >> np.uint32(31 - db)
-    for T in range(0, orc.pr.L, max(1, orc.pr.L // 17)):
+    bins = np.sort(orc.keys >> np.uint32(31 - db), axis=1)
+    for T in range(orc.pr.L):
         want = np.searchsorted(bins[T], np.arange((1 << db) + 1), side="left")
-        assert np.array_equal(dr[T], want.astype(np.uint32))
+        assert np.array_equal(dr[T], want.astype(np.uint32)), f"table {T}"
 
 
 def test_queries_exact(case):
@@ -187,6 +188,26 @@ def test_single_point_and_empty_batch():
     idx.close()
 
 
+def test_empty_super_bins():
+    # few distinct points: most directory bins and whole top-8-bit super-bins
+    # are empty in every table
+    rng = np.random.default_rng(9)
+    distinct = synth.uniform_points(3, 128, rng)
+    pts = distinct[rng.integers(0, 3, size=5000)]
+    pr = oracle.derive_params(128, 4, 79)
+    orc = OracleIndex(pts, pr, with_tables=False)
+    idx = fc.Index(dev(pts), 128, 4, seed=79)
+    db = idx.info["dir_bits"]
+    dr = as_u32(idx.directory())
+    bins = np.sort(orc.keys >> np.uint32(31 - db), axis=1)
+    for T in range(orc.pr.L):
+        want = np.searchsorted(bins[T], np.arange((1 << db) + 1), side="left")
+        assert np.array_equal(dr[T], want.astype(np.uint32)), f"table {T}"
+    bf = oracle.brute_force(pts, 128, distinct, 4)
+    assert_same_lists(csr_lists(*idx.query(dev(distinct), 4)), bf.ids)
+    idx.close()
+
+
 def test_duplicates_and_heavy_buckets():
     # many identical points: one bucket holds them in every table
     rng = np.random.default_rng(6)
@@ -198,11 +219,29 @@ def test_duplicates_and_heavy_buckets():
     orc = OracleIndex(pts, pr)
     idx = fc.Index(dev(pts), 256, 8, seed=77)
     tk, ti = idx.tables()
-    assert np.array_equal(as_u32(tk), orc.tk) and np.array_equal(as_u32(ti), orc.ti)
+    wk, wi = orc.binned_tables(idx.info["dir_bits"])
+    assert np.array_equal(as_u32(tk), wk) and np.array_equal(as_u32(ti), wi)
     bf = oracle.brute_force(pts, 256, qs, 8)
     assert len(bf.ids[0]) >= 1000
     assert_same_lists(csr_lists(*idx.query(dev(qs), 8)), bf.ids)
     assert np.array_equal(idx.collisions(dev(qs)).cpu().numpy(), orc.strategy2(qs, 8).collisions)
+    idx.close()
+
+
+def test_all_points_identical():
+    # every table is one bucket of n entries: the pass-2 workgroup walks it in
+    # many chunks
+    rng = np.random.default_rng(8)
+    n = 20011
+    pts = np.repeat(synth.uniform_points(1, 64, rng), n, axis=0)
+    pr = oracle.derive_params(64, 3, 78)
+    orc = OracleIndex(pts, pr, with_tables=False)
+    idx = fc.Index(dev(pts), 64, 3, seed=78)
+    tk, ti = idx.tables()
+    wk, wi = orc.binned_tables(idx.info["dir_bits"])
+    assert np.array_equal(as_u32(tk), wk) and np.array_equal(as_u32(ti), wi)
+    offs, ids = idx.query(dev(pts[:1]), 3)
+    assert np.array_equal(csr_lists(offs, ids)[0], np.arange(n, dtype=np.uint32))
     idx.close()
 
 
