@@ -69,10 +69,11 @@ struct DevBuf {
 
 // Per-part gather plan of the hash kernel (see hash.hip).
 struct HashPlan {
-    int logD = 1, G = 1, V = 2, U = 64, t = 1, E = 0, W = 1;
-    int32_t *seg = nullptr;    // [t][V+1] entry ranges per in-lane column k
-    int32_t *coord = nullptr;  // [t][E][G] coordinate of each entry (or the zero slot)
-    double *bval = nullptr;    // [t][E][G] even representative of b mod P, as double
+    int logD = 1, logV = 1, G = 1, V = 2, U = 64, t = 1, E = 0, W = 1;
+    bool specific = true;        // at most one coordinate per Hadamard column
+    int blocks_per_part_cap = 2048;
+    int32_t *seg = nullptr;      // [t][V+1] entry ranges per in-lane column k
+    uint2 *gtab = nullptr;       // [t][E][G] (even representative of b mod P, coordinate)
 };
 
 struct Index {

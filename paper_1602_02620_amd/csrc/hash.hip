@@ -35,134 +35,250 @@ namespace {
 
 constexpr double kTwo52 = 4503599627370496.0;
 
-template <int LOGD>
+// Shape of one launch: V = 2^LOGV sketch entries per lane, G lanes per unit
+// (point, part), U = 64/G units per wave.
+template <int LOGD, int LOGV>
 struct Shape {
     static constexpr int D = 1 << LOGD;
-    static constexpr int G = D > 64 ? D / 64 : 1;  // lanes per unit
-    static constexpr int V = D / G;                // sketch entries per lane
-    static constexpr int U = 64 / G;               // units per wave
+    static constexpr int V = 1 << LOGV;
+    static constexpr int LOGG = LOGD - LOGV;
+    static constexpr int G = 1 << LOGG;
+    static constexpr int LOGU = 6 - LOGG;
+    static constexpr int U = 1 << LOGU;
+    static_assert(LOGG >= 0 && LOGG <= 6, "G must divide a wave");
+    // Cross-lane stage b (lane bit LOGU + b, partner distance U << b) is a
+    // "swap" stage when the distance is 16 or 32: a permlane swap of register
+    // pairs (k, k ^ 2^q), q = LOGV - LOGG + b, moves index bit LOGV + b into
+    // register bit q and the (already transformed) index bit q into the lane
+    // bit; the butterfly then runs inside each lane.
+    static constexpr bool swap_stage(int b) { return LOGU + b >= 4; }
+    static constexpr int swap_reg(int b) { return LOGV - LOGG + b; }
+    // Index bit held by register bit r after all stages.
+    static constexpr int reg_bit_index(int r) {
+        for (int b = 0; b < LOGG; ++b)
+            if (swap_stage(b) && swap_reg(b) == r) return LOGV + b;
+        return r;
+    }
+    // Index bits carried by register number k.
+    static constexpr int vreg(int k) {
+        int v = 0;
+        for (int r = 0; r < LOGV; ++r)
+            if ((k >> r) & 1) v |= 1 << reg_bit_index(r);
+        return v;
+    }
 };
 
-template <int LOGD>
-__global__ __launch_bounds__(256) void fht_hash_kernel(
-    const uint64_t *__restrict__ pts, int64_t m, int W, const int32_t *__restrict__ seg,
-    const int32_t *__restrict__ ecoord, const double *__restrict__ eb, int E,
-    uint32_t *__restrict__ keys, int64_t key_stride) {
-    using S = Shape<LOGD>;
-    constexpr int D = S::D, G = S::G, V = S::V, U = S::U;
-    extern __shared__ uint32_t xs[];
+__device__ inline double dpp_f64(double x, int ctrl_sel) {
+    const uint64_t u = __double_as_longlong(x);
+    int lo = int(uint32_t(u)), hi = int(uint32_t(u >> 32));
+    switch (ctrl_sel) {
+        case 8:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x128, 0xf, 0xf, false);  // row_ror:8 = lane ^ 8
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x128, 0xf, 0xf, false);
+            break;
+        case 4:
+            lo = __builtin_amdgcn_ds_swizzle(lo, (4 << 10) | 0x1F);  // lane ^ 4 within 32
+            hi = __builtin_amdgcn_ds_swizzle(hi, (4 << 10) | 0x1F);
+            break;
+        case 2:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xf, 0xf, false);
+            break;
+        default:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xf, 0xf, false);
+            break;
+    }
+    return __longlong_as_double((int64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
 
+// After the swap, a holds the partner-pair element with the partner-lane
+// index bit 0 and b the one with it 1, in every lane (dist 16 or 32).
+template <int DIST>
+__device__ inline void swap_f64(double &a, double &b) {
+    const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    uint32_t alo = uint32_t(ua), ahi = uint32_t(ua >> 32), blo = uint32_t(ub), bhi = uint32_t(ub >> 32);
+    if constexpr (DIST == 32) {
+        auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
+    } else {
+        auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
+    }
+    a = __longlong_as_double((int64_t(ahi) << 32) | alo);
+    b = __longlong_as_double((int64_t(bhi) << 32) | blo);
+}
+
+template <int LOGD, int LOGV, int B>
+__device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
+    using S = Shape<LOGD, LOGV>;
+    if constexpr (B >= 0) {
+        constexpr int dist = S::U << B;
+        if constexpr (S::swap_stage(B)) {
+            constexpr int q = S::swap_reg(B);
+#pragma unroll
+            for (int k = 0; k < S::V; ++k) {
+                if (!(k & (1 << q))) {
+                    double a = t[k], b = t[k | (1 << q)];
+                    swap_f64<dist>(a, b);
+                    t[k] = a + b;
+                    t[k | (1 << q)] = a - b;
+                }
+            }
+        } else {
+            const double sgn = (lane & dist) ? -1.0 : 1.0;
+#pragma unroll
+            for (int k = 0; k < S::V; ++k) t[k] = fma(sgn, t[k], dpp_f64(t[k], dist));
+        }
+        cross_stages<LOGD, LOGV, B - 1>(t, lane);
+    }
+}
+
+// One workgroup of 4 waves per (part, slice of point groups); each wave
+// takes groups of U consecutive points in a grid-stride loop.  The part's
+// gather table (per in-lane column k and sub-lane s, the coordinate feeding
+// it and its even representative b'') is staged in LDS once per workgroup.
+template <int LOGD, int LOGV, bool SPECIFIC>
+__global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restrict__ pts, int64_t m, int W,
+                                                       const int32_t *__restrict__ seg,
+                                                       const uint2 *__restrict__ gtab, int E,
+                                                       uint32_t *__restrict__ keys, int64_t key_stride) {
+    using S = Shape<LOGD, LOGV>;
+    constexpr int V = S::V, G = S::G, U = S::U, D = S::D;
+    extern __shared__ uint32_t lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    const int s = lane / U;  // sub-index of this lane within its unit
-    const int u = lane % U;  // unit slot within the wave
+    const int s = lane >> S::LOGU;
+    const int u = lane & (U - 1);
     const int p = blockIdx.y;
-    const int stride = 2 * W + 1;  // dwords per staged point (+1 zero dword)
-    uint32_t *wx = xs + wave * U * stride;
-    const int64_t base = (int64_t(blockIdx.x) * wpb + wave) * U;
+    const int stride = 2 * W + 1;
+    uint2 *tab = reinterpret_cast<uint2 *>(lds);
+    uint32_t *wx = lds + 2 * E * G + wave * U * stride;
 
-    // Stage the wave's U points (coalesced uint64 loads) into LDS as dwords.
-    for (int e = lane; e < U * W; e += 64) {
-        const int uu = e / W, w = e - uu * W;
-        const int64_t i = base + uu;
-        const uint64_t v = (i < m) ? pts[i * W + w] : 0ull;
-        wx[uu * stride + 2 * w] = uint32_t(v);
-        wx[uu * stride + 2 * w + 1] = uint32_t(v >> 32);
-    }
-    if (lane < U) wx[lane * stride + 2 * W] = 0u;
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int i = threadIdx.x; i < E * G; i += 256) tab[i] = gtab[int64_t(p) * E * G + i];
+    __syncthreads();
 
-    const uint32_t *myx = wx + u * stride;
-    const int32_t *sg = seg + p * (V + 1);
-    const int32_t *ec = ecoord + int64_t(p) * E * G + s;
-    const double *ebp = eb + int64_t(p) * E * G + s;
-
-    // Sketch (Alg. 2 lines 2-8).
-    double t[V];
+    // index bits of the output held by this lane (see Shape)
+    int vlane = 0;
 #pragma unroll
-    for (int k = 0; k < V; ++k) {
-        double acc = 0.0;
-        const int e1 = sg[k + 1];
-        for (int e = sg[k]; e < e1; ++e) {
-            const int c = ec[e * G];
-            const uint32_t word = myx[c >> 5];
-            const double bv = ebp[e * G];
-            acc += ((word >> (c & 31)) & 1u) ? bv : 0.0;
+    for (int b = 0; b < S::LOGG; ++b)
+        if ((lane >> (S::LOGU + b)) & 1) vlane |= 1 << (S::swap_stage(b) ? S::swap_reg(b) : LOGV + b);
+
+    const int64_t ngroups = (m + U - 1) / U;
+    for (int64_t grp = int64_t(blockIdx.x) * 4 + wave; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
+        const int64_t base = grp * U;
+        for (int e = lane; e < U * W; e += 64) {
+            const int uu = e / W, w = e - uu * W;
+            const int64_t i = base + uu;
+            const uint64_t v = (i < m) ? pts[i * W + w] : 0ull;
+            wx[uu * stride + 2 * w] = uint32_t(v);
+            wx[uu * stride + 2 * w + 1] = uint32_t(v >> 32);
         }
-        t[k] = acc;
-    }
+        if (lane < U) wx[lane * stride + 2 * W] = 0u;
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t *myx = wx + u * stride;
 
-    // Fast Hadamard transform (Alg. 2 line 10), in-register stages.
+        // Sketch (Alg. 2 lines 2-8)
+        double t[V];
+        if constexpr (SPECIFIC) {
 #pragma unroll
-    for (int h = 1; h < V; h <<= 1) {
+            for (int k = 0; k < V; ++k) {
+                const uint2 en = tab[k * G + s];
+                const uint32_t bit = (myx[en.y >> 5] >> (en.y & 31)) & 1u;
+                t[k] = double(bit ? en.x : 0u);
+            }
+        } else {
+            const int32_t *sg = seg + p * (V + 1);
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            if (!(k & h)) {
-                const double a = t[k], b = t[k | h];
-                t[k] = a + b;
-                t[k | h] = a - b;
+            for (int k = 0; k < V; ++k) {
+                double acc = 0.0;
+                const int e1 = sg[k + 1];
+                for (int e = sg[k]; e < e1; ++e) {
+                    const uint2 en = tab[e * G + s];
+                    const uint32_t bit = (myx[en.y >> 5] >> (en.y & 31)) & 1u;
+                    acc += double(bit ? en.x : 0u);
+                }
+                t[k] = acc;
             }
         }
-    }
-    // Stages across the G lanes of a unit (lane distance U << g).
-#pragma unroll
-    for (int g = 1; g < G; g <<= 1) {
-        const double sgn = (s & g) ? -1.0 : 1.0;
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const double o = __shfl_xor(t[k], g * U, 64);
-            t[k] = fma(sgn, t[k], o);
-        }
-    }
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
 
-    // S'' = F''_0 lives in sub-index 0 (lane u) at k = 0.
-    const double Sm = __shfl(t[0], u, 64) + kTwo52;
-    const int64_t i = base + u;
-    if (i < m) {
-        uint32_t *out = keys + int64_t(p) * (D - 1) * key_stride + i;
+        // Fast Hadamard transform (Alg. 2 line 10): in-register stages ...
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const int v = s * V + k;
-            if (v == 0) continue;  // all-zero codeword, removed by Alg. 2
-            const double z = Sm - t[k];
-            const uint64_t zb = __double_as_longlong(z);
-            uint32_t y = (uint32_t(zb) >> 1) + (uint32_t(zb >> 32) & 0xFFFFFu);
-            y = min(y, y - kPrime);
-            out[int64_t(v - 1) * key_stride] = y;
+        for (int h = 1; h < V; h <<= 1) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (!(k & h)) {
+                    const double a = t[k], b = t[k | h];
+                    t[k] = a + b;
+                    t[k | h] = a - b;
+                }
+            }
+        }
+        // ... then the stages across the G lanes of a unit
+        cross_stages<LOGD, LOGV, S::LOGG - 1>(t, lane);
+
+        // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
+        const double Sm = __shfl(t[0], u, 64) + kTwo52;
+        const int64_t i = base + u;
+        if (i < m) {
+            uint32_t *out = keys + (int64_t(p) * (D - 1) + vlane - 1) * key_stride + i;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int vr = S::vreg(k);
+                if (vr == 0 && vlane == 0) continue;  // row 0: all-zero codeword, dropped
+                const double z = Sm - t[k];
+                const uint64_t zb = __double_as_longlong(z);
+                uint32_t y = (uint32_t(zb) >> 1) + (uint32_t(zb >> 32) & 0xFFFFFu);
+                y = min(y, y - kPrime);
+                out[int64_t(vr) * key_stride] = y;
+            }
         }
     }
 }
 
-template <int LOGD>
-fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys,
-                      int64_t key_stride, hipStream_t st) {
-    using S = Shape<LOGD>;
+template <int LOGD, int LOGV>
+fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys, int64_t key_stride,
+                      hipStream_t st) {
+    using S = Shape<LOGD, LOGV>;
     const HashPlan &pl = ix.plan;
-    const size_t per_wave = size_t(S::U) * (2 * pl.W + 1) * 4;
-    int wpb = int(65536 / per_wave);
-    if (wpb > 4) wpb = 4;
-    if (wpb < 1) return fail(FCLSH_EUNSUPPORTED, "point too wide for the hash kernel");
-    const int64_t per_block = int64_t(wpb) * S::U;
-    const int64_t nblk = (m + per_block - 1) / per_block;
-    if (nblk > 0x7FFFFFFF) return fail(FCLSH_EINVAL, "too many points for one launch");
+    const size_t lds = size_t(pl.E) * S::G * 8 + size_t(4) * S::U * (2 * pl.W + 1) * 4;
+    if (lds > 160 * 1024) return fail(FCLSH_EUNSUPPORTED, "hash kernel LDS need %zu bytes", lds);
+    const int64_t ngroups = (m + S::U - 1) / S::U;
+    int64_t nblk = (ngroups + 3) / 4;
+    const int64_t cap = int64_t(pl.blocks_per_part_cap);
+    if (nblk > cap) nblk = cap;
     dim3 grid(unsigned(nblk), unsigned(pl.t));
-    hipLaunchKernelGGL(fht_hash_kernel<LOGD>, grid, dim3(64 * wpb), per_wave * wpb, st, pts, m,
-                       pl.W, pl.seg, pl.coord, pl.bval, pl.E, keys, key_stride);
+    if (pl.specific)
+        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, true>), grid, dim3(256), lds, st, pts, m, pl.W, pl.seg,
+                           pl.gtab, pl.E, keys, key_stride);
+    else
+        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, false>), grid, dim3(256), lds, st, pts, m, pl.W, pl.seg,
+                           pl.gtab, pl.E, keys, key_stride);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
 
 }  // namespace
 
+// 32 sketch entries per lane (64 VGPRs of fp64) keep several waves per SIMD;
+// 64 only where a unit would otherwise need more than a wave (D = 4096).
+int hash_log_v(int logD) { return logD <= 5 ? logD : (logD - 6 > 5 ? logD - 6 : 5); }
+
 fclsh_status build_hash_plan(Index *ix) {
     const Params &p = ix->prm;
     HashPlan &pl = ix->plan;
     const int D = p.D();
     pl.logD = p.rp + 1;
-    pl.G = D > 64 ? D / 64 : 1;
-    pl.V = D / pl.G;
+    pl.logV = hash_log_v(pl.logD);
+    pl.V = 1 << pl.logV;
+    pl.G = D / pl.V;
     pl.U = 64 / pl.G;
     pl.t = p.t;
     pl.W = ix->W;
@@ -172,42 +288,50 @@ fclsh_status build_hash_plan(Index *ix) {
     // column -> coordinates of each part
     std::vector<std::vector<std::vector<int32_t>>> lists(p.t, std::vector<std::vector<int32_t>>(D));
     for (int c = 0; c < p.d; ++c) lists[p.part[c]][p.col[c]].push_back(c);
+    size_t most = 0;
+    for (auto &lp : lists)
+        for (auto &l : lp) most = std::max(most, l.size());
+    pl.specific = most <= 1;
 
+    // in-lane column k of sub-lane s is Hadamard column s*V + k; entries of k
+    // are padded to the longest list among the G sub-lanes
     std::vector<int32_t> seg(size_t(p.t) * (V + 1), 0);
     int E = 0;
     for (int q = 0; q < p.t; ++q) {
         int32_t *sq = &seg[size_t(q) * (V + 1)];
         for (int k = 0; k < V; ++k) {
-            size_t mx = 0;
+            size_t mx = pl.specific ? 1 : 0;
             for (int s = 0; s < G; ++s) mx = std::max(mx, lists[q][s * V + k].size());
             sq[k + 1] = sq[k] + int32_t(mx);
         }
         E = std::max(E, int(sq[V]));
     }
     pl.E = std::max(E, 1);
-    std::vector<int32_t> coord(size_t(p.t) * pl.E * G, zero_slot);
-    std::vector<double> bval(size_t(p.t) * pl.E * G, 0.0);
+    std::vector<uint32_t> tab(size_t(p.t) * pl.E * G * 2, 0);
+    for (size_t i = 0; i < tab.size(); i += 2) tab[i + 1] = uint32_t(zero_slot);
     for (int q = 0; q < p.t; ++q) {
         const int32_t *sq = &seg[size_t(q) * (V + 1)];
         for (int k = 0; k < V; ++k)
             for (int s = 0; s < G; ++s) {
                 const auto &lst = lists[q][s * V + k];
                 for (size_t a = 0; a < lst.size(); ++a) {
-                    const size_t e = size_t(sq[k]) + a;
-                    const size_t at = (size_t(q) * pl.E + e) * G + s;
+                    const size_t at = ((size_t(q) * pl.E + size_t(sq[k]) + a) * G + s) * 2;
                     const int c = lst[a];
-                    coord[at] = c;
                     const uint64_t b = p.b[c];
-                    bval[at] = double((b & 1) ? b + kPrime : b);
+                    tab[at] = uint32_t((b & 1) ? b + kPrime : b);  // even representative, < 2^32
+                    tab[at + 1] = uint32_t(c);
                 }
             }
     }
+    // One point group per wave: short-lived waves keep every SIMD full (a
+    // grid-stride loop over groups measured 1.9x slower on the mid workload,
+    // its waves serialising staging loads and compute).  The cap only bounds
+    // the grid for very large batches.
+    pl.blocks_per_part_cap = 1 << 30;
     FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.seg), seg.size() * 4, "hash plan"));
-    FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.coord), coord.size() * 4, "hash plan"));
-    FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.bval), bval.size() * 8, "hash plan"));
+    FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.gtab), tab.size() * 4, "hash plan"));
     FCLSH_HIP(hipMemcpy(pl.seg, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
-    FCLSH_HIP(hipMemcpy(pl.coord, coord.data(), coord.size() * 4, hipMemcpyHostToDevice));
-    FCLSH_HIP(hipMemcpy(pl.bval, bval.data(), bval.size() * 8, hipMemcpyHostToDevice));
+    FCLSH_HIP(hipMemcpy(pl.gtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
     return FCLSH_OK;
 }
 
@@ -215,18 +339,18 @@ fclsh_status launch_hash(const Index &ix, const uint64_t *pts, int64_t m, uint32
                          int64_t key_stride, hipStream_t st) {
     if (m == 0) return FCLSH_OK;
     switch (ix.plan.logD) {
-        case 1: return launch_t<1>(ix, pts, m, keys, key_stride, st);
-        case 2: return launch_t<2>(ix, pts, m, keys, key_stride, st);
-        case 3: return launch_t<3>(ix, pts, m, keys, key_stride, st);
-        case 4: return launch_t<4>(ix, pts, m, keys, key_stride, st);
-        case 5: return launch_t<5>(ix, pts, m, keys, key_stride, st);
-        case 6: return launch_t<6>(ix, pts, m, keys, key_stride, st);
-        case 7: return launch_t<7>(ix, pts, m, keys, key_stride, st);
-        case 8: return launch_t<8>(ix, pts, m, keys, key_stride, st);
-        case 9: return launch_t<9>(ix, pts, m, keys, key_stride, st);
-        case 10: return launch_t<10>(ix, pts, m, keys, key_stride, st);
-        case 11: return launch_t<11>(ix, pts, m, keys, key_stride, st);
-        case 12: return launch_t<12>(ix, pts, m, keys, key_stride, st);
+        case 1: return launch_t<1, 1>(ix, pts, m, keys, key_stride, st);
+        case 2: return launch_t<2, 2>(ix, pts, m, keys, key_stride, st);
+        case 3: return launch_t<3, 3>(ix, pts, m, keys, key_stride, st);
+        case 4: return launch_t<4, 4>(ix, pts, m, keys, key_stride, st);
+        case 5: return launch_t<5, 5>(ix, pts, m, keys, key_stride, st);
+        case 6: return launch_t<6, 5>(ix, pts, m, keys, key_stride, st);
+        case 7: return launch_t<7, 5>(ix, pts, m, keys, key_stride, st);
+        case 8: return launch_t<8, 5>(ix, pts, m, keys, key_stride, st);
+        case 9: return launch_t<9, 5>(ix, pts, m, keys, key_stride, st);
+        case 10: return launch_t<10, 5>(ix, pts, m, keys, key_stride, st);
+        case 11: return launch_t<11, 5>(ix, pts, m, keys, key_stride, st);
+        case 12: return launch_t<12, 6>(ix, pts, m, keys, key_stride, st);
         default: return fail(FCLSH_EUNSUPPORTED, "Hadamard order 2^%d", ix.plan.logD);
     }
 }

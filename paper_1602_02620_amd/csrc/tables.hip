@@ -36,7 +36,7 @@ constexpr int kMaxLoBits = 11;
 
 // A wave's LDS operations execute in issue order; this keeps the compiler from
 // moving plain LDS accesses across the atomics between phases.
-__device__ inline void wave_lds_order() {
+[[maybe_unused]] __device__ inline void wave_lds_order() {
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_wave_barrier();
 }
