@@ -54,6 +54,9 @@ typedef int32_t fclsh_status;
 /* Opaque, immutable once built; may be queried from several streams. */
 typedef struct fclsh_index_s *fclsh_index;
 
+/* An instantiated HIP graph of one batched query (fclsh_query_graph_create). */
+typedef struct fclsh_graph_s *fclsh_graph;
+
 /* Build options (all-zero = the paper's defaults). */
 typedef struct {
     int32_t partitions;        /* t; 0 = the experiments' rule: 1 if r < 10 else 2
@@ -206,6 +209,67 @@ FCLSH_API fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_quer
                                int64_t nq, int32_t r_query, void *stream,
                                uint64_t *d_offsets, uint32_t *d_ids,
                                int64_t ids_capacity, int64_t *total_out);
+
+/* ---------------------------------------------------------------------------
+ * Batching and serving (batched execution of Strategy 2 for many queries).
+ * ------------------------------------------------------------------------- */
+
+/* As fclsh_query_batch, with one radius per query: d_radii (device, nq int32,
+ * each in [0, max_radius]) and max_radius <= the index's r (else
+ * FCLSH_ERADIUS).  Queries of different radii share one launch sequence. */
+FCLSH_API fclsh_status fclsh_query_batch_radii(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                               const int32_t *d_radii, int32_t max_radius, void *stream,
+                                               uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
+                                               int64_t *total_out);
+
+/* Sizes the query workspace of `stream` for up to max_nq queries per batch,
+ * pair_capacity reported (query, id) pairs and spill_capacity chunks of large
+ * buckets (see fclsh_query_batch_async).  Allocates; synchronises `stream`.
+ * Call before fclsh_query_batch_async or graph capture. */
+FCLSH_API fclsh_status fclsh_query_reserve(fclsh_index idx, int64_t max_nq, int64_t pair_capacity,
+                                           int64_t spill_capacity, void *stream);
+
+/* The batched pipeline without any host synchronisation or allocation:
+ * hash, bucket lookup, verification by persistent waves that pull work from
+ * device queues (a bucket larger than the tuned tile is split into
+ * tile-sized chunks), CSR offsets and per-query sorting, all enqueued on
+ * `stream`.  The workspace of `stream` must have been reserved for nq
+ * queries.  r_query applies to all queries unless d_radii (device, nq int32)
+ * is given.  Outputs as fclsh_query_batch, plus d_result (device, 2 uint64):
+ * [0] = total reported ids, [1] = status bits: 1 pair buffer overflow,
+ * 2 spill queue overflow (reserve more and rerun), 4 ids_capacity too small
+ * (d_offsets valid, d_ids not written).  Capturable in a HIP graph. */
+FCLSH_API fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                               int32_t r_query, const int32_t *d_radii, void *stream,
+                                               uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
+                                               uint64_t *d_result);
+
+/* Captures fclsh_query_batch_async with these fixed buffers into a HIP graph
+ * on `stream` (which must not be the null stream) and instantiates it.
+ * Replaying it (fclsh_graph_launch) answers whatever queries d_queries holds
+ * at that time.  The stream's workspace must be reserved first and must not
+ * be re-reserved while the graph is alive. */
+FCLSH_API fclsh_status fclsh_query_graph_create(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                                int32_t r_query, const int32_t *d_radii, uint64_t *d_offsets,
+                                                uint32_t *d_ids, int64_t ids_capacity, uint64_t *d_result,
+                                                void *stream, fclsh_graph *out);
+FCLSH_API fclsh_status fclsh_graph_launch(fclsh_graph graph, void *stream);
+FCLSH_API void fclsh_graph_free(fclsh_graph graph);
+
+/* Launch shape of the batched verification: tile = bucket entries per work
+ * item and per spill chunk (64 .. 2^20), blocks_per_cu = persistent
+ * workgroups per compute unit (1 .. 64). */
+FCLSH_API fclsh_status fclsh_index_set_tuning(fclsh_index idx, int32_t tile, int32_t blocks_per_cu);
+FCLSH_API fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, int32_t *blocks_per_cu);
+
+/* Autotuner: times the batched pipeline on a sample batch (device queries)
+ * for a grid of (tile, blocks_per_cu) and keeps the fastest on the index; the
+ * choice is also cached for later indexes of the same shape (d, t, r',
+ * ceil(log2 n)) on the same device.  Outputs (optional): the chosen values
+ * and its time per batch in ms.  Synchronises `stream`. */
+FCLSH_API fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                      int32_t r_query, void *stream, int32_t *tile_out,
+                                      int32_t *blocks_out, float *best_ms_out);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,15 @@ EXPORTS = [
     "fclsh_derive_params", "fclsh_build_index", "fclsh_build_index_with_params", "fclsh_query_batch",
     "fclsh_index_free", "fclsh_last_error", "fclsh_index_info", "fclsh_index_params", "fclsh_hash",
     "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_query_collisions", "fclsh_query_plain",
+    "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
+    "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
+    "fclsh_autotune",
 ]
+
+# status bits of the device result of fclsh_query_batch_async
+QUERY_PAIR_OVERFLOW = 1
+QUERY_SPILL_OVERFLOW = 2
+QUERY_IDS_OVERFLOW = 4
 
 
 class FclshError(RuntimeError):
@@ -71,6 +79,14 @@ def lib():
             "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
             "fclsh_index_rebuild": [vp, vp],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
+            "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
+            "fclsh_query_reserve": [vp, i64, i64, i64, vp],
+            "fclsh_query_batch_async": [vp, vp, i64, i32, vp, vp, vp, vp, i64, vp],
+            "fclsh_query_graph_create": [vp, vp, i64, i32, vp, vp, vp, i64, vp, vp, P(vp)],
+            "fclsh_graph_launch": [vp, vp],
+            "fclsh_index_set_tuning": [vp, i32, i32],
+            "fclsh_index_get_tuning": [vp, P(i32), P(i32)],
+            "fclsh_autotune": [vp, vp, i64, i32, vp, P(i32), P(i32), P(ctypes.c_float)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -78,6 +94,8 @@ def lib():
             f.restype = i32
         L.fclsh_index_free.argtypes = [vp]
         L.fclsh_index_free.restype = None
+        L.fclsh_graph_free.argtypes = [vp]
+        L.fclsh_graph_free.restype = None
         L.fclsh_last_error.argtypes = []
         L.fclsh_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -265,6 +283,73 @@ class Index:
         """Same answers via one launch sequence per query (the unbatched baseline)."""
         return self._run_query(lib().fclsh_query_plain, queries, r, ids_capacity, stream)
 
+    def query_radii(self, queries, radii, ids_capacity=None, stream=None):
+        """Exact r-NN reporting with one radius per query (int32 CUDA tensor)."""
+        torch = _torch()
+        q = _dev_words(queries, self.d, "queries")
+        rad = radii.to(device=q.device, dtype=torch.int32).contiguous()
+        nq = q.shape[0]
+        if rad.shape != (nq,):
+            raise ValueError("one radius per query")
+        rmax = int(rad.max().item()) if nq else 0
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=q.device)
+        cap = int(ids_capacity) if ids_capacity is not None else max(1024, 64 * nq)
+        total = ctypes.c_int64()
+        for _ in range(2):
+            ids = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
+            st = lib().fclsh_query_batch_radii(self._h, ctypes.c_void_p(q.data_ptr()), nq,
+                                               ctypes.c_void_p(rad.data_ptr()), rmax, _stream_ptr(stream),
+                                               ctypes.c_void_p(offsets.data_ptr()),
+                                               ctypes.c_void_p(ids.data_ptr()), cap, ctypes.byref(total))
+            if st == FCLSH_ECAPACITY and ids_capacity is None:
+                cap = total.value
+                continue
+            _check(st)
+            return offsets, ids[:total.value]
+        raise FclshError(FCLSH_ECAPACITY, "result did not fit after resizing")
+
+    def reserve(self, max_nq: int, pair_capacity: int, spill_capacity: int = 1 << 16, stream=None):
+        """Size the stream's query workspace for the asynchronous / graph path."""
+        _check(lib().fclsh_query_reserve(self._h, max_nq, pair_capacity, spill_capacity, _stream_ptr(stream)))
+
+    def query_async(self, queries, r: int, offsets, ids, result, radii=None, stream=None):
+        """Enqueue a batch without host synchronisation.  offsets: int64
+        [nq+1], ids: int32 [capacity], result: int64 [2] (total, status bits),
+        all CUDA tensors owned by the caller."""
+        q = _dev_words(queries, self.d, "queries")
+        rp = ctypes.c_void_p(radii.data_ptr()) if radii is not None else ctypes.c_void_p()
+        _check(lib().fclsh_query_batch_async(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0], r, rp,
+                                             _stream_ptr(stream), ctypes.c_void_p(offsets.data_ptr()),
+                                             ctypes.c_void_p(ids.data_ptr()), ids.numel(),
+                                             ctypes.c_void_p(result.data_ptr())))
+
+    def query_graph(self, queries, r: int, offsets, ids, result, radii=None, stream=None):
+        """Capture query_async on these buffers into a replayable HIP graph."""
+        q = _dev_words(queries, self.d, "queries")
+        rp = ctypes.c_void_p(radii.data_ptr()) if radii is not None else ctypes.c_void_p()
+        g = ctypes.c_void_p()
+        _check(lib().fclsh_query_graph_create(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0], r, rp,
+                                              ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                                              ids.numel(), ctypes.c_void_p(result.data_ptr()),
+                                              _stream_ptr(stream), ctypes.byref(g)))
+        return QueryGraph(g)
+
+    def set_tuning(self, tile: int, blocks_per_cu: int):
+        _check(lib().fclsh_index_set_tuning(self._h, tile, blocks_per_cu))
+
+    def get_tuning(self):
+        t, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fclsh_index_get_tuning(self._h, ctypes.byref(t), ctypes.byref(b)))
+        return {"tile": t.value, "blocks_per_cu": b.value}
+
+    def autotune(self, queries, r: int, stream=None):
+        """Pick the batched launch shape on a sample batch; returns it with its time."""
+        q = _dev_words(queries, self.d, "queries")
+        t, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        _check(lib().fclsh_autotune(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0], r, _stream_ptr(stream),
+                                    ctypes.byref(t), ctypes.byref(b), ctypes.byref(ms)))
+        return {"tile": t.value, "blocks_per_cu": b.value, "ms": ms.value}
+
     def collisions(self, queries, stream=None):
         """#Collisions (Sec. 4.1) per query, int64 [nq]."""
         torch = _torch()
@@ -273,6 +358,27 @@ class Index:
         _check(lib().fclsh_query_collisions(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0],
                                             _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())))
         return out
+
+
+class QueryGraph:
+    """A captured batched query; launch() replays it on a stream."""
+
+    def __init__(self, handle):
+        self._g = handle
+
+    def launch(self, stream=None):
+        _check(lib().fclsh_graph_launch(self._g, _stream_ptr(stream)))
+
+    def close(self):
+        if self._g and self._g.value:
+            lib().fclsh_graph_free(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _hip = None

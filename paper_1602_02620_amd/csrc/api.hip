@@ -2,6 +2,7 @@
 // index object and its device memory, per-stream query workspaces.
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -71,6 +72,8 @@ struct IndexHandle {
     }
 };
 
+static void lookup_tuning(Index &ix);
+
 static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bits) {
     const size_t L = size_t(p.L());
     size_t b = size_t(n) * W * 8;                        // point copy
@@ -114,6 +117,13 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
     ix.dir_bits = table_dir_bits(n);
     ix.budget = budget;
     (void)hipGetDevice(&ix.device);
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ix.device) == hipSuccess && prop.multiProcessorCount > 0)
+            ix.num_cus = prop.multiProcessorCount;
+        (void)hipGetLastError();
+    }
+    lookup_tuning(ix);
     auto bail = [&](fclsh_status s) {
         dev_free_all(&ix);
         delete h;
@@ -150,6 +160,45 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
 }
 
 static IndexHandle *handle(fclsh_index idx) { return reinterpret_cast<IndexHandle *>(idx); }
+
+// Process-wide cache of autotuned launch shapes, keyed by index shape and
+// device, so that a rebuilt index of the same shape starts tuned.
+struct TuneKey {
+    int device, d, t, rp, logn;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(device, d, t, rp, logn) < std::tie(o.device, o.d, o.t, o.rp, o.logn);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, QueryTuning> g_tune_cache;
+
+static TuneKey tune_key(const Index &ix) {
+    return TuneKey{ix.device, ix.prm.d, ix.prm.t, ix.prm.rp, ilog2_ceil(uint64_t(ix.n))};
+}
+
+static void lookup_tuning(Index &ix) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(ix));
+    if (it != g_tune_cache.end()) ix.tuning = it->second;
+}
+
+namespace {
+__global__ void publish_result_kernel(const QueryCtrl *ctrl, uint64_t *out) {
+    out[0] = ctrl->total;
+    out[1] = ctrl->status;
+}
+}  // namespace
+
+static fclsh_status publish_result(QueryWorkspace &ws, uint64_t *d_result, hipStream_t st) {
+    hipLaunchKernelGGL(publish_result_kernel, dim3(1), dim3(1), 0, st, ws.ctrl, d_result);
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
+}
+
+struct GraphHandle {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 }  // namespace fclsh
 
@@ -275,8 +324,8 @@ fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries, int64
     if (r_query > h->ix.prm.r)
         return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", r_query, h->ix.prm.r);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return query_batch(h->ix, *h->workspace(st), d_queries, nq, r_query, st, d_offsets, d_ids, ids_capacity,
-                       total_out);
+    return query_batch(h->ix, *h->workspace(st), d_queries, nq, r_query, nullptr, st, d_offsets, d_ids,
+                       ids_capacity, total_out);
 }
 
 fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries, int64_t nq, void *stream,
@@ -302,6 +351,181 @@ fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_queries, int64
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     return query_plain(h->ix, *h->workspace(st), d_queries, nq, r_query, st, d_offsets, d_ids, ids_capacity,
                        total_out);
+}
+
+fclsh_status fclsh_query_batch_radii(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                     const int32_t *d_radii, int32_t max_radius, void *stream,
+                                     uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
+                                     int64_t *total_out) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
+    if (nq < 0 || nq > 0x7FFFFFFFll || (nq && (!d_queries || !d_radii))) return fail(FCLSH_EINVAL, "bad queries");
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    IndexHandle *h = handle(idx);
+    if (max_radius < 0) return fail(FCLSH_EINVAL, "negative query radius");
+    if (max_radius > h->ix.prm.r)
+        return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", max_radius, h->ix.prm.r);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return query_batch(h->ix, *h->workspace(st), d_queries, nq, 0, d_radii, st, d_offsets, d_ids, ids_capacity,
+                       total_out);
+}
+
+fclsh_status fclsh_query_reserve(fclsh_index idx, int64_t max_nq, int64_t pair_capacity,
+                                 int64_t spill_capacity, void *stream) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (max_nq < 0 || pair_capacity < 1 || spill_capacity < 1) return fail(FCLSH_EINVAL, "bad capacities");
+    IndexHandle *h = handle(idx);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    FCLSH_HIP(hipStreamSynchronize(st));  // buffers may be replaced
+    return ws_reserve(*h->workspace(st), max_nq, h->ix.prm.L(), pair_capacity, spill_capacity);
+}
+
+fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
+                                     const int32_t *d_radii, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
+                                     int64_t ids_capacity, uint64_t *d_result) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
+    if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    IndexHandle *h = handle(idx);
+    if (r_query < 0) return fail(FCLSH_EINVAL, "negative query radius");
+    if (r_query > h->ix.prm.r)
+        return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", r_query, h->ix.prm.r);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    QueryWorkspace &ws = *h->workspace(st);
+    FCLSH_TRY(query_batch_async(h->ix, ws, d_queries, nq, r_query, d_radii, st, d_offsets, d_ids, ids_capacity));
+    return publish_result(ws, d_result, st);
+}
+
+fclsh_status fclsh_query_graph_create(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
+                                      const int32_t *d_radii, uint64_t *d_offsets, uint32_t *d_ids,
+                                      int64_t ids_capacity, uint64_t *d_result, void *stream,
+                                      fclsh_graph *out) {
+    if (!out) return fail(FCLSH_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!stream) return fail(FCLSH_EINVAL, "graph capture needs a non-null stream");
+    auto *g = new GraphHandle();
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete g;
+        return fail(FCLSH_EDEVICE, "hipStreamBeginCapture failed");
+    }
+    fclsh_status s = fclsh_query_batch_async(idx, d_queries, nq, r_query, d_radii, stream, d_offsets, d_ids,
+                                             ids_capacity, d_result);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s != FCLSH_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return s != FCLSH_OK ? s : fail(FCLSH_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    }
+    g->graph = graph;
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return fail(FCLSH_EDEVICE, "hipGraphInstantiate failed");
+    }
+    *out = reinterpret_cast<fclsh_graph>(g);
+    return FCLSH_OK;
+}
+
+fclsh_status fclsh_graph_launch(fclsh_graph graph, void *stream) {
+    if (!graph) return fail(FCLSH_EINVAL, "null graph");
+    FCLSH_HIP(hipGraphLaunch(reinterpret_cast<GraphHandle *>(graph)->exec, reinterpret_cast<hipStream_t>(stream)));
+    return FCLSH_OK;
+}
+
+void fclsh_graph_free(fclsh_graph graph) {
+    if (!graph) return;
+    auto *g = reinterpret_cast<GraphHandle *>(graph);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+fclsh_status fclsh_index_set_tuning(fclsh_index idx, int32_t tile, int32_t blocks_per_cu) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (tile < 64 || tile > (1 << 20) || blocks_per_cu < 1 || blocks_per_cu > 64)
+        return fail(FCLSH_EINVAL, "tile in [64, 2^20], blocks per CU in [1, 64]");
+    handle(idx)->ix.tuning = QueryTuning{tile, blocks_per_cu};
+    return FCLSH_OK;
+}
+
+fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, int32_t *blocks_per_cu) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (tile) *tile = handle(idx)->ix.tuning.tile;
+    if (blocks_per_cu) *blocks_per_cu = handle(idx)->ix.tuning.blocks_per_cu;
+    return FCLSH_OK;
+}
+
+fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
+                            void *stream, int32_t *tile_out, int32_t *blocks_out, float *best_ms_out) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (nq < 1 || !d_queries) return fail(FCLSH_EINVAL, "autotuning needs a sample batch");
+    IndexHandle *h = handle(idx);
+    if (r_query < 0 || r_query > h->ix.prm.r) return fail(FCLSH_ERADIUS, "bad query radius");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    QueryWorkspace &ws = *h->workspace(st);
+    Index &ix = h->ix;
+    // size the buffers once with the synchronous path, then time candidates
+    uint64_t *offs = nullptr;
+    uint32_t *ids = nullptr;
+    uint64_t *res = nullptr;
+    FCLSH_HIP(hipMalloc(&offs, size_t(nq + 1) * 8));
+    FCLSH_HIP(hipMalloc(&res, 16));
+    int64_t total = 0;
+    fclsh_status s = query_batch(ix, ws, d_queries, nq, r_query, nullptr, st, offs, nullptr, 0, &total);
+    if (s != FCLSH_OK && s != FCLSH_ECAPACITY) {
+        (void)hipFree(offs);
+        (void)hipFree(res);
+        return s;
+    }
+    if (hipMalloc(&ids, size_t(std::max<int64_t>(total, 1)) * 4) != hipSuccess) {
+        (void)hipFree(offs);
+        (void)hipFree(res);
+        return fail(FCLSH_ENOMEM, "autotune buffers");
+    }
+    const QueryTuning saved = ix.tuning;
+    const int tiles[] = {64, 128, 256, 512, 1024, 4096};
+    const int bpcs[] = {2, 4, 8, 16};
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 1e30f;
+    QueryTuning best_t = saved;
+    for (int tl : tiles)
+        for (int bp : bpcs) {
+            ix.tuning = QueryTuning{tl, bp};
+            fclsh_status r1 = query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
+            if (r1 != FCLSH_OK) continue;
+            (void)hipEventRecord(e0, st);
+            for (int rep = 0; rep < 3; ++rep)
+                (void)query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= 3;
+            if (ms < best) {
+                best = ms;
+                best_t = ix.tuning;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(offs);
+    (void)hipFree(ids);
+    (void)hipFree(res);
+    ix.tuning = best_t;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[tune_key(ix)] = best_t;
+    }
+    if (tile_out) *tile_out = best_t.tile;
+    if (blocks_out) *blocks_out = best_t.blocks_per_cu;
+    if (best_ms_out) *best_ms_out = best;
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
 }
 
 }  // extern "C"

@@ -76,8 +76,16 @@ struct HashPlan {
     uint2 *gtab = nullptr;       // [t][E][G] (even representative of b mod P, coordinate)
 };
 
+// Launch shape of the batched verify kernels, chosen by the autotuner.
+struct QueryTuning {
+    int tile = 256;          // bucket entries per work item / spill chunk
+    int blocks_per_cu = 8;   // persistent workgroups per CU
+};
+
 struct Index {
     Params prm;
+    QueryTuning tuning;
+    int num_cus = 256;
     int W = 1;
     int64_t n = 0;
     int dir_bits = 1;
@@ -140,23 +148,48 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
                                 uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
                                 uint32_t *dir, hipStream_t st);
 
+// Device-side control block of one query batch.
+struct QueryCtrl {
+    unsigned long long item_head;   // next (query, table) item to verify
+    unsigned long long spills;      // spill chunks recorded
+    unsigned long long spill_head;  // next spill chunk to verify
+    unsigned long long pairs;       // reported (query, id) pairs
+    unsigned long long total;       // pairs, as published with the offsets
+    uint32_t status;                // kQuery*Overflow bits
+    uint32_t pad;
+};
+constexpr uint32_t kQueryPairOverflow = 1u;
+constexpr uint32_t kQuerySpillOverflow = 2u;
+constexpr uint32_t kQueryIdsOverflow = 4u;
+
 // Scratch of the query path for one index and stream, grown on demand.
 struct QueryWorkspace {
-    uint32_t *qkeys = nullptr, *rstart = nullptr, *rcount = nullptr, *rmatch = nullptr, *qcount = nullptr;
-    uint64_t *qcount64 = nullptr, *offs1 = nullptr;
-    unsigned long long *cursor = nullptr;
-    uint32_t *pq = nullptr, *pid = nullptr, *sk = nullptr, *sv = nullptr, *tk = nullptr, *tv = nullptr;
-    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0;
+    uint32_t *qkeys = nullptr, *rstart = nullptr, *rlen = nullptr, *rmatch = nullptr;
+    uint32_t *qcount = nullptr, *qfill = nullptr;
+    uint64_t *qcount64 = nullptr, *scan_part = nullptr, *offs1 = nullptr;
+    QueryCtrl *ctrl = nullptr;
+    uint32_t *pq = nullptr, *pid = nullptr, *sorttmp = nullptr;
+    uint4 *spill = nullptr;
+    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0, cap_spill = 0;
 };
 
-fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs);
+fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills);
 void ws_release(QueryWorkspace &ws);
+fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
+                               const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids,
+                               int64_t ids_cap);
 fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
-                         hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
+                         const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap,
+                         int64_t *total_out);
 fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                          hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
 fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq,
                               uint64_t *coll, hipStream_t st);
+// Exclusive scan of n uint64 (in place allowed) using caller-provided
+// partials (scan_partials_needed(n) entries): no allocation, graph-safe.
+int64_t scan_partials_needed(int64_t n);
+fclsh_status exclusive_scan_u64_ws(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *partials,
+                                   hipStream_t st);
 const char *last_error_cstr();
 
 }  // namespace fclsh

@@ -1,8 +1,8 @@
 // Queries: Strategy 2 of Sec. 2.2 as the three steps of Sec. 4.1.
 //
 //   S1  the query's L keys, by the same Alg. 2 kernel as the build
-//   S2  per table, the query's bucket (directory bin + binary search in the
-//       sorted keys); #Collisions is the sum of the bucket sizes
+//   S2  per table, the query's directory bin; the entries of the bin whose
+//       key equals the query's form its bucket (#Collisions = their count)
 //   S3  every colliding point is checked by popcount(x XOR q) <= r_query
 //
 // Duplicate elimination without per-query state.  The paper removes
@@ -18,6 +18,16 @@
 // is found by keeping a basis with distinct leading bits while the
 // constraints are added, then taking the basis vector with the lowest
 // leading bit.
+//
+// The batched pipeline runs on the device without a host round trip, so a
+// whole batch can be captured in a HIP graph:
+//   hash -> lookup -> verify (one wave per (query, table) bucket, at most
+//   `tile` entries each; the rest of a large bucket is cut into `tile`-sized
+//   chunks on a spill queue) -> spill (persistent waves pull chunks from the
+//   queue) -> CSR offsets -> scatter into per-query segments -> per-query
+//   sort (ids ascending).  Skewed buckets (1 to 1e5 candidates) thus spread
+//   over all CUs.  Counters are cleared by fill kernels, never by memset
+//   nodes, so graph replays start clean.
 #include <algorithm>
 
 #include "common.h"
@@ -29,8 +39,8 @@ namespace {
 // First table (in (part, v) order) where x and q share the masked value, or
 // -1 if there is none (then d(x, q) exceeds what the family covers).
 __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t *__restrict__ q, int W,
-                                  int d, const int32_t *__restrict__ part, const int32_t *__restrict__ col,
-                                  int t, int mbits, int Lp, uint64_t last_mask) {
+                                  const int32_t *__restrict__ part, const int32_t *__restrict__ col, int t,
+                                  int mbits, int Lp, uint64_t last_mask) {
     for (int p = 0; p < t; ++p) {
         uint32_t B[kMaxLogD];
 #pragma unroll
@@ -70,6 +80,74 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
     return -1;
 }
 
+struct VerifyArgs {
+    const uint64_t *pts;
+    int W, t, mbits, Lp, L;
+    uint64_t last_mask;
+    const int32_t *part, *col;
+    const uint64_t *queries;
+    int64_t nq;
+    const int32_t *rq_vec;  // per-query radius, or null: rq for all
+    int rq;
+    const uint32_t *tkeys, *tids;
+    int64_t n;
+    const uint32_t *qkeys;                   // [L][nq]
+    const uint32_t *rstart, *rlen, *rmatch;  // [nq][L]
+    QueryCtrl *ctrl;
+    uint4 *spill;  // (item, begin, end, 0)
+    int64_t spill_cap;
+    uint32_t *out_q, *out_id;
+    int64_t pair_cap;
+    uint32_t *qcount;
+    uint32_t tile;
+};
+
+// Verifies entries [j0, j1) of (query qi, table T)'s bin; reports near points
+// whose first shared table is T.  Whole wave, uniform arguments.
+__device__ inline void verify_range(const VerifyArgs &a, int64_t qi, int T, uint32_t j0, uint32_t j1) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
+    const uint32_t st = a.rstart[qi * a.L + T];
+    const uint64_t *qp = a.queries + qi * a.W;
+    const uint32_t *ids = a.tids + int64_t(T) * a.n + st;
+    const uint32_t *bk = a.tkeys + int64_t(T) * a.n + st;
+    const int rq = a.rq_vec ? a.rq_vec[qi] : a.rq;
+    for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
+        const uint32_t j = b0 + lane;
+        bool emit = false;
+        uint32_t id = 0;
+        if (j < j1 && bk[j] == qkey) {
+            id = ids[j];
+            const uint64_t *xp = a.pts + int64_t(id) * a.W;
+            int dist = 0;
+            for (int w = 0; w < a.W; ++w) {
+                uint64_t df = xp[w] ^ qp[w];
+                if (w == a.W - 1) df &= a.last_mask;
+                dist += __popcll(df);
+            }
+            if (dist <= rq)
+                emit = first_shared_table(xp, qp, a.W, a.part, a.col, a.t, a.mbits, a.Lp, a.last_mask) == T;
+        }
+        const uint64_t bal = __ballot(emit);
+        if (bal) {
+            unsigned long long base = 0;
+            if (lane == 0) {
+                base = atomicAdd(&a.ctrl->pairs, (unsigned long long)__popcll(bal));
+                atomicAdd(&a.qcount[qi], uint32_t(__popcll(bal)));
+            }
+            base = __shfl(base, 0, 64);
+            if (emit) {
+                const unsigned long long slot = base + __popcll(bal & lt);
+                if (slot < (unsigned long long)a.pair_cap) {
+                    a.out_q[slot] = uint32_t(qi);
+                    a.out_id[slot] = id;
+                }
+            }
+        }
+    }
+}
+
 // S2: per (query, table) the query's directory bin [start, start+len) in
 // table T and the number of entries in it whose key equals the query's key
 // (the bucket size, i.e. this table's share of #Collisions).
@@ -105,64 +183,69 @@ __global__ void collisions_kernel(const uint32_t *__restrict__ rmatch, int64_t n
     coll[qi] = s;
 }
 
-// S3 + emission.  One wave per (query, table) item; lanes stride over the
-// query's directory bin and keep the entries of its bucket (equal key).  Each reported (query, id) pair takes a slot from a global cursor
-// (one atomic per wave); slots past `cap` are dropped and recounted by the
-// host with a larger buffer.
-__global__ __launch_bounds__(256) void verify_kernel(
-    const uint64_t *__restrict__ pts, int W, int d, const uint64_t *__restrict__ queries, int64_t nq,
-    int L, const uint32_t *__restrict__ tkeys, const uint32_t *__restrict__ tids, int64_t n,
-    const uint32_t *__restrict__ qkeys, const uint32_t *__restrict__ rstart, const uint32_t *__restrict__ rmatch,
-    const uint32_t *__restrict__ rlen, int rq, const int32_t *__restrict__ part,
-    const int32_t *__restrict__ col, int t, int mbits, int Lp, uint64_t last_mask,
-    unsigned long long *__restrict__ cursor, uint32_t *__restrict__ out_q, uint32_t *__restrict__ out_id,
-    int64_t cap, uint32_t *__restrict__ qcount) {
+// Clears the per-batch counters (a kernel, not a memset: graph-safe).
+__global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill, int64_t nq) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) *ctrl = QueryCtrl{};
+    for (int64_t k = i; k < nq; k += int64_t(gridDim.x) * blockDim.x) {
+        qcount[k] = 0;
+        qfill[k] = 0;
+    }
+}
+
+// S3, pass 1: waves claim 64 (query, table) items per atomic; the lanes
+// check the 64 bucket sizes at once and the wave then verifies each
+// non-empty bucket in turn, its first `tile` entries directly and the rest as
+// tile-sized chunks on the spill queue.  Every wave leaves once the counter
+// passes the number of items.
+__global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave0 = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x >> 6);
-    const int64_t items = nq * L;
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int64_t it = __builtin_amdgcn_readfirstlane(wave0); it < items; it += nwaves) {
-        if (rmatch[it] == 0) continue;
-        const uint32_t cnt = rlen[it];
-        const int64_t qi = it / L;
-        const int T = int(it - qi * L);
-        const uint32_t st = rstart[it];
-        const uint32_t qkey = qkeys[int64_t(T) * nq + qi];
-        const uint64_t *qp = queries + qi * W;
-        const uint32_t *ids = tids + int64_t(T) * n + st;
-        const uint32_t *bk = tkeys + int64_t(T) * n + st;
-        for (uint32_t j0 = 0; j0 < cnt; j0 += 64) {
-            const uint32_t j = j0 + lane;
-            bool emit = false;
-            uint32_t id = 0;
-            if (j < cnt && bk[j] == qkey) {
-                id = ids[j];
-                const uint64_t *xp = pts + int64_t(id) * W;
-                int dist = 0;
-                for (int w = 0; w < W; ++w) {
-                    uint64_t df = xp[w] ^ qp[w];
-                    if (w == W - 1) df &= last_mask;
-                    dist += __popcll(df);
-                }
-                if (dist <= rq)
-                    emit = first_shared_table(xp, qp, W, d, part, col, t, mbits, Lp, last_mask) == T;
-            }
-            const uint64_t bal = __ballot(emit);
-            if (bal) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(cursor, (unsigned long long)__popcll(bal));
-                base = __shfl(base, 0, 64);
-                if (lane == 0) atomicAdd(&qcount[qi], uint32_t(__popcll(bal)));
-                if (emit) {
-                    const unsigned long long slot = base + __popcll(bal & lt);
-                    if (slot < (unsigned long long)cap) {
-                        out_q[slot] = uint32_t(qi);
-                        out_id[slot] = id;
+    const unsigned long long items = (unsigned long long)(a.nq * a.L);
+    for (;;) {
+        unsigned long long it0 = 0;
+        if (lane == 0) it0 = atomicAdd(&a.ctrl->item_head, 64ull);
+        it0 = __shfl(it0, 0, 64);
+        if (it0 >= items) break;
+        const unsigned long long mine = it0 + lane;
+        const bool hit = mine < items && a.rmatch[mine] != 0;
+        uint64_t todo = __ballot(hit);
+        while (todo) {
+            const int k = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const unsigned long long it = it0 + k;
+            const int64_t qi = int64_t(it) / a.L;
+            const int T = int(int64_t(it) - qi * a.L);
+            const uint32_t len = a.rlen[it];
+            const uint32_t first = len < a.tile ? len : a.tile;
+            if (len > a.tile && lane == 0) {
+                const uint32_t nch = (len - first + a.tile - 1) / a.tile;
+                const unsigned long long at = atomicAdd(&a.ctrl->spills, (unsigned long long)nch);
+                for (uint32_t c = 0; c < nch; ++c) {
+                    if (at + c < (unsigned long long)a.spill_cap) {
+                        const uint32_t b = first + c * a.tile;
+                        a.spill[at + c] = make_uint4(uint32_t(it), b, min(len, b + a.tile), 0u);
                     }
                 }
             }
+            verify_range(a, qi, T, 0, first);
         }
+    }
+}
+
+// S3, pass 2: persistent waves drain the spill queue (every wave leaves once
+// the counter passes the number of recorded chunks).
+__global__ __launch_bounds__(256) void verify_spill_kernel(VerifyArgs a) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long nsp = min((unsigned long long)a.spill_cap, a.ctrl->spills);
+    for (;;) {
+        unsigned long long k = 0;
+        if (lane == 0) k = atomicAdd(&a.ctrl->spill_head, 1ull);
+        k = __shfl(k, 0, 64);
+        if (k >= nsp) break;
+        const uint4 r = a.spill[k];
+        const int64_t qi = int64_t(r.x) / a.L;
+        const int T = int(int64_t(r.x) - qi * a.L);
+        verify_range(a, qi, T, r.y, r.z);
     }
 }
 
@@ -171,8 +254,125 @@ __global__ void widen_counts_kernel(const uint32_t *__restrict__ c32, int64_t nq
     if (i < nq) c64[i] = c32[i];
 }
 
-__global__ void set_last_offset_kernel(uint64_t *offsets, int64_t nq, const unsigned long long *cursor) {
-    offsets[nq] = *cursor;
+// offsets[nq] = number of reported pairs; flags overflow of the internal
+// pair buffer, the spill queue or the caller's id buffer.
+__global__ void finish_offsets_kernel(uint64_t *offsets, int64_t nq, QueryCtrl *ctrl, int64_t pair_cap,
+                                      int64_t spill_cap, int64_t ids_cap) {
+    const unsigned long long tot = ctrl->pairs;
+    offsets[nq] = tot;
+    ctrl->total = tot;
+    uint32_t st = 0;
+    if (tot > (unsigned long long)pair_cap) st |= kQueryPairOverflow;
+    if (ctrl->spills > (unsigned long long)spill_cap) st |= kQuerySpillOverflow;
+    if (tot > (unsigned long long)ids_cap) st |= kQueryIdsOverflow;
+    ctrl->status = st;
+}
+
+constexpr uint32_t kAnyOverflow = kQueryPairOverflow | kQuerySpillOverflow | kQueryIdsOverflow;
+
+// Pairs into per-query segments (order inside a segment fixed by the sort).
+__global__ void scatter_pairs_kernel(const uint32_t *__restrict__ pq, const uint32_t *__restrict__ pid,
+                                     const QueryCtrl *__restrict__ ctrl, int64_t pair_cap,
+                                     const uint64_t *__restrict__ offsets, uint32_t *__restrict__ qfill,
+                                     uint32_t *__restrict__ ids, int64_t ids_cap) {
+    if (ctrl->status & kAnyOverflow) return;
+    const int64_t tot = int64_t(min((unsigned long long)pair_cap, ctrl->pairs));
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t q = pq[i];
+        const uint64_t slot = offsets[q] + atomicAdd(&qfill[q], 1u);
+        if (slot < uint64_t(ids_cap)) ids[slot] = pid[i];
+    }
+}
+
+// Sorts each query's segment of ids ascending: a bitonic sort in LDS for
+// segments up to kSortCap ids; longer segments run a stable LSD radix sort
+// over global memory inside the workgroup, with tmp as the second buffer.
+constexpr int kSortNT = 256;
+constexpr int kSortCap = 4096;
+
+__global__ __launch_bounds__(kSortNT) void segment_sort_kernel(const uint64_t *__restrict__ offsets,
+                                                               const QueryCtrl *__restrict__ ctrl,
+                                                               uint32_t *__restrict__ ids,
+                                                               uint32_t *__restrict__ tmp, int idbits) {
+    __shared__ uint32_t s[kSortCap];
+    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t sh[kSortNT / 64 + 1];
+    if (ctrl->status & kAnyOverflow) return;
+    const int64_t q = blockIdx.x;
+    const uint64_t b = offsets[q], e = offsets[q + 1];
+    const uint32_t m = uint32_t(e - b);
+    if (m <= 1) return;
+    uint32_t *seg = ids + b;
+    if (m <= uint32_t(kSortCap)) {
+        uint32_t P = 1;
+        while (P < m) P <<= 1;
+        for (uint32_t i = threadIdx.x; i < P; i += kSortNT) s[i] = i < m ? seg[i] : 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = threadIdx.x; i < P; i += kSortNT) {
+                    const uint32_t l = i ^ j;
+                    if (l > i) {
+                        const uint32_t x = s[i], y = s[l];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            s[i] = y;
+                            s[l] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) seg[i] = s[i];
+        return;
+    }
+    // long segment: 8-bit LSD passes, each a histogram, a scan of the 256
+    // digit counts and a stable scatter, chunk by chunk, in which thread d
+    // moves the chunk's entries with digit d in their order
+    uint32_t *src = seg, *dst = tmp + b;
+    const int npass = (idbits + 7) / 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int ps = 0; ps < npass; ++ps) {
+        const int sft = 8 * ps;
+        cnt[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) atomicAdd(&cnt[(src[i] >> sft) & 255u], 1u);
+        __syncthreads();
+        const uint32_t c = cnt[threadIdx.x];
+        uint32_t x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) sh[wave] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int w = 0; w < kSortNT / 64; ++w) {
+                const uint32_t cc = sh[w];
+                sh[w] = run;
+                run += cc;
+            }
+        }
+        __syncthreads();
+        uint32_t pos = x - c + sh[wave];  // running start of digit threadIdx.x
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < m; c0 += kSortCap) {
+            const uint32_t c1 = min(m, c0 + uint32_t(kSortCap));
+            for (uint32_t i = c0 + threadIdx.x; i < c1; i += kSortNT) s[i - c0] = src[i];
+            __syncthreads();
+            for (uint32_t i = 0; i < c1 - c0; ++i)
+                if (((s[i] >> sft) & 255u) == threadIdx.x) dst[pos++] = s[i];
+            __syncthreads();
+        }
+        uint32_t *tsw = src;
+        src = dst;
+        dst = tsw;
+    }
+    if (src != seg)
+        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) seg[i] = src[i];
 }
 
 unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
@@ -182,138 +382,177 @@ unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
     return unsigned(g);
 }
 
-}  // namespace
-
-
-
-namespace {
-
 template <class T>
-fclsh_status regrow(T **p, int64_t have, int64_t want, const char *what) {
-    if (want <= have && *p) return FCLSH_OK;
+fclsh_status regrow(T **p, int64_t want, const char *what) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
-    if (hipMalloc(reinterpret_cast<void **>(p), size_t(std::max<int64_t>(want, 1)) * sizeof(T)) != hipSuccess)
+    if (hipMalloc(reinterpret_cast<void **>(p), size_t(std::max<int64_t>(want, 1)) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
         return fail(FCLSH_ENOMEM, "device allocation for %s failed", what);
+    }
     return FCLSH_OK;
 }
 
+uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 1) : ~uint64_t(0); }
+
 }  // namespace
 
-fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs) {
+fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills) {
     const int64_t items = nq * L;
-    if (items > ws.cap_items) {
-        FCLSH_TRY(regrow(&ws.qkeys, 0, items, "query keys"));
-        FCLSH_TRY(regrow(&ws.rstart, 0, items, "query ranges"));
-        FCLSH_TRY(regrow(&ws.rcount, 0, items, "query ranges"));
-        FCLSH_TRY(regrow(&ws.rmatch, 0, items, "query ranges"));
+    if (items > ws.cap_items || !ws.qkeys) {
+        FCLSH_TRY(regrow(&ws.qkeys, items, "query keys"));
+        FCLSH_TRY(regrow(&ws.rstart, items, "query ranges"));
+        FCLSH_TRY(regrow(&ws.rlen, items, "query ranges"));
+        FCLSH_TRY(regrow(&ws.rmatch, items, "query ranges"));
         ws.cap_items = items;
     }
-    if (nq + 1 > ws.cap_q) {
-        FCLSH_TRY(regrow(&ws.qcount, 0, nq + 1, "query counts"));
-        FCLSH_TRY(regrow(&ws.qcount64, 0, nq + 1, "query counts"));
+    if (nq + 1 > ws.cap_q || !ws.qcount) {
+        FCLSH_TRY(regrow(&ws.qcount, nq + 1, "query counts"));
+        FCLSH_TRY(regrow(&ws.qfill, nq + 1, "query counts"));
+        FCLSH_TRY(regrow(&ws.qcount64, nq + 1, "query counts"));
+        FCLSH_TRY(regrow(&ws.scan_part, scan_partials_needed(nq + 1), "scan partials"));
         ws.cap_q = nq + 1;
     }
-    if (!ws.cursor) FCLSH_TRY(regrow(&ws.cursor, 0, 1, "cursor"));
-    if (!ws.offs1) FCLSH_TRY(regrow(&ws.offs1, 0, 2, "plain offsets"));
-    if (pairs > ws.cap_pairs) {
-        FCLSH_TRY(regrow(&ws.pq, 0, pairs, "result pairs"));
-        FCLSH_TRY(regrow(&ws.pid, 0, pairs, "result pairs"));
-        FCLSH_TRY(regrow(&ws.sk, 0, pairs, "result sort"));
-        FCLSH_TRY(regrow(&ws.sv, 0, pairs, "result sort"));
-        FCLSH_TRY(regrow(&ws.tk, 0, pairs, "result sort"));
-        FCLSH_TRY(regrow(&ws.tv, 0, pairs, "result sort"));
+    if (!ws.ctrl) FCLSH_TRY(regrow(&ws.ctrl, 1, "query control"));
+    if (!ws.offs1) FCLSH_TRY(regrow(&ws.offs1, 2, "plain offsets"));
+    if (pairs > ws.cap_pairs || !ws.pq) {
+        FCLSH_TRY(regrow(&ws.pq, pairs, "result pairs"));
+        FCLSH_TRY(regrow(&ws.pid, pairs, "result pairs"));
+        FCLSH_TRY(regrow(&ws.sorttmp, pairs, "result sort"));
         ws.cap_pairs = pairs;
+    }
+    if (spills > ws.cap_spill || !ws.spill) {
+        FCLSH_TRY(regrow(&ws.spill, spills, "spill queue"));
+        ws.cap_spill = spills;
     }
     return FCLSH_OK;
 }
 
 void ws_release(QueryWorkspace &ws) {
-    void *ps[] = {ws.qkeys, ws.rstart, ws.rcount, ws.rmatch, ws.qcount, ws.qcount64, ws.offs1, ws.cursor,
-                  ws.pq, ws.pid, ws.sk, ws.sv, ws.tk, ws.tv};
+    void *ps[] = {ws.qkeys, ws.rstart, ws.rlen, ws.rmatch, ws.qcount, ws.qfill, ws.qcount64, ws.scan_part,
+                  ws.offs1, ws.ctrl, ws.pq, ws.pid, ws.sorttmp, ws.spill};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     ws = QueryWorkspace{};
-}
-
-static uint64_t last_word_mask(int d) {
-    return (d % 64) ? ((uint64_t(1) << (d % 64)) - 1) : ~uint64_t(0);
 }
 
 // S1 + S2 for a batch; leaves keys and ranges in the workspace.
 fclsh_status query_lookup(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, hipStream_t st) {
     const int L = ix.prm.L();
     FCLSH_TRY(launch_hash(ix, queries, nq, ws.qkeys, nq, st));
-    hipLaunchKernelGGL(lookup_kernel, dim3(grid_for(nq * L, 256)), dim3(256), 0, st, ws.qkeys, nq, L,
-                       ix.tkeys, ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rcount, ws.rmatch);
+    hipLaunchKernelGGL(lookup_kernel, dim3(grid_for(nq * L, 256)), dim3(256), 0, st, ws.qkeys, nq, L, ix.tkeys,
+                       ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rlen, ws.rmatch);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
 
 fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq,
                               uint64_t *coll, hipStream_t st) {
-    FCLSH_TRY(ws_reserve(ws, nq, ix.prm.L(), 0));
+    FCLSH_TRY(ws_reserve(ws, nq, ix.prm.L(), std::max<int64_t>(ws.cap_pairs, 1), std::max<int64_t>(ws.cap_spill, 1)));
     FCLSH_TRY(query_lookup(ix, ws, queries, nq, st));
-    hipLaunchKernelGGL(collisions_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.rmatch, nq,
-                       ix.prm.L(), coll);
+    hipLaunchKernelGGL(collisions_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.rmatch, nq, ix.prm.L(),
+                       coll);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
 
-// Full batched query into CSR (see fclsh_query_batch).
+// The batched pipeline, entirely on the stream: no allocation, no host
+// synchronisation (the workspace must already hold nq queries, ws.cap_pairs
+// pairs and ws.cap_spill spill chunks).  Outputs: offsets[nq+1], ids (up to
+// ids_cap), and ws.ctrl->{total, status}.
+fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
+                               const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids,
+                               int64_t ids_cap) {
+    const int L = ix.prm.L();
+    const QueryTuning &tu = ix.tuning;
+    if (nq * L > ws.cap_items || nq + 1 > ws.cap_q || !ws.ctrl || !ws.pq || !ws.spill)
+        return fail(FCLSH_EINVAL, "query workspace not reserved for %lld queries", (long long)nq);
+    hipLaunchKernelGGL(reset_kernel, dim3(grid_for(nq, 256, 1024)), dim3(256), 0, st, ws.ctrl, ws.qcount, ws.qfill,
+                       nq);
+    FCLSH_HIP(hipGetLastError());
+    if (nq > 0) FCLSH_TRY(query_lookup(ix, ws, queries, nq, st));
+    VerifyArgs a{};
+    a.pts = ix.pts;
+    a.W = ix.W;
+    a.t = ix.prm.t;
+    a.mbits = ix.prm.rp + 1;
+    a.Lp = ix.prm.Lp();
+    a.L = L;
+    a.last_mask = last_word_mask(ix.prm.d);
+    a.part = ix.dpart;
+    a.col = ix.dcol;
+    a.queries = queries;
+    a.nq = nq;
+    a.rq_vec = rq_vec;
+    a.rq = rq;
+    a.tkeys = ix.tkeys;
+    a.tids = ix.tids;
+    a.n = ix.n;
+    a.qkeys = ws.qkeys;
+    a.rstart = ws.rstart;
+    a.rlen = ws.rlen;
+    a.rmatch = ws.rmatch;
+    a.ctrl = ws.ctrl;
+    a.spill = ws.spill;
+    a.spill_cap = ws.cap_spill;
+    a.out_q = ws.pq;
+    a.out_id = ws.pid;
+    a.pair_cap = ws.cap_pairs;
+    a.qcount = ws.qcount;
+    a.tile = uint32_t(tu.tile);
+    const unsigned vblocks = unsigned(std::max(1, tu.blocks_per_cu * ix.num_cus));
+    if (nq > 0) {
+        hipLaunchKernelGGL(verify_items_kernel, dim3(vblocks), dim3(256), 0, st, a);
+        FCLSH_HIP(hipGetLastError());
+        hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(256), 0, st, a);
+        FCLSH_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(widen_counts_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.qcount, nq, ws.qcount64);
+    FCLSH_HIP(hipGetLastError());
+    FCLSH_TRY(exclusive_scan_u64_ws(ws.qcount64, offsets, nq, ws.scan_part, st));
+    hipLaunchKernelGGL(finish_offsets_kernel, dim3(1), dim3(1), 0, st, offsets, nq, ws.ctrl, ws.cap_pairs,
+                       ws.cap_spill, ids_cap);
+    FCLSH_HIP(hipGetLastError());
+    if (nq > 0 && ids_cap > 0) {
+        hipLaunchKernelGGL(scatter_pairs_kernel, dim3(grid_for(ws.cap_pairs, 256, 4096)), dim3(256), 0, st, ws.pq,
+                           ws.pid, ws.ctrl, ws.cap_pairs, offsets, ws.qfill, ids, ids_cap);
+        FCLSH_HIP(hipGetLastError());
+        const int idbits = std::max(1, ilog2_ceil(uint64_t(ix.n)));
+        for (int64_t q0 = 0; q0 < nq; q0 += 65535) {
+            const int64_t qn = std::min<int64_t>(65535, nq - q0);
+            hipLaunchKernelGGL(segment_sort_kernel, dim3(unsigned(qn)), dim3(kSortNT), 0, st, offsets + q0, ws.ctrl,
+                               ids, ws.sorttmp, idbits);
+            FCLSH_HIP(hipGetLastError());
+        }
+    }
+    return FCLSH_OK;
+}
+
+// Synchronous form (fclsh_query_batch): sizes the workspace, runs the device
+// pipeline, reads the result size back once and grows and reruns if an
+// internal buffer overflowed.
 fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
-                         hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap,
+                         const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap,
                          int64_t *total_out) {
     const int L = ix.prm.L();
-    if (nq == 0) {
-        FCLSH_HIP(hipMemsetAsync(offsets, 0, 8, st));
+    int64_t pairs = std::max<int64_t>(ws.cap_pairs, std::max<int64_t>(1 << 16, nq * 16));
+    int64_t spills = std::max<int64_t>(ws.cap_spill, 1 << 16);
+    QueryCtrl h{};
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        FCLSH_TRY(ws_reserve(ws, nq, L, pairs, spills));
+        FCLSH_TRY(query_batch_async(ix, ws, queries, nq, rq, rq_vec, st, offsets, ids, ids_cap));
+        FCLSH_HIP(hipMemcpyAsync(&h, ws.ctrl, sizeof h, hipMemcpyDeviceToHost, st));
         FCLSH_HIP(hipStreamSynchronize(st));
-        *total_out = 0;
-        return FCLSH_OK;
+        if (!(h.status & (kQueryPairOverflow | kQuerySpillOverflow))) break;
+        if (h.status & kQueryPairOverflow) pairs = int64_t(h.pairs) + int64_t(h.pairs >> 3) + 1;
+        if (h.status & kQuerySpillOverflow) spills = int64_t(h.spills) + int64_t(h.spills >> 3) + 1;
     }
-    int64_t pairs_cap = std::max<int64_t>(ws.cap_pairs, std::max<int64_t>(1 << 16, nq * 8));
-    FCLSH_TRY(ws_reserve(ws, nq, L, pairs_cap));
-    FCLSH_TRY(query_lookup(ix, ws, queries, nq, st));
-    const uint64_t lm = last_word_mask(ix.prm.d);
-    unsigned long long total = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        FCLSH_HIP(hipMemsetAsync(ws.cursor, 0, 8, st));
-        FCLSH_HIP(hipMemsetAsync(ws.qcount, 0, size_t(nq) * 4, st));
-        const int64_t items = nq * L;
-        hipLaunchKernelGGL(verify_kernel, dim3(grid_for(items, 4, 65536)), dim3(256), 0, st, ix.pts, ix.W,
-                           ix.prm.d, queries, nq, L, ix.tkeys, ix.tids, ix.n, ws.qkeys, ws.rstart, ws.rmatch,
-                           ws.rcount, rq, ix.dpart, ix.dcol,
-                           ix.prm.t, ix.prm.rp + 1, ix.prm.Lp(), lm, ws.cursor, ws.pq, ws.pid, ws.cap_pairs,
-                           ws.qcount);
-        FCLSH_HIP(hipGetLastError());
-        FCLSH_HIP(hipMemcpyAsync(&total, ws.cursor, 8, hipMemcpyDeviceToHost, st));
-        FCLSH_HIP(hipStreamSynchronize(st));
-        if (int64_t(total) <= ws.cap_pairs) break;
-        FCLSH_TRY(ws_reserve(ws, nq, L, int64_t(total) + (int64_t(total) >> 3)));
-    }
-    // CSR offsets from the per-query counts
-    hipLaunchKernelGGL(widen_counts_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.qcount, nq,
-                       ws.qcount64);
-    FCLSH_HIP(hipGetLastError());
-    Scratch scr;
-    FCLSH_TRY(exclusive_scan_u64(ws.qcount64, offsets, nq, nullptr, scr, st));
-    hipLaunchKernelGGL(set_last_offset_kernel, dim3(1), dim3(1), 0, st, offsets, nq, ws.cursor);
-    FCLSH_HIP(hipGetLastError());
-    *total_out = int64_t(total);
-    if (int64_t(total) > ids_cap) {
-        FCLSH_HIP(hipStreamSynchronize(st));
-        return fail(FCLSH_ECAPACITY, "%lld ids do not fit the output capacity %lld", (long long)total,
+    if (h.status & (kQueryPairOverflow | kQuerySpillOverflow))
+        return fail(FCLSH_ENOMEM, "query buffers kept overflowing");
+    *total_out = int64_t(h.total);
+    if (h.status & kQueryIdsOverflow)
+        return fail(FCLSH_ECAPACITY, "%lld ids do not fit the output capacity %lld", (long long)h.total,
                     (long long)ids_cap);
-    }
-    if (total > 0) {
-        // canonical order: by query, ids ascending (two stable LSD sorts)
-        const int idbits = std::max(1, ilog2_ceil(uint64_t(ix.n)));
-        const int qbits = std::max(1, ilog2_ceil(uint64_t(nq)));
-        FCLSH_TRY(radix_sort_pairs(ws.pid, ws.pq, ws.sk, ws.sv, ws.tk, ws.tv, 1, int64_t(total), 0, idbits, scr,
-                                   st));
-        FCLSH_TRY(radix_sort_pairs(ws.sv, ws.sk, ws.pq, ids, ws.tk, ws.tv, 1, int64_t(total), 0, qbits, scr, st));
-    }
-    FCLSH_HIP(hipStreamSynchronize(st));
     return FCLSH_OK;
 }
 
@@ -327,7 +566,7 @@ fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
     for (int64_t i = 0; i < nq; ++i) {
         int64_t got = 0;
         const int64_t room = over ? 0 : ids_cap - run;
-        fclsh_status s = query_batch(ix, ws, queries + i * ix.W, 1, rq, st, ws.offs1,
+        fclsh_status s = query_batch(ix, ws, queries + i * ix.W, 1, rq, nullptr, st, ws.offs1,
                                      room > 0 ? ids + run : nullptr, room > 0 ? room : 0, &got);
         if (s == FCLSH_ECAPACITY) {
             over = true;

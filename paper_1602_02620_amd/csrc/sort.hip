@@ -272,6 +272,31 @@ fclsh_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, 
     return FCLSH_OK;
 }
 
+int64_t scan_partials_needed(int64_t n) {
+    int64_t need = 0;
+    for (int64_t m = (n + kScanTile - 1) / kScanTile; m > 1; m = (m + kScanTile - 1) / kScanTile) need += m;
+    return need + 1;
+}
+
+fclsh_status exclusive_scan_u64_ws(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *partials,
+                                   hipStream_t st) {
+    if (n <= 0) return FCLSH_OK;
+    const int64_t nblk = (n + kScanTile - 1) / kScanTile;
+    if (nblk == 1) {
+        hipLaunchKernelGGL(scan_apply_kernel, dim3(1), dim3(kScanNT), 0, st, in, out, n, (const uint64_t *)nullptr);
+        FCLSH_HIP(hipGetLastError());
+        return FCLSH_OK;
+    }
+    uint64_t *part = partials;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(unsigned(nblk)), dim3(kScanNT), 0, st, in, n, part);
+    FCLSH_HIP(hipGetLastError());
+    FCLSH_TRY(exclusive_scan_u64_ws(part, part, nblk, partials + nblk, st));
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(unsigned(nblk)), dim3(kScanNT), 0, st, in, out, n,
+                       (const uint64_t *)part);
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
+}
+
 fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *total,
                                 Scratch &scr, hipStream_t st) {
     if (n <= 0) {

@@ -1,0 +1,174 @@
+"""GPU tests of the batched query machinery: per-query radii, the spill queue
+for large buckets, the synchronisation-free path and its HIP-graph replays,
+the autotuner, overflow reporting, and equality of every answer alone and in
+a mixed batch.  Expected answers come from the CPU oracle's linear scan."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._helpers import assert_same_lists, csr_lists
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1602_02620_amd as fc  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return fc.to_device_words(a)
+
+
+def brute_mixed(points, d, queries, radii):
+    out = []
+    for i in range(queries.shape[0]):
+        out.append(oracle.brute_force(points, d, queries[i:i + 1], int(radii[i])).ids[0])
+    return out
+
+
+@pytest.fixture(scope="module")
+def served():
+    # shape of the served index A (r = 10, two parts), scaled down; per-query
+    # radii with neighbours planted inside each query's own radius
+    rng = np.random.default_rng(4)
+    nq = 48
+    radii = rng.integers(0, 11, size=nq).astype(np.int32)
+    w = synth.uniform_with_planted(6000, 256, 10, nq, 5, 1205, "served_small", query_radius=radii)
+    _say(f"[build] served_small n={w.n}")
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=3105)
+    yield w, idx
+    idx.close()
+
+
+def test_mixed_radii(served):
+    w, idx = served
+    want = brute_mixed(w.points, w.d, w.queries, w.query_radius)
+    got = csr_lists(*idx.query_radii(dev(w.queries), torch.from_numpy(w.query_radius)))
+    assert_same_lists(got, want)
+
+
+def test_alone_equals_in_mix(served):
+    """Every query's answer is the same alone and inside a mixed batch."""
+    w, idx = served
+    rad = torch.from_numpy(w.query_radius)
+    mix = csr_lists(*idx.query_radii(dev(w.queries), rad))
+    for i in range(0, w.nq, 5):
+        alone = csr_lists(*idx.query_radii(dev(w.queries[i:i + 1]), rad[i:i + 1]))[0]
+        assert np.array_equal(alone, mix[i]), f"query {i}"
+        plain = csr_lists(*idx.query_plain(dev(w.queries[i:i + 1]), int(w.query_radius[i])))[0]
+        assert np.array_equal(plain, mix[i])
+
+
+def test_spill_queue_for_large_buckets():
+    # 1500 copies of one point: its bucket in every table holds >= 1500 entries;
+    # with 64-entry tiles each such bucket is cut into ~23 spill chunks
+    rng = np.random.default_rng(10)
+    base = synth.uniform_points(1, 128, rng)
+    pts = synth.uniform_points(4500, 128, rng)
+    pts[::3] = base
+    qs = np.vstack([base, synth.flip_distinct(base[0], 128, 2, rng)[None], pts[1:4]])
+    idx = fc.Index(dev(pts), 128, 4, seed=91)
+    want = oracle.brute_force(pts, 128, qs, 4).ids
+    for tile, bpc in [(64, 1), (64, 8), (256, 4), (4096, 2)]:
+        idx.set_tuning(tile, bpc)
+        assert idx.get_tuning() == {"tile": tile, "blocks_per_cu": bpc}
+        assert_same_lists(csr_lists(*idx.query(dev(qs), 4)), want)
+    idx.close()
+
+
+def test_async_and_graph_replays(served):
+    w, idx = served
+    nq = 16
+    r = 8
+    stream = torch.cuda.Stream()
+    total_cap = 4096
+    qbuf = torch.empty((nq, fc.words(w.d)), dtype=torch.int64, device="cuda")
+    offsets = torch.zeros(nq + 1, dtype=torch.int64, device="cuda")
+    ids = torch.zeros(total_cap, dtype=torch.int32, device="cuda")
+    result = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with torch.cuda.stream(stream):
+        idx.reserve(nq, pair_capacity=1 << 15, spill_capacity=1 << 12, stream=stream)
+        # direct asynchronous call
+        qbuf.copy_(dev(w.queries[:nq]))
+        idx.query_async(qbuf, r, offsets, ids, result, stream=stream)
+    stream.synchronize()
+    want = oracle.brute_force(w.points, w.d, w.queries[:nq], r).ids
+    assert int(result[1]) == 0 and int(result[0]) == sum(len(x) for x in want)
+    assert_same_lists(csr_lists(offsets, ids[:int(result[0])]), want)
+    # graph: capture once, replay on new query contents, with eager work and
+    # synchronisations between the replays
+    with torch.cuda.stream(stream):
+        g = idx.query_graph(qbuf, r, offsets, ids, result, stream=stream)
+    stream.synchronize()
+    for rep, start in enumerate([0, 16, 32, 0]):
+        batch = w.queries[start:start + nq]
+        with torch.cuda.stream(stream):
+            qbuf.copy_(dev(batch))
+            ids.fill_(-1)
+            g.launch(stream=stream)
+        stream.synchronize()
+        want = oracle.brute_force(w.points, w.d, batch, r).ids
+        assert int(result[1]) == 0, f"replay {rep} status {int(result[1])}"
+        assert_same_lists(csr_lists(offsets, ids[:int(result[0])]), want)
+        _ = torch.randn(1000, device="cuda").sum().item()  # unrelated eager work between replays
+    g.close()
+
+
+def test_async_reports_overflow(served):
+    w, idx = served
+    stream = torch.cuda.Stream()
+    nq = 8
+    q = dev(w.queries[:nq])
+    offsets = torch.zeros(nq + 1, dtype=torch.int64, device="cuda")
+    ids = torch.zeros(1, dtype=torch.int32, device="cuda")
+    result = torch.zeros(2, dtype=torch.int64, device="cuda")
+    want = oracle.brute_force(w.points, w.d, w.queries[:nq], 10).ids
+    total = sum(len(x) for x in want)
+    assert total > 1
+    with torch.cuda.stream(stream):
+        idx.reserve(nq, pair_capacity=1 << 14, spill_capacity=1 << 12, stream=stream)
+        idx.query_async(q, 10, offsets, ids, result, stream=stream)
+    stream.synchronize()
+    assert int(result[0]) == total and int(result[1]) & fc.QUERY_IDS_OVERFLOW
+    assert int(offsets[-1]) == total
+    # a pair buffer smaller than the answer is reported, not overrun (a fresh
+    # stream has a fresh workspace: reserving only ever grows one)
+    ids = torch.zeros(total, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        idx.reserve(nq, pair_capacity=1, spill_capacity=1 << 12, stream=stream)
+        idx.query_async(q, 10, offsets, ids, result, stream=stream)
+    stream.synchronize()
+    assert int(result[1]) & fc.QUERY_PAIR_OVERFLOW
+    # the synchronous path grows its buffers and answers
+    assert_same_lists(csr_lists(*idx.query(q, 10, stream=stream)), want)
+
+
+def test_autotune_keeps_answers(served):
+    w, idx = served
+    res = idx.autotune(dev(w.queries), 10)
+    assert res["tile"] in (64, 128, 256, 512, 1024, 4096) and 1 <= res["blocks_per_cu"] <= 16
+    assert res["ms"] > 0
+    assert idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"]}
+    want = oracle.brute_force(w.points, w.d, w.queries, 10).ids
+    assert_same_lists(csr_lists(*idx.query(dev(w.queries), 10)), want)
+
+
+def test_large_result_segment_sort():
+    # one query whose answer (> 4096 ids) takes the long-segment sort
+    rng = np.random.default_rng(12)
+    base = synth.uniform_points(1, 64, rng)
+    pts = synth.uniform_points(9000, 64, rng)
+    pts[::2] = base
+    idx = fc.Index(dev(pts), 64, 3, seed=93)
+    want = oracle.brute_force(pts, 64, base, 3).ids
+    assert len(want[0]) > 4096
+    assert_same_lists(csr_lists(*idx.query(dev(base), 3)), want)
+    idx.close()
