@@ -1,0 +1,121 @@
+"""GPU parity at the full sizes of the five workloads, in the launch
+configuration the benchmark times.  The oracle cannot hash millions of points
+in O(dL), so it checks sampled outputs one by one: the keys of sampled points
+(all tables), the placement of those points in the stored tables, structural
+properties of whole sampled tables, and the exact answers of sampled queries
+against its linear scan."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._helpers import assert_same_lists, csr_lists
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1602_02620_amd as fc  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def check_index(w, seed, n_pts=48, n_tables=6, n_queries=24, radii=None):
+    rng = np.random.default_rng(seed)
+    _say(f"[full] {w.name}: build n={w.n} d={w.d} r={w.r}")
+    pts_d = fc.to_device_words(w.points)
+    idx = fc.Index(pts_d, w.d, w.r, seed=seed)
+    inf = idx.info
+    pr = oracle.derive_params(w.d, w.r, seed)
+    assert inf["L"] == pr.L
+    mask = oracle.masks(pr)
+
+    # keys of sampled points, all tables (Lemma 3 at full size)
+    which = np.sort(rng.choice(w.n, size=n_pts, replace=False))
+    want = oracle.keys(w.points, pr, which=which, mask=mask)
+    got = u32(idx.hash(pts_d[torch.from_numpy(which).cuda()]))
+    assert np.array_equal(got, want), f"{w.name}: sampled keys differ"
+
+    # sampled tables: whole-table structure, and the sampled points sit in
+    # the bin of their oracle key
+    db = inf["dir_bits"]
+    tabs = np.sort(rng.choice(pr.L, size=min(n_tables, pr.L), replace=False))
+    dr_all = u32(idx.directory())
+    for T in tabs:
+        tk, ti = (u32(x)[0] for x in idx.tables(int(T), int(T) + 1))
+        bins = tk >> np.uint32(31 - db)
+        assert np.all(np.diff(bins.astype(np.int64)) >= 0), f"table {T} not grouped by bin"
+        same = np.diff(bins.astype(np.int64)) == 0
+        assert np.all(np.diff(ti.astype(np.int64))[same] > 0), f"table {T}: ids not ascending in a bin"
+        assert np.array_equal(np.sort(ti), np.arange(w.n, dtype=np.uint32)), f"table {T}: not a permutation"
+        dr = dr_all[T]
+        assert np.array_equal(dr, np.searchsorted(bins, np.arange((1 << db) + 1)).astype(np.uint32))
+        pos = np.empty(w.n, np.int64)
+        pos[ti] = np.arange(w.n)
+        for j, pid in enumerate(which):
+            k = want[T, j]
+            p = pos[pid]
+            assert tk[p] == k and dr[k >> (31 - db)] <= p < dr[(k >> (31 - db)) + 1]
+
+    # sampled queries answered exactly (the whole batch runs on the GPU)
+    qs_d = fc.to_device_words(w.queries)
+    if radii is None:
+        offs, ids = idx.query(qs_d, w.r)
+    else:
+        offs, ids = idx.query_radii(qs_d, torch.from_numpy(radii))
+    got_q = csr_lists(offs, ids)
+    sample = np.sort(rng.choice(w.nq, size=min(n_queries, w.nq), replace=False))
+    for i in sample:
+        rq = w.r if radii is None else int(radii[i])
+        bf = oracle.brute_force(w.points, w.d, w.queries[i:i + 1], rq).ids[0]
+        assert np.array_equal(got_q[i], bf), f"{w.name}: query {i} differs"
+    _say(f"[full] {w.name}: ok, {int(offs[-1])} neighbours in the batch")
+    return idx
+
+
+def test_full_small():
+    w = synth.small()
+    idx = check_index(w, 3001, n_queries=100)
+    # at this size the oracle checks everything
+    pr = oracle.derive_params(w.d, w.r, 3001)
+    assert np.array_equal(u32(idx.hash(fc.to_device_words(w.points))), oracle.keys(w.points, pr))
+    bf = oracle.brute_force(w.points, w.d, w.queries, w.r)
+    assert_same_lists(csr_lists(*idx.query(fc.to_device_words(w.queries), w.r)), bf.ids)
+    idx.close()
+
+
+def test_full_mid():
+    idx = check_index(synth.mid(), 3002)
+    idx.close()
+
+
+def test_full_learned_code():
+    idx = check_index(synth.learned_code(), 3003, n_queries=12)
+    idx.close()
+
+
+def test_full_batched():
+    w = synth.batched()
+    idx = check_index(w, 3004, n_queries=12)
+    # skew: the per-query bucket sizes of the batch span orders of magnitude
+    coll = idx.collisions(fc.to_device_words(w.queries[:2000])).cpu().numpy()
+    _say(f"[full] batched #Collisions min {coll.min()} median {np.median(coll)} max {coll.max()}")
+    assert coll.max() >= 100 * max(1, int(np.median(coll)))
+    idx.close()
+
+
+def test_full_served_indexes():
+    a = synth.served_a(nq=512)
+    idx = check_index(a, 3005, radii=a.query_radius)
+    idx.close()
+    b = synth.served_b(nq=256)
+    idx = check_index(b, 3006, n_pts=16, n_tables=3, n_queries=12, radii=b.query_radius)
+    idx.close()
