@@ -39,10 +39,21 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="rough CPU budget of the oracle leg")
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--plain-queries", type=int, default=200)
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the 100k-query batched section (off by default)")
+    ap.add_argument("--served", action="store_true",
+                    help="also run the served section (off by default)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rps", type=float, default=100.0, help="Poisson request rate of the served run")
     ap.add_argument("--kernel-only", choices=["hash", "build"], default=None,
                     help="profiling aid: launch only this part (plus a plain copy of known size "
                          "for counter calibration) --kernel-reps times")
     return ap.parse_args()
+
+
+def stage(msg):
+    """Progress line on stderr, flushed, naming the step about to run."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def pct(a, q):
@@ -69,10 +80,12 @@ def main():
     qs = fc.to_device_words(w.queries, dev)
     stream = torch.cuda.current_stream()
 
+    stage(f"build index: {w.name} n={n} d={d} r={r}")
     idx = fc.Index(pts, d, r, seed=args.seed)
     info = idx.info
     L = info["L"]
     if args.kernel_only:
+        stage(f"kernel-only {args.kernel_only}")
         kernel_only(args, idx, pts, n, L, dev, torch)
         idx.close()
         return
@@ -81,6 +94,7 @@ def main():
         idx.rebuild()
         return idx.query(qs, r)
 
+    stage(f"{args.warmup} warmup + {args.steps} timed steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -92,7 +106,26 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     total_ids = int(offs[-1].item())
 
-    # ---- per-phase timing with HIP events on the stream the kernels run on
+    # ---- per-kernel durations: HIP events recorded by the library between
+    # the kernels, on the stream they are launched on
+    stage("per-kernel timing of the rebuild")
+    idx.rebuild_timed()
+    runs = [idx.rebuild_timed() for _ in range(args.kernel_reps)]
+    phase_ms = {k: float(np.mean([run[k] for run in runs])) for k in runs[0]}
+    nblk = (n + 8191) // 8192
+    entries = n * L
+    kernel_bytes = {  # algorithmic bytes per launch
+        "fht_hash_kernel": n * (W * 8 + 4 * L),                    # read the point, write its L keys
+        "p1_hist_kernel": 4 * entries + 4 * L * nblk * 256,          # read keys, write tile histograms
+        "p1_scan_kernel": 8 * L * nblk * 256,                        # read + write the histograms
+        "p1_scatter_kernel": 12 * entries,                           # read key, write key + id
+        "p2_bucket_kernel": 16 * entries + 4 * L * ((1 << info["dir_bits"]) + 1),  # read + write key, id; directory
+    }
+    dominant = max(phase_ms, key=phase_ms.get)
+    achieved = kernel_bytes[dominant] / (phase_ms[dominant] * 1e-3) / 1e9
+    ms_hash = phase_ms["fht_hash_kernel"]
+    ms_build = sum(v for k, v in phase_ms.items() if k != "fht_hash_kernel")
+
     def ev_time(fn, reps):
         st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         fn()
@@ -104,13 +137,12 @@ def main():
         en.synchronize()
         return st.elapsed_time(en) / reps
 
-    keys = torch.empty((L, n), dtype=torch.int32, device=dev)
-    ms_hash = ev_time(lambda: idx.hash(pts, out=keys), args.kernel_reps)
-    ms_build = ev_time(lambda: idx.rebuild(), max(2, args.kernel_reps // 3))
+    stage("query batch timing")
     ms_query = ev_time(lambda: idx.query(qs, r), max(2, args.kernel_reps // 3))
 
     # per-query latency: batched (whole batch, each query waits for the batch)
     # vs plain (one launch sequence and sync per query)
+    stage(f"plain path, {min(args.plain_queries, nq)} queries")
     nplain = min(args.plain_queries, nq)
     lat_plain = []
     for i in range(nplain):
@@ -125,8 +157,11 @@ def main():
         idx.query(qs, r)
         lat_batch.append((time.perf_counter() - a) * 1e3)
 
-    hash_bytes = n * (W * 8 + 4 * L)  # algorithmic: read the point, write L uint32 keys
-    achieved = hash_bytes / (ms_hash * 1e-3) / 1e9
+    stage("keys of all points for the oracle comparison")
+    keys = torch.empty((L, n), dtype=torch.int32, device=dev)
+    idx.hash(pts, out=keys)
+    torch.cuda.synchronize()
+    build_bytes = 12 * entries  # the table build as a whole: read key, write key + id
     out = {
         "metric": METRIC,
         "value": n / (ms_step * 1e-3),
@@ -145,21 +180,178 @@ def main():
         "breakdown": {
             "hash_ms": ms_hash, "hash_points_per_s": n / (ms_hash * 1e-3),
             "hash_keys_per_s": n * L / (ms_hash * 1e-3),
-            "build_ms": ms_build, "build_points_per_s": n / (ms_build * 1e-3),
+            "hash_GBps": kernel_bytes["fht_hash_kernel"] / (ms_hash * 1e-3) / 1e9,
+            "build_ms": ms_build, "build_entries_per_s": entries / (ms_build * 1e-3),
+            "build_GBps_at_12B_per_entry": build_bytes / (ms_build * 1e-3) / 1e9,
+            "kernel_ms": phase_ms,
             "query_batch_ms": ms_query, "queries_per_s": nq / (ms_query * 1e-3),
             "reported_ids": total_ids,
             "plain_query_ms_p50": pct(lat_plain, 50), "plain_query_ms_p99": pct(lat_plain, 99),
             "plain_queries_per_s": 1e3 / float(np.mean(lat_plain)) if lat_plain else None,
             "batch_latency_ms_p50": pct(lat_batch, 50), "batch_latency_ms_p99": pct(lat_batch, 99),
         },
-        "roofline": {"kernel": "fht_hash_kernel", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": hash_bytes},
+        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dominant, n, d, r),
+                     "bytes_per_launch": kernel_bytes[dominant], "ms_per_launch": phase_ms[dominant]},
     }
+    checks = []
     if not args.no_cpu_baseline:
+        stage(f"oracle on the host, about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(w, idx, qs, keys, args, fc)
     idx.close()
+    del keys
+    torch.cuda.empty_cache()
+    if args.batched:
+        stage("batched section")
+        out["batched"], chk = batched_section(args, fc, torch)
+        checks.append(chk)
+    if args.served:
+        stage("served section")
+        out["served"], chk = served_section(args, fc, torch)
+        checks.append(chk)
+    if checks and not args.no_cpu_baseline:
+        out["cpu_baseline"]["answers_checked"] = verify_samples(checks)
     print(json.dumps(out), flush=True)
+
+
+def batched_section(args, fc, torch):
+    """100,000 queries against the skewed 4M-point, 512-bit mixture index
+    (r = 12, two parts): one batched launch sequence with the autotuned
+    shape, against the plain path (one launch sequence per query)."""
+    import synth
+
+    w = synth.batched()
+    pts = fc.to_device_words(w.points)
+    qs = fc.to_device_words(w.queries)
+    idx = fc.Index(pts, w.d, w.r, seed=3004)
+    tune = idx.autotune(qs[:8192], w.r)
+    idx.query(qs, w.r)  # size the workspace
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        offs, ids = idx.query(qs, w.r)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / reps
+    coll = idx.collisions(qs).cpu().numpy()
+    nplain = min(args.plain_queries, w.nq)
+    lat = []
+    for i in range(nplain):
+        a = time.perf_counter()
+        idx.query_plain(qs[i:i + 1], w.r)
+        lat.append((time.perf_counter() - a) * 1e3)
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(w.nq, size=8, replace=False))
+    o = offs.cpu().numpy()
+    v = ids.cpu().numpy().view(np.uint32)
+    chk = (w, sample, [v[o[i]:o[i + 1]] for i in sample], [w.r] * len(sample))
+    res = {"workload": f"batched: n={w.n} d={w.d} r={w.r} L={idx.info['L']} nq={w.nq}",
+           "batch_ms": ms_batch, "queries_per_s": w.nq / (ms_batch * 1e-3),
+           "reported_ids": int(o[-1]), "tuning": tune,
+           "collisions_min": int(coll.min()), "collisions_median": float(np.median(coll)),
+           "collisions_max": int(coll.max()),
+           "plain_query_ms_p50": pct(lat, 50), "plain_query_ms_p99": pct(lat, 99),
+           "plain_queries_per_s": 1e3 / float(np.mean(lat)),
+           "speedup_vs_plain": (w.nq / (ms_batch * 1e-3)) / (1e3 / float(np.mean(lat)))}
+    idx.close()
+    return res, chk
+
+
+def served_section(args, fc, torch):
+    """Two resident indexes (n=2M d=256 r=10; n=500k d=1024 r=20), Poisson
+    request arrivals, request sizes U[1, 4096], index and radius mixed."""
+    import synth
+    from paper_1602_02620_amd.serve import Server, poisson_trace
+
+    a = synth.served_a(nq=4096)
+    b = synth.served_b(nq=4096)
+    ia = fc.Index(fc.to_device_words(a.points), a.d, a.r, seed=3005)
+    ib = fc.Index(fc.to_device_words(b.points), b.d, b.r, seed=3006)
+    # plain service time per query of each index (one launch sequence each)
+    plain = {}
+    for name, w, ix in (("A", a, ia), ("B", b, ib)):
+        qd = fc.to_device_words(w.queries[:64])
+        ix.query_plain(qd[:1], w.r)
+        lat = []
+        for i in range(64):
+            t0 = time.perf_counter()
+            ix.query_plain(qd[i:i + 1], w.r)
+            lat.append(time.perf_counter() - t0)
+        plain[name] = float(np.mean(lat))
+    srv = Server({"A": ia, "B": ib}, max_batch=4096, streams=3, mem_budget=8 << 30, ids_per_query=16)
+    rng = np.random.default_rng(31)
+    arrivals = poisson_trace(args.serve_rps, args.serve_seconds, rng)
+    reqs = []
+    t0 = time.perf_counter()
+    for ta in arrivals:
+        while time.perf_counter() - t0 < ta:
+            time.sleep(50e-6)
+        name = "A" if rng.random() < 0.5 else "B"
+        w = a if name == "A" else b
+        m = int(rng.integers(1, 4097))
+        rows = rng.integers(0, w.nq, size=m)
+        rad = int(rng.integers(0, w.r + 1))
+        reqs.append((name, w, rows, rad, srv.submit(name, w.queries[rows], rad)))
+    results = [f.result(timeout=600) for *_, f in reqs]
+    t_end = time.perf_counter()
+    srv.close()
+    st = srv.stats()
+    plain_req = [plain[nm] * len(rows) * 1e3 for nm, _, rows, _, _ in reqs]
+    k = int(rng.integers(0, len(reqs)))
+    nm, w, rows, rad, _ = reqs[k]
+    pick = np.arange(min(4, len(rows)))
+    chk = (w, rows[pick], [results[k][i] for i in pick], [rad] * len(pick))
+    res = {"workload": "served: A n=2000000 d=256 r=10 L=126; B n=500000 d=1024 r=20 L=4094",
+           "offered_requests_per_s": args.serve_rps, "seconds": args.serve_seconds,
+           "requests": st["requests"], "queries": st["queries"], "batches": st["batches"],
+           "queries_per_s": st["queries"] / (t_end - t0),
+           "latency_ms_p50": st["p50_ms"], "latency_ms_p99": st["p99_ms"],
+           "plain_service_ms_p50": pct(plain_req, 50), "plain_service_ms_p99": pct(plain_req, 99),
+           "plain_query_ms": {k2: v2 * 1e3 for k2, v2 in plain.items()}}
+    ia.close()
+    ib.close()
+    return res, chk
+
+
+def verify_samples(checks):
+    """Oracle linear scan of sampled queries of the batched and served runs,
+    compared with the answers the GPU returned for them."""
+    import oracle
+
+    out = []
+    for w, rows, got, radii in checks:
+        ok = True
+        for q, g, rq in zip(rows, got, radii):
+            want = oracle.brute_force(w.points, w.d, w.queries[q:q + 1], rq).ids[0]
+            ok &= bool(np.array_equal(np.asarray(g, np.uint32), want))
+        out.append({"workload": w.name, "queries": int(len(rows)), "equal": ok})
+    return out
+
+
+KERNEL_SOURCES = {"fht_hash_kernel": "hash.hip", "p1_hist_kernel": "tables.hip", "p1_scan_kernel": "tables.hip",
+                  "p1_scatter_kernel": "tables.hip", "p2_bucket_kernel": "tables.hip"}
+
+
+def measured_traffic(kernel, n, d, r):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a copy of
+    known size), or None when there is none for this kernel and workload or
+    the kernel's source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec or (rec["n"], rec["d"], rec["r"]) != (n, d, r):
+        return None
+    src = os.path.join(ROOT, "paper_1602_02620_amd", "csrc", KERNEL_SOURCES[kernel])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
@@ -194,8 +386,10 @@ def cpu_baseline(w, idx, qs, keys, args, fc):
     pr = oracle.derive_params(w.d, w.r, args.seed)
     mask = oracle.masks(pr)
     cores = oracle.num_threads()
-    # keys: calibrate on a small sample, then size the timed sample to ~half the budget
-    probe = np.arange(64)
+    # keys: calibrate on a sample that keeps every thread busy (the oracle
+    # hands out points in chunks of 64), then size the timed sample to about
+    # half the budget
+    probe = np.arange(min(w.n, 64 * 4 * cores))
     a = time.perf_counter()
     oracle.keys(w.points, pr, which=probe, mask=mask)
     per_pt = (time.perf_counter() - a) / len(probe)
@@ -208,9 +402,10 @@ def cpu_baseline(w, idx, qs, keys, args, fc):
     gk = keys[:, which].cpu().numpy().view(np.uint32)
     keys_equal = bool(np.array_equal(gk, ok))
     # queries: brute force on a sample of the batch, compared with the GPU answers
+    nprobe = min(w.nq, 2 * cores)  # one query per thread at a time
     a = time.perf_counter()
-    oracle.brute_force(w.points, w.d, w.queries[:2], w.r)
-    per_q = (time.perf_counter() - a) / 2
+    oracle.brute_force(w.points, w.d, w.queries[:nprobe], w.r)
+    per_q = (time.perf_counter() - a) / nprobe
     nqs = int(max(2, min(w.nq, 0.4 * budget / max(per_q, 1e-9))))
     a = time.perf_counter()
     bf = oracle.brute_force(w.points, w.d, w.queries[:nqs], w.r)

@@ -190,9 +190,17 @@ FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tk
                                 const uint64_t **d_points);
 
 /* Rebuild the tables of an existing index from its own points (the bucketing
- * step alone: hash + table build), for timing.  Asynchronous except for the
- * oversize-bucket check. */
+ * step alone: hash + table build), for timing.  Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
+
+/* The same rebuild with HIP events recorded on `stream` around each kernel.
+ * phase_ms[0..4] (host, nphase >= 5) receive the durations in ms of: the key
+ * computation of Alg. 2 for all points and tables, the pass-1 histogram, the
+ * pass-1 scan, the pass-1 scatter and pass 2 of the table build.
+ * Errors: FCLSH_EINVAL for a short phase_ms, FCLSH_EDEVICE for HIP errors.
+ * Synchronises `stream`. */
+FCLSH_API fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms,
+                                                 int32_t nphase);
 
 /* Per-query diagnostics of Sec. 4.1: #Collisions (summed sizes of the query's
  * L buckets) for each query, written to device d_collisions[nq] (uint64).
@@ -265,8 +273,12 @@ FCLSH_API fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, in
 /* Autotuner: times the batched pipeline on a sample batch (device queries)
  * for a grid of (tile, blocks_per_cu) and keeps the fastest on the index; the
  * choice is also cached for later indexes of the same shape (d, t, r',
- * ceil(log2 n)) on the same device.  Outputs (optional): the chosen values
- * and its time per batch in ms.  Synchronises `stream`. */
+ * ceil(log2 n)) on the same device.  Each shape first runs once through the
+ * synchronous path, which grows the stream's workspace until the run is
+ * complete; a timed run that still reports an overflow is not a candidate.
+ * Outputs (optional): the chosen values and its time per batch in ms.
+ * Errors: FCLSH_EDEVICE if no shape completes or a HIP call fails (the
+ * index keeps its previous shape).  Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
                                       int32_t r_query, void *stream, int32_t *tile_out,
                                       int32_t *blocks_out, float *best_ms_out);

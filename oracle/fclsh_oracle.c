@@ -90,7 +90,7 @@ static void orc_shuffle(orc_rng *g, int32_t *perm, int32_t len)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Parameters (Alg. 1 pre-processing and Alg. 2 lines 1, 4, 7)               */
+/* Parameters (Alg. 1 pre-processing; the random draws of Alg. 2)            */
 /* ------------------------------------------------------------------------ */
 
 /* Number of parts t.  The experiments (Sec. 4.1 parameter settings and
@@ -114,11 +114,11 @@ int orc_parts_for_radius(int r, int override_t)
  *            [p*floor(d/t), (p+1)*floor(d/t)) of pi; the last part also
  *            takes the remainder up to d (Alg. 1, contiguous split).
  *  col     : per part, in pi order.  If the part has d_p <= D coordinates
- *            (specific construction, Alg. 2 line 7) its coordinates take the
+ *            (specific construction of Alg. 2) its coordinates take the
  *            first d_p entries of a uniform permutation of [0, D); otherwise
- *            (general construction, Eq. (5), Alg. 2 line 4) each coordinate
+ *            (general construction, Eq. (5), Alg. 2) each coordinate
  *            takes an independent uniform column in [0, D).
- *  b       : b[c] uniform in [0, P) for c = 0..d-1 (Alg. 2 line 1).
+ *  b       : b[c] uniform in [0, P) for c = 0..d-1 (the seed vector of Eq. (1)).
  *
  * Draw order: pi, then the columns part by part, then b.
  * Returns 0, or -1 on bad arguments (r' + 1 > 20 is refused). */

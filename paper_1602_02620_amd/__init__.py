@@ -31,7 +31,7 @@ FCLSH_EUNSUPPORTED = -6
 EXPORTS = [
     "fclsh_derive_params", "fclsh_build_index", "fclsh_build_index_with_params", "fclsh_query_batch",
     "fclsh_index_free", "fclsh_last_error", "fclsh_index_info", "fclsh_index_params", "fclsh_hash",
-    "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_query_collisions", "fclsh_query_plain",
+    "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_index_rebuild_timed", "fclsh_query_collisions", "fclsh_query_plain",
     "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
     "fclsh_autotune",
@@ -78,6 +78,7 @@ def lib():
             "fclsh_hash": [vp, vp, i64, vp, vp],
             "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
             "fclsh_index_rebuild": [vp, vp],
+            "fclsh_index_rebuild_timed": [vp, vp, P(ctypes.c_float), i32],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_reserve": [vp, i64, i64, i64, vp],
@@ -227,6 +228,15 @@ class Index:
 
     def rebuild(self, stream=None):
         _check(lib().fclsh_index_rebuild(self._h, _stream_ptr(stream)))
+
+    REBUILD_PHASES = ("fht_hash_kernel", "p1_hist_kernel", "p1_scan_kernel", "p1_scatter_kernel",
+                      "p2_bucket_kernel")
+
+    def rebuild_timed(self, stream=None) -> dict:
+        """Rebuild with HIP events between the kernels: kernel name -> ms."""
+        ms = (ctypes.c_float * len(self.REBUILD_PHASES))()
+        _check(lib().fclsh_index_rebuild_timed(self._h, _stream_ptr(stream), ms, len(self.REBUILD_PHASES)))
+        return dict(zip(self.REBUILD_PHASES, (float(x) for x in ms)))
 
     def table_pointers(self):
         k, i, dr, p = (ctypes.c_void_p() for _ in range(4))

@@ -54,6 +54,9 @@ uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 
 
 }  // namespace
 
+// hash, pass-1 histogram, pass-1 scan, pass-1 scatter, pass 2
+constexpr int kRebuildPhases = 5;
+
 struct IndexHandle {
     Index ix;
     std::mutex mu;
@@ -84,7 +87,9 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
     return b;
 }
 
-static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st) {
+// Hash + table build on st, then a synchronisation.  marks (optional, 6
+// events): before the hash, after the hash, then after each table kernel.
+static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *marks = nullptr) {
     Index &ix = h->ix;
     const int64_t L = ix.prm.L();
     if (!h->keys) {
@@ -94,9 +99,11 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st) {
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n),
                             "table histograms"));
     }
+    if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
     FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
+    if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
-                                 st));
+                                 st, marks ? marks + 2 : nullptr));
     FCLSH_HIP(hipStreamSynchronize(st));
     return FCLSH_OK;
 }
@@ -194,6 +201,25 @@ static fclsh_status publish_result(QueryWorkspace &ws, uint64_t *d_result, hipSt
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
+
+// Device buffers and events of one autotuning run, released on every exit.
+struct DeviceBuffers {
+    void *offs = nullptr;
+    void *ids = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool alloc(void **p, size_t bytes) {
+        if (hipMalloc(p, bytes) == hipSuccess) return true;
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    ~DeviceBuffers() {
+        if (offs) (void)hipFree(offs);
+        if (ids) (void)hipFree(ids);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
 
 struct GraphHandle {
     hipGraph_t graph = nullptr;
@@ -309,6 +335,25 @@ fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const
 fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream) {
     if (!idx) return fail(FCLSH_EINVAL, "null index");
     return hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream));
+}
+
+fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms, int32_t nphase) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!phase_ms || nphase < kRebuildPhases) return fail(FCLSH_EINVAL, "phase_ms needs %d entries", kRebuildPhases);
+    hipEvent_t ev[kRebuildPhases + 1] = {};
+    fclsh_status s = FCLSH_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            s = fail(FCLSH_EDEVICE, "hipEventCreate failed");
+            break;
+        }
+    if (s == FCLSH_OK) s = hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream), ev);
+    for (int k = 0; s == FCLSH_OK && k < kRebuildPhases; ++k)
+        if (hipEventElapsedTime(&phase_ms[k], ev[k], ev[k + 1]) != hipSuccess)
+            s = fail(FCLSH_EDEVICE, "hipEventElapsedTime failed");
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return s;
 }
 
 fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
@@ -467,55 +512,60 @@ fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     QueryWorkspace &ws = *h->workspace(st);
     Index &ix = h->ix;
-    // size the buffers once with the synchronous path, then time candidates
-    uint64_t *offs = nullptr;
-    uint32_t *ids = nullptr;
-    uint64_t *res = nullptr;
-    FCLSH_HIP(hipMalloc(&offs, size_t(nq + 1) * 8));
-    FCLSH_HIP(hipMalloc(&res, 16));
-    int64_t total = 0;
-    fclsh_status s = query_batch(ix, ws, d_queries, nq, r_query, nullptr, st, offs, nullptr, 0, &total);
-    if (s != FCLSH_OK && s != FCLSH_ECAPACITY) {
-        (void)hipFree(offs);
-        (void)hipFree(res);
-        return s;
-    }
-    if (hipMalloc(&ids, size_t(std::max<int64_t>(total, 1)) * 4) != hipSuccess) {
-        (void)hipFree(offs);
-        (void)hipFree(res);
-        return fail(FCLSH_ENOMEM, "autotune buffers");
-    }
     const QueryTuning saved = ix.tuning;
+    DeviceBuffers buf;
+    // the answer size of the sample (the id buffer is sized to it once)
+    int64_t total = 0;
+    if (!buf.alloc(&buf.offs, size_t(nq + 1) * 8)) return fail(FCLSH_ENOMEM, "autotune buffers");
+    fclsh_status s = query_batch(ix, ws, d_queries, nq, r_query, nullptr, st, static_cast<uint64_t *>(buf.offs),
+                                 nullptr, 0, &total);
+    if (s != FCLSH_OK && s != FCLSH_ECAPACITY) return s;
+    if (!buf.alloc(&buf.ids, size_t(std::max<int64_t>(total, 1)) * 4)) return fail(FCLSH_ENOMEM, "autotune buffers");
+    uint64_t *offs = static_cast<uint64_t *>(buf.offs);
+    uint32_t *ids = static_cast<uint32_t *>(buf.ids);
+    if (hipEventCreate(&buf.e0) != hipSuccess || hipEventCreate(&buf.e1) != hipSuccess)
+        return fail(FCLSH_EDEVICE, "hipEventCreate failed");
     const int tiles[] = {64, 128, 256, 512, 1024, 4096};
     const int bpcs[] = {2, 4, 8, 16};
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    float best = 1e30f;
+    float best = -1.0f;
     QueryTuning best_t = saved;
     for (int tl : tiles)
         for (int bp : bpcs) {
             ix.tuning = QueryTuning{tl, bp};
-            fclsh_status r1 = query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
-            if (r1 != FCLSH_OK) continue;
-            (void)hipEventRecord(e0, st);
-            for (int rep = 0; rep < 3; ++rep)
-                (void)query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
-            (void)hipEventRecord(e1, st);
-            (void)hipEventSynchronize(e1);
+            // the synchronous path first: it grows the spill queue and the
+            // pair buffer until this shape's run is complete
+            int64_t got = 0;
+            s = query_batch(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total, &got);
+            if (s != FCLSH_OK) {
+                ix.tuning = saved;
+                return s;
+            }
+            FCLSH_HIP(hipEventRecord(buf.e0, st));
+            for (int rep = 0; rep < 3; ++rep) {
+                s = query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
+                if (s != FCLSH_OK) {
+                    (void)hipStreamSynchronize(st);
+                    ix.tuning = saved;
+                    return s;
+                }
+            }
+            FCLSH_HIP(hipEventRecord(buf.e1, st));
+            FCLSH_HIP(hipEventSynchronize(buf.e1));
+            QueryCtrl c{};
+            FCLSH_HIP(hipMemcpy(&c, ws.ctrl, sizeof c, hipMemcpyDeviceToHost));
+            if (c.status != 0) continue;  // an overflowing run skipped work: not a valid timing
             float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            FCLSH_HIP(hipEventElapsedTime(&ms, buf.e0, buf.e1));
             ms /= 3;
-            if (ms < best) {
+            if (best < 0 || ms < best) {
                 best = ms;
                 best_t = ix.tuning;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(offs);
-    (void)hipFree(ids);
-    (void)hipFree(res);
+    if (best < 0) {
+        ix.tuning = saved;
+        return fail(FCLSH_EDEVICE, "no launch shape completed the sample batch");
+    }
     ix.tuning = best_t;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
@@ -524,7 +574,6 @@ fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t 
     if (tile_out) *tile_out = best_t.tile;
     if (blocks_out) *blocks_out = best_t.blocks_per_cu;
     if (best_ms_out) *best_ms_out = best;
-    FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
 

@@ -2,9 +2,9 @@
 // O(d + L log L).
 //
 //   sketch   t_j = sum of b_c over coordinates c of the part with x_c = 1
-//            and m(c) = j (Alg. 2 lines 2-8; the specific construction is the
+//            and m(c) = j (the sketch of Alg. 2; the specific construction is the
 //            case of at most one coordinate per column, 0-padded)
-//   FHT      F = H t with the Sylvester Hadamard matrix (Alg. 2 line 10)
+//   FHT      F = H t with the Sylvester Hadamard matrix (Alg. 2, Eq. (6))
 //   keys     h_v = (S - F_v) / 2 mod P with S = sum_j t_j (= F_0), v >= 1
 //            (Eq. (6); the v = 0 value is the all-zero codeword, dropped)
 //
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
         __builtin_amdgcn_wave_barrier();
         const uint32_t *myx = wx + u * stride;
 
-        // Sketch (Alg. 2 lines 2-8)
+        // Sketch (Alg. 2)
         double t[V];
         if constexpr (SPECIFIC) {
 #pragma unroll
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
         __asm__ volatile("" ::: "memory");
         __builtin_amdgcn_wave_barrier();
 
-        // Fast Hadamard transform (Alg. 2 line 10): in-register stages ...
+        // Fast Hadamard transform (Alg. 2): in-register stages ...
 #pragma unroll
         for (int h = 1; h < V; h <<= 1) {
 #pragma unroll

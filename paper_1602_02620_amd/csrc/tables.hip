@@ -363,7 +363,7 @@ size_t table_build_scratch_bytes(int64_t L, int64_t n) {
 
 fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
                                 uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
-                                uint32_t *dir, hipStream_t st) {
+                                uint32_t *dir, hipStream_t st, hipEvent_t *marks) {
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
     if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
@@ -372,16 +372,20 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     uint32_t *bstart = scratch + size_t(L) * nblk * kHiBins;
     hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
     FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
     hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins), 0, st, hist, nblk, n, bstart);
     FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     hipLaunchKernelGGL(p1_scatter_kernel, dim3(nblk, unsigned(L)), dim3(kNT), 0, st, keys, n, hist, nblk, tmpk,
                        tmpv);
     FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[2], st));
     const int lo_bits = dir_bits - kHiBits;
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
     hipLaunchKernelGGL(p2_bucket_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
                        lo_bits, tkeys, tids, dir);
     FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
     return FCLSH_OK;
 }
 

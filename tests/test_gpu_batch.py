@@ -172,3 +172,57 @@ def test_large_result_segment_sort():
     assert len(want[0]) > 4096
     assert_same_lists(csr_lists(*idx.query(dev(base), 3)), want)
     idx.close()
+
+
+def _heavy_index():
+    # 1500 copies of one point: every table holds a bucket of >= 1500 entries
+    rng = np.random.default_rng(10)
+    base = synth.uniform_points(1, 128, rng)
+    pts = synth.uniform_points(4500, 128, rng)
+    pts[::3] = base
+    return base, pts, fc.Index(dev(pts), 128, 4, seed=91)
+
+
+def test_sync_path_grows_overflowing_buffers():
+    """100 copies of the heavy query: with 64-entry tiles the first run needs
+    more spill chunks (~23 per bucket, 31 tables) and more pairs than the
+    first sizing holds; the synchronous path grows both and answers exactly."""
+    base, pts, idx = _heavy_index()
+    rng = np.random.default_rng(13)
+    qs = np.vstack([np.repeat(base, 100, axis=0), synth.uniform_points(4, 128, rng)])
+    want = oracle.brute_force(pts, 128, qs, 4).ids
+    assert sum(len(x) for x in want) > 1 << 17
+    idx.set_tuning(64, 2)
+    stream = torch.cuda.Stream()
+    _say("[batch] heavy queries, 64-entry tiles, fresh workspace")
+    with torch.cuda.stream(stream):
+        got = csr_lists(*idx.query(dev(qs), 4, stream=stream))
+    assert_same_lists(got, want)
+    # the asynchronous path on a workspace reserved too small reports it
+    stream2 = torch.cuda.Stream()
+    nq = qs.shape[0]
+    offsets = torch.zeros(nq + 1, dtype=torch.int64, device="cuda")
+    ids = torch.zeros(1 << 18, dtype=torch.int32, device="cuda")
+    result = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with torch.cuda.stream(stream2):
+        idx.reserve(nq, pair_capacity=1 << 18, spill_capacity=64, stream=stream2)
+        idx.query_async(dev(qs), 4, offsets, ids, result, stream=stream2)
+    stream2.synchronize()
+    assert int(result[1]) & fc.QUERY_SPILL_OVERFLOW
+    idx.close()
+
+
+def test_autotune_with_heavy_buckets():
+    """Shapes whose spill queue overflows the first sizing are run complete
+    (the workspace grows) before they are timed; the chosen shape answers
+    exactly."""
+    base, pts, idx = _heavy_index()
+    rng = np.random.default_rng(14)
+    qs = np.vstack([np.repeat(base, 40, axis=0), synth.flip_distinct(base[0], 128, 3, rng)[None],
+                    synth.uniform_points(8, 128, rng)])
+    want = oracle.brute_force(pts, 128, qs, 4).ids
+    _say("[batch] autotune over heavy buckets")
+    res = idx.autotune(dev(qs), 4)
+    assert res["ms"] > 0 and idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"]}
+    assert_same_lists(csr_lists(*idx.query(dev(qs), 4)), want)
+    idx.close()

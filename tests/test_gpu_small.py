@@ -293,3 +293,17 @@ def test_rebuild_is_deterministic():
     tk1, ti1 = (as_u32(t) for t in idx.tables())
     assert np.array_equal(tk0, tk1) and np.array_equal(ti0, ti1)
     idx.close()
+
+
+def test_timed_rebuild_reports_every_kernel():
+    """The timed rebuild gives the same tables and a positive duration for
+    each of its five kernels."""
+    w = synth.small(0.1)
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=5)
+    tk0, ti0 = (as_u32(t) for t in idx.tables())
+    ms = idx.rebuild_timed()
+    assert list(ms) == list(fc.Index.REBUILD_PHASES)
+    assert all(v > 0 for v in ms.values()), ms
+    tk1, ti1 = (as_u32(t) for t in idx.tables())
+    assert np.array_equal(tk0, tk1) and np.array_equal(ti0, ti1)
+    idx.close()
