@@ -134,8 +134,9 @@ FCLSH_API fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, i
  * Sec. 2.2 with Steps S1-S3 of Sec. 4.1): for each query, every data point id
  * at Hamming distance <= r_query, ids ascending.
  *
- * d_queries: device, nq*W uint64.  nq >= 0.  0 <= r_query <= the index's r
- * (an r-covering family covers every smaller radius); larger r_query gives
+ * d_queries: device, nq*W uint64.  nq >= 0 with nq * L < 2^32 (else
+ * FCLSH_EINVAL; split larger batches).  0 <= r_query <= the index's r (an
+ * r-covering family covers every smaller radius); larger r_query gives
  * FCLSH_ERADIUS.
  * Output (device, caller-owned): d_offsets[nq+1] uint64 CSR offsets and
  * d_ids[ids_capacity] uint32; query i's neighbours are
@@ -194,9 +195,10 @@ FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tk
 FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
 
 /* The same rebuild with HIP events recorded on `stream` around each kernel.
- * phase_ms[0..4] (host, nphase >= 5) receive the durations in ms of: the key
+ * phase_ms[0..5] (host, nphase >= 6) receive the durations in ms of: the key
  * computation of Alg. 2 for all points and tables, the pass-1 histogram, the
- * pass-1 scan, the pass-1 scatter and pass 2 of the table build.
+ * pass-1 scan, the pass-1 scatter, the pass-2 fast path and the pass-2
+ * stable path (super-bins the fast path left) of the table build.
  * Errors: FCLSH_EINVAL for a short phase_ms, FCLSH_EDEVICE for HIP errors.
  * Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms,

@@ -230,7 +230,7 @@ class Index:
         _check(lib().fclsh_index_rebuild(self._h, _stream_ptr(stream)))
 
     REBUILD_PHASES = ("fht_hash_kernel", "p1_hist_kernel", "p1_scan_kernel", "p1_scatter_kernel",
-                      "p2_bucket_kernel")
+                      "p2_fast_kernel", "p2_rest_kernel")
 
     def rebuild_timed(self, stream=None) -> dict:
         """Rebuild with HIP events between the kernels: kernel name -> ms."""

@@ -54,8 +54,8 @@ uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 
 
 }  // namespace
 
-// hash, pass-1 histogram, pass-1 scan, pass-1 scatter, pass 2
-constexpr int kRebuildPhases = 5;
+// hash, pass-1 histogram, pass-1 scan, pass-1 scatter, pass-2 fast, pass-2 stable
+constexpr int kRebuildPhases = 6;
 
 struct IndexHandle {
     Index ix;
@@ -87,8 +87,9 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
     return b;
 }
 
-// Hash + table build on st, then a synchronisation.  marks (optional, 6
-// events): before the hash, after the hash, then after each table kernel.
+// Hash + table build on st, then a synchronisation.  marks (optional,
+// kRebuildPhases + 1 events): before the hash, after the hash, then after
+// each table kernel.
 static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *marks = nullptr) {
     Index &ix = h->ix;
     const int64_t L = ix.prm.L();

@@ -144,8 +144,9 @@ fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, ui
 // key bits, ids ascending per bin, plus the directory [L][2^dir_bits + 1].
 int table_dir_bits(int64_t n);
 size_t table_build_scratch_bytes(int64_t L, int64_t n);
-// marks (optional, 4 events) are recorded on st after each of the four
-// kernels: pass-1 histogram, pass-1 scan, pass-1 scatter, pass 2.
+// marks (optional, 5 events) are recorded on st after each of the five
+// kernels: pass-1 histogram, pass-1 scan, pass-1 scatter, pass-2 fast path,
+// pass-2 stable path.
 fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
                                 uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
                                 uint32_t *dir, hipStream_t st, hipEvent_t *marks = nullptr);

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
                                                        uint32_t *__restrict__ keys, int64_t key_stride) {
     using S = Shape<LOGD, LOGV>;
     constexpr int V = S::V, G = S::G, U = S::U, D = S::D;
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int s = lane >> S::LOGU;

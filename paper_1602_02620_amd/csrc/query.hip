@@ -21,13 +21,15 @@
 //
 // The batched pipeline runs on the device without a host round trip, so a
 // whole batch can be captured in a HIP graph:
-//   hash -> lookup -> verify (one wave per (query, table) bucket, at most
-//   `tile` entries each; the rest of a large bucket is cut into `tile`-sized
-//   chunks on a spill queue) -> spill (persistent waves pull chunks from the
-//   queue) -> CSR offsets -> scatter into per-query segments -> per-query
-//   sort (ids ascending).  Skewed buckets (1 to 1e5 candidates) thus spread
-//   over all CUs.  Counters are cleared by fill kernels, never by memset
-//   nodes, so graph replays start clean.
+//   hash -> verify (each lane takes one (query, table) item: it probes the
+//   directory and, when the bin holds at most kLaneBin entries, scans it and
+//   verifies the bucket itself; a larger bin is cut into `tile`-sized chunks
+//   on a spill queue) -> spill (persistent waves verify one chunk at a time,
+//   a lane per entry) -> CSR offsets -> scatter into per-query segments ->
+//   per-query sort (ids ascending).  Small buckets thus cost one lane, not one
+//   wave, and skewed buckets (1 to 1e5 candidates) spread over all CUs.
+//   Counters are cleared by fill kernels, never by memset nodes, so graph
+//   replays start clean.
 #include <algorithm>
 
 #include "common.h"
@@ -89,12 +91,12 @@ struct VerifyArgs {
     int64_t nq;
     const int32_t *rq_vec;  // per-query radius, or null: rq for all
     int rq;
-    const uint32_t *tkeys, *tids;
+    const uint32_t *tkeys, *tids, *dir;
     int64_t n;
-    const uint32_t *qkeys;                   // [L][nq]
-    const uint32_t *rstart, *rlen, *rmatch;  // [nq][L]
+    int dir_bits;
+    const uint32_t *qkeys;  // [L][nq]
     QueryCtrl *ctrl;
-    uint4 *spill;  // (item, begin, end, 0)
+    uint4 *spill;  // (item, begin, end, 0): absolute positions in the item's table
     int64_t spill_cap;
     uint32_t *out_q, *out_id;
     int64_t pair_cap;
@@ -102,47 +104,66 @@ struct VerifyArgs {
     uint32_t tile;
 };
 
-// Verifies entries [j0, j1) of (query qi, table T)'s bin; reports near points
-// whose first shared table is T.  Whole wave, uniform arguments.
+// Bins of at most this many entries are scanned by one lane.
+constexpr uint32_t kLaneBin = 32;
+
+__device__ inline int query_radius(const VerifyArgs &a, int64_t qi) { return a.rq_vec ? a.rq_vec[qi] : a.rq; }
+
+// popcount(x XOR q) over the W words (pad bits masked).
+__device__ inline int hamming(const uint64_t *x, const uint64_t *q, int W, uint64_t last_mask) {
+    int dist = 0;
+    for (int w = 0; w < W; ++w) {
+        uint64_t df = x[w] ^ q[w];
+        if (w == W - 1) df &= last_mask;
+        dist += __popcll(df);
+    }
+    return dist;
+}
+
+// Records (qi, id) for the lanes of the wave that call it together: one
+// atomic per wave for the pair slots (the first active lane takes them).
+__device__ inline void emit_pair(const VerifyArgs &a, int64_t qi, uint32_t id) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t act = __ballot(1);
+    const int leader = __builtin_ctzll(act);
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(&a.ctrl->pairs, (unsigned long long)__popcll(act));
+    base = __shfl(base, leader, 64);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const unsigned long long slot = base + __popcll(act & lt);
+    atomicAdd(&a.qcount[qi], 1u);
+    if (slot < (unsigned long long)a.pair_cap) {
+        a.out_q[slot] = uint32_t(qi);
+        a.out_id[slot] = id;
+    }
+}
+
+// Checks one bin entry j of table T against query qi: same key, within the
+// query's radius, and T is the first table the two share (dedupe).
+__device__ inline bool near_in_table(const VerifyArgs &a, int64_t qi, int T, uint32_t qkey, int rq, uint32_t key,
+                                     uint32_t id) {
+    if (key != qkey) return false;
+    const uint64_t *xp = a.pts + int64_t(id) * a.W;
+    const uint64_t *qp = a.queries + qi * a.W;
+    if (hamming(xp, qp, a.W, a.last_mask) > rq) return false;
+    return first_shared_table(xp, qp, a.W, a.part, a.col, a.t, a.mbits, a.Lp, a.last_mask) == T;
+}
+
+// Whole wave, uniform arguments: entries [j0, j1) of table T (absolute
+// positions), a lane per entry.
 __device__ inline void verify_range(const VerifyArgs &a, int64_t qi, int T, uint32_t j0, uint32_t j1) {
     const int lane = threadIdx.x & 63;
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
-    const uint32_t st = a.rstart[qi * a.L + T];
-    const uint64_t *qp = a.queries + qi * a.W;
-    const uint32_t *ids = a.tids + int64_t(T) * a.n + st;
-    const uint32_t *bk = a.tkeys + int64_t(T) * a.n + st;
-    const int rq = a.rq_vec ? a.rq_vec[qi] : a.rq;
+    const uint32_t *ids = a.tids + int64_t(T) * a.n;
+    const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
+    const int rq = query_radius(a, qi);
     for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
         const uint32_t j = b0 + lane;
-        bool emit = false;
-        uint32_t id = 0;
-        if (j < j1 && bk[j] == qkey) {
-            id = ids[j];
-            const uint64_t *xp = a.pts + int64_t(id) * a.W;
-            int dist = 0;
-            for (int w = 0; w < a.W; ++w) {
-                uint64_t df = xp[w] ^ qp[w];
-                if (w == a.W - 1) df &= a.last_mask;
-                dist += __popcll(df);
-            }
-            if (dist <= rq)
-                emit = first_shared_table(xp, qp, a.W, a.part, a.col, a.t, a.mbits, a.Lp, a.last_mask) == T;
-        }
-        const uint64_t bal = __ballot(emit);
-        if (bal) {
-            unsigned long long base = 0;
-            if (lane == 0) {
-                base = atomicAdd(&a.ctrl->pairs, (unsigned long long)__popcll(bal));
-                atomicAdd(&a.qcount[qi], uint32_t(__popcll(bal)));
-            }
-            base = __shfl(base, 0, 64);
-            if (emit) {
-                const unsigned long long slot = base + __popcll(bal & lt);
-                if (slot < (unsigned long long)a.pair_cap) {
-                    a.out_q[slot] = uint32_t(qi);
-                    a.out_id[slot] = id;
-                }
+        if (j < j1) {
+            const uint32_t key = bk[j];
+            if (key == qkey) {
+                const uint32_t id = ids[j];
+                if (near_in_table(a, qi, T, qkey, rq, key, id)) emit_pair(a, qi, id);
             }
         }
     }
@@ -193,50 +214,57 @@ __global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill,
     }
 }
 
-// S3, pass 1: waves claim 64 (query, table) items per atomic; the lanes
-// check the 64 bucket sizes at once and the wave then verifies each
-// non-empty bucket in turn, its first `tile` entries directly and the rest as
-// tile-sized chunks on the spill queue.  Every wave leaves once the counter
+// S2 + S3, pass 1: waves claim 64 (query, table) items per atomic, a lane
+// per item.  The lane probes the directory; a bin of at most kLaneBin entries
+// is scanned and verified by the lane alone, a larger one is cut into
+// `tile`-entry chunks on the spill queue.  Every wave leaves once the counter
 // passes the number of items.
 __global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long items = (unsigned long long)(a.nq * a.L);
+    const int64_t nb = int64_t(1) << a.dir_bits;
     for (;;) {
         unsigned long long it0 = 0;
         if (lane == 0) it0 = atomicAdd(&a.ctrl->item_head, 64ull);
         it0 = __shfl(it0, 0, 64);
         if (it0 >= items) break;
-        const unsigned long long mine = it0 + lane;
-        const bool hit = mine < items && a.rmatch[mine] != 0;
-        uint64_t todo = __ballot(hit);
-        while (todo) {
-            const int k = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const unsigned long long it = it0 + k;
-            const int64_t qi = int64_t(it) / a.L;
-            const int T = int(int64_t(it) - qi * a.L);
-            const uint32_t len = a.rlen[it];
-            const uint32_t first = len < a.tile ? len : a.tile;
-            if (len > a.tile && lane == 0) {
-                const uint32_t nch = (len - first + a.tile - 1) / a.tile;
-                const unsigned long long at = atomicAdd(&a.ctrl->spills, (unsigned long long)nch);
-                for (uint32_t c = 0; c < nch; ++c) {
-                    if (at + c < (unsigned long long)a.spill_cap) {
-                        const uint32_t b = first + c * a.tile;
-                        a.spill[at + c] = make_uint4(uint32_t(it), b, min(len, b + a.tile), 0u);
-                    }
+        const unsigned long long it = it0 + lane;
+        if (it >= items) continue;
+        const int64_t qi = int64_t(it) / a.L;
+        const int T = int(int64_t(it) - qi * a.L);
+        const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
+        const uint32_t *dr = a.dir + int64_t(T) * (nb + 1);
+        const uint32_t bin = qkey >> (31 - a.dir_bits);
+        const uint32_t lo = dr[bin], hi = dr[bin + 1];
+        if (hi - lo > kLaneBin) {
+            const uint32_t nch = (hi - lo + a.tile - 1) / a.tile;
+            const unsigned long long at = atomicAdd(&a.ctrl->spills, (unsigned long long)nch);
+            for (uint32_t c = 0; c < nch; ++c)
+                if (at + c < (unsigned long long)a.spill_cap) {
+                    const uint32_t b = lo + c * a.tile;
+                    a.spill[at + c] = make_uint4(uint32_t(it), b, min(hi, b + a.tile), 0u);
                 }
+            continue;
+        }
+        const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
+        const uint32_t *ids = a.tids + int64_t(T) * a.n;
+        const int rq = query_radius(a, qi);
+        for (uint32_t j = lo; j < hi; ++j) {
+            const uint32_t key = bk[j];
+            if (key == qkey) {
+                const uint32_t id = ids[j];
+                if (near_in_table(a, qi, T, qkey, rq, key, id)) emit_pair(a, qi, id);
             }
-            verify_range(a, qi, T, 0, first);
         }
     }
 }
 
 // S3, pass 2: persistent waves drain the spill queue (every wave leaves once
-// the counter passes the number of recorded chunks).
+// the counter passes the number of recorded chunks; with no chunks, at once).
 __global__ __launch_bounds__(256) void verify_spill_kernel(VerifyArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long nsp = min((unsigned long long)a.spill_cap, a.ctrl->spills);
+    if (nsp == 0) return;
     for (;;) {
         unsigned long long k = 0;
         if (lane == 0) k = atomicAdd(&a.ctrl->spill_head, 1ull);
@@ -467,10 +495,12 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     const QueryTuning &tu = ix.tuning;
     if (nq * L > ws.cap_items || nq + 1 > ws.cap_q || !ws.ctrl || !ws.pq || !ws.spill)
         return fail(FCLSH_EINVAL, "query workspace not reserved for %lld queries", (long long)nq);
+    if (nq * L > int64_t(0xFFFFFFFF))  // spill chunks name their item in 32 bits
+        return fail(FCLSH_EINVAL, "%lld queries x %d tables exceed 2^32 items per batch", (long long)nq, L);
     hipLaunchKernelGGL(reset_kernel, dim3(grid_for(nq, 256, 1024)), dim3(256), 0, st, ws.ctrl, ws.qcount, ws.qfill,
                        nq);
     FCLSH_HIP(hipGetLastError());
-    if (nq > 0) FCLSH_TRY(query_lookup(ix, ws, queries, nq, st));
+    if (nq > 0) FCLSH_TRY(launch_hash(ix, queries, nq, ws.qkeys, nq, st));
     VerifyArgs a{};
     a.pts = ix.pts;
     a.W = ix.W;
@@ -487,11 +517,10 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.rq = rq;
     a.tkeys = ix.tkeys;
     a.tids = ix.tids;
+    a.dir = ix.dir;
     a.n = ix.n;
+    a.dir_bits = ix.dir_bits;
     a.qkeys = ws.qkeys;
-    a.rstart = ws.rstart;
-    a.rlen = ws.rlen;
-    a.rmatch = ws.rmatch;
     a.ctrl = ws.ctrl;
     a.spill = ws.spill;
     a.spill_cap = ws.cap_spill;
@@ -502,7 +531,9 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.tile = uint32_t(tu.tile);
     const unsigned vblocks = unsigned(std::max(1, tu.blocks_per_cu * ix.num_cus));
     if (nq > 0) {
-        hipLaunchKernelGGL(verify_items_kernel, dim3(vblocks), dim3(256), 0, st, a);
+        // the item pass needs no more waves than 64-item claims
+        const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 256));
+        hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(256), 0, st, a);
         FCLSH_HIP(hipGetLastError());
         hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(256), 0, st, a);
         FCLSH_HIP(hipGetLastError());

@@ -50,6 +50,7 @@ __device__ inline uint64_t lanemask_lt() {
 // lanes with ok set), from one ballot per digit bit.
 __device__ inline uint64_t same_digit_lanes(uint32_t dg, int bits, bool ok) {
     uint64_t same = __ballot(ok);
+    if (!same) return 0;  // a round without entries (wave-uniform)
     for (int b = 0; b < bits; ++b) {
         const bool on = (dg >> b) & 1u;
         const uint64_t bb = __ballot(on);
@@ -237,19 +238,127 @@ __global__ __launch_bounds__(kNT) void p1_scatter_kernel(const uint32_t *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: one workgroup per (table, super-bin).  A super-bin of at most
-// kTile entries (the usual case) is read once, ranked, reordered in LDS and
-// written out contiguously.  A larger one gets a histogram read first and is
-// then scattered chunk by chunk with running digit starts.
+// Pass 2: one workgroup per (table, super-bin).
+//
+// Fast path (a super-bin of at most kTile entries whose bins all hold at most
+// kMaxFastBin entries -- the usual case): every entry takes a slot inside its
+// bin with one LDS atomic (slots in arbitrary order), the block scans the bin
+// counts into bin starts (the directory entries), the ids are placed in LDS
+// by slot, and each entry's final position is its bin start plus the number
+// of ids in its bin smaller than its own (ids are distinct; bins hold a
+// handful of entries).  Keys, then ids, are reordered through LDS and the
+// super-bin is written out contiguously.  The result equals the stable
+// reorder exactly.
+//
+// Otherwise the stable path: wave-ballot ranks in input order (pass 1 is
+// stable, so input order is id order), an LDS reorder, and for super-bins
+// over kTile entries a histogram read first and a chunk-by-chunk scatter with
+// running digit starts.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kNT) void p2_bucket_kernel(const uint32_t *__restrict__ ikeys,
-                                                        const uint32_t *__restrict__ iids, int64_t n,
-                                                        const uint32_t *__restrict__ bstart, int lo_bits,
-                                                        uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
-                                                        uint32_t *__restrict__ dir) {
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t sh[kWaves + 1];
-    const int R = 1 << lo_bits;
+constexpr uint32_t kMaxFastBin = 48;
+
+struct P2Args {
+    const uint32_t *kin, *vin;  // the super-bin's input run (table offset applied)
+    uint32_t *okey, *oid;       // the super-bin's output run
+    uint32_t *dr;               // directory entries of the super-bin's bins
+    uint32_t count;             // entries in the super-bin
+    uint32_t bs;                // super-bin start within the table
+    int shift, lo_bits;
+    uint32_t mask;
+};
+
+// Block-wide maximum of one value per thread.
+__device__ inline uint32_t block_max_u32(uint32_t v, uint32_t *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, uint32_t(__shfl_xor(v, o, 64)));
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    uint32_t m = 0;
+    for (int w = 0; w < kWaves; ++w) m = max(m, sh[w]);
+    __syncthreads();
+    return m;
+}
+
+// Fast path; returns false (having written nothing to the tables) when a bin
+// is too large for the per-entry rank count.
+__device__ bool p2_fast(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+    const int R = 1 << a.lo_bits;
+    uint32_t *buf = lds;  // kTile words: ids in slot order, then keys, then ids in final order
+    uint32_t *cnt = lds + kTile;
+    uint32_t *start = cnt + R;
+    for (int i = threadIdx.x; i < R; i += kNT) cnt[i] = 0;
+    __syncthreads();
+    uint32_t rk[kItems], rv[kItems], pos[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
+        const bool ok = e < a.count;
+        rk[it] = ok ? a.kin[e] : 0u;
+        rv[it] = ok ? a.vin[e] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (uint32_t(it * kNT) >= a.count) break;  // block-uniform
+        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
+        pos[it] = e < a.count ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
+    }
+    __syncthreads();
+    uint32_t mx = 0;
+    for (int i = threadIdx.x; i < R; i += kNT) {
+        mx = max(mx, cnt[i]);
+        start[i] = cnt[i];
+    }
+    if (block_max_u32(mx, sh) > kMaxFastBin) return false;
+    digit_starts(start, R, 0u, sh);
+    for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
+    // ids into their bins, in slot order
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (uint32_t(it * kNT) >= a.count) break;
+        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
+        if (e < a.count) {
+            pos[it] += start[(rk[it] >> a.shift) & a.mask];
+            buf[pos[it]] = rv[it];
+        }
+    }
+    __syncthreads();
+    // final position = bin start + number of ids in the bin smaller than
+    // this one (ids are distinct): independent LDS reads, no serial chain
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (uint32_t(it * kNT) >= a.count) break;
+        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
+        if (e < a.count) {
+            const uint32_t dg = (rk[it] >> a.shift) & a.mask;
+            const uint32_t b0 = start[dg], m = cnt[dg];
+            uint32_t r = 0;
+            for (uint32_t k = 0; k < m; ++k) r += buf[b0 + k] < rv[it] ? 1u : 0u;
+            pos[it] = b0 + r;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (uint32_t(it * kNT) >= a.count) break;
+        if (uint32_t(it * kNT) + threadIdx.x < a.count) buf[pos[it]] = rk[it];
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < a.count; j += kNT) a.okey[j] = buf[j];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (uint32_t(it * kNT) >= a.count) break;
+        if (uint32_t(it * kNT) + threadIdx.x < a.count) buf[pos[it]] = rv[it];
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < a.count; j += kNT) a.oid[j] = buf[j];
+    return true;
+}
+
+// Stable path for a super-bin of at most kTile entries.
+__device__ void p2_stable_single(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+    const int R = 1 << a.lo_bits;
     // region A (kTile*2 words): first the per-wave counters [kWaves][R], then
     // the reordered keys and ids; region B: start[R], tot[R]
     uint32_t *wc = lds;
@@ -257,66 +366,58 @@ __global__ __launch_bounds__(kNT) void p2_bucket_kernel(const uint32_t *__restri
     uint32_t *rid = lds + kTile;
     uint32_t *start = lds + 2 * kTile;
     uint32_t *tot = start + R;
-
-    const int T = blockIdx.y, sb = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int shift = 31 - kHiBits - lo_bits;
-    const uint32_t mask = uint32_t(R - 1);
-    const int64_t toff = int64_t(T) * n;
-    const uint32_t bs = bstart[int64_t(T) * (kHiBins + 1) + sb];
-    const uint32_t be = bstart[int64_t(T) * (kHiBins + 1) + sb + 1];
-    const uint32_t *kin = ikeys + toff;
-    const uint32_t *vin = iids + toff;
-    uint32_t *dr = dir + int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1);
-    const bool single = (be - bs) <= uint32_t(kTile);
-    if (sb == kHiBins - 1 && threadIdx.x == 0) dr[int64_t(kHiBins) << lo_bits] = uint32_t(n);
-
-    if (single) {
-        for (int i = threadIdx.x; i < kWaves * R; i += kNT) wc[i] = 0;
-        __syncthreads();
-        uint32_t rk[kItems], rv[kItems], dg[kItems], rank[kItems];
-        bool ok[kItems];
+    for (int i = threadIdx.x; i < kWaves * R; i += kNT) wc[i] = 0;
+    __syncthreads();
+    uint32_t rk[kItems], rv[kItems], dg[kItems], rank[kItems];
+    bool ok[kItems];
 #pragma unroll
-        for (int it = 0; it < kItems; ++it) {
-            const uint32_t e = bs + uint32_t(wave * (64 * kItems) + it * 64 + lane);
-            ok[it] = e < be;
-            rk[it] = ok[it] ? kin[e] : 0u;
-            rv[it] = ok[it] ? vin[e] : 0u;
-            dg[it] = (rk[it] >> shift) & mask;
-        }
-        wave_stable_ranks<kItems>(dg, ok, lo_bits, wc + wave * R, rank);
-        __syncthreads();
-        wave_offsets(wc, R, tot);
-        __syncthreads();
-        for (int i = threadIdx.x; i < R; i += kNT) start[i] = tot[i];
-        __syncthreads();
-        digit_starts(start, R, 0u, sh);
-        for (int i = threadIdx.x; i < R; i += kNT) dr[(int64_t(sb) << lo_bits) + i] = bs + start[i];
-#pragma unroll
-        for (int it = 0; it < kItems; ++it)
-            if (ok[it]) rank[it] += start[dg[it]] + wc[wave * R + dg[it]];
-        __syncthreads();  // the counters' space becomes the reorder buffer
-#pragma unroll
-        for (int it = 0; it < kItems; ++it)
-            if (ok[it]) {
-                rkey[rank[it]] = rk[it];
-                rid[rank[it]] = rv[it];
-            }
-        __syncthreads();
-        for (uint32_t j = threadIdx.x; j < be - bs; j += kNT) {
-            tkeys[toff + bs + j] = rkey[j];
-            tids[toff + bs + j] = rid[j];
-        }
-        return;
+    for (int it = 0; it < kItems; ++it) {
+        const uint32_t e = uint32_t(wave * (64 * kItems) + it * 64 + lane);
+        ok[it] = e < a.count;
+        rk[it] = ok[it] ? a.kin[e] : 0u;
+        rv[it] = ok[it] ? a.vin[e] : 0u;
+        dg[it] = (rk[it] >> a.shift) & a.mask;
     }
+    wave_stable_ranks<kItems>(dg, ok, a.lo_bits, wc + wave * R, rank);
+    __syncthreads();
+    wave_offsets(wc, R, tot);
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += kNT) start[i] = tot[i];
+    __syncthreads();
+    digit_starts(start, R, 0u, sh);
+    for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+        if (ok[it]) rank[it] += start[dg[it]] + wc[wave * R + dg[it]];
+    __syncthreads();  // the counters' space becomes the reorder buffer
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+        if (ok[it]) {
+            rkey[rank[it]] = rk[it];
+            rid[rank[it]] = rv[it];
+        }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
+        a.okey[j] = rkey[j];
+        a.oid[j] = rid[j];
+    }
+}
 
+// Stable path for a super-bin of more than kTile entries.
+__device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+    const int R = 1 << a.lo_bits;
+    uint32_t *wc = lds;
+    uint32_t *start = lds + 2 * kTile;
+    uint32_t *tot = start + R;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < R; i += kNT) start[i] = 0;
     __syncthreads();
-    for (uint32_t e = bs + threadIdx.x; e < be; e += kNT) atomicAdd(&start[(kin[e] >> shift) & mask], 1u);
+    for (uint32_t e = threadIdx.x; e < a.count; e += kNT) atomicAdd(&start[(a.kin[e] >> a.shift) & a.mask], 1u);
     __syncthreads();
-    digit_starts(start, R, bs, sh);
-    for (int i = threadIdx.x; i < R; i += kNT) dr[(int64_t(sb) << lo_bits) + i] = start[i];
-    for (uint32_t c0 = bs; c0 < be; c0 += kTile) {
+    digit_starts(start, R, 0u, sh);
+    for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
+    for (uint32_t c0 = 0; c0 < a.count; c0 += kTile) {
         for (int i = threadIdx.x; i < kWaves * R; i += kNT) wc[i] = 0;
         __syncthreads();
         uint32_t dg[kItems], rank[kItems];
@@ -324,10 +425,10 @@ __global__ __launch_bounds__(kNT) void p2_bucket_kernel(const uint32_t *__restri
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
             const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
-            ok[it] = e < be;
-            dg[it] = ok[it] ? (kin[e] >> shift) & mask : 0u;
+            ok[it] = e < a.count;
+            dg[it] = ok[it] ? (a.kin[e] >> a.shift) & a.mask : 0u;
         }
-        wave_stable_ranks<kItems>(dg, ok, lo_bits, wc + wave * R, rank);
+        wave_stable_ranks<kItems>(dg, ok, a.lo_bits, wc + wave * R, rank);
         __syncthreads();
         wave_offsets(wc, R, tot);
         __syncthreads();
@@ -335,14 +436,68 @@ __global__ __launch_bounds__(kNT) void p2_bucket_kernel(const uint32_t *__restri
         for (int it = 0; it < kItems; ++it)
             if (ok[it]) {
                 const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
-                const int64_t dst = toff + int64_t(start[dg[it]]) + wc[wave * R + dg[it]] + rank[it];
-                tkeys[dst] = kin[e];
-                tids[dst] = vin[e];
+                const uint32_t dst = start[dg[it]] + wc[wave * R + dg[it]] + rank[it];
+                a.okey[dst] = a.kin[e];
+                a.oid[dst] = a.vin[e];
             }
         __syncthreads();
         for (int d = threadIdx.x; d < R; d += kNT) start[d] += tot[d];
         __syncthreads();
     }
+}
+
+__device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *bstart,
+                                 int lo_bits, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, int T, int sb) {
+    const int64_t toff = int64_t(T) * n;
+    const uint32_t bs = bstart[int64_t(T) * (kHiBins + 1) + sb];
+    const uint32_t be = bstart[int64_t(T) * (kHiBins + 1) + sb + 1];
+    P2Args a;
+    a.kin = ikeys + toff + bs;
+    a.vin = iids + toff + bs;
+    a.okey = tkeys + toff + bs;
+    a.oid = tids + toff + bs;
+    a.dr = dir + int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1) + (int64_t(sb) << lo_bits);
+    a.count = be - bs;
+    a.bs = bs;
+    a.lo_bits = lo_bits;
+    a.shift = 31 - kHiBits - lo_bits;
+    a.mask = (1u << lo_bits) - 1u;
+    return a;
+}
+
+// Pass 2, fast path over every (table, super-bin); flags[T][sb] = 1 marks the
+// super-bins left to p2_rest_kernel (over kTile entries or a large bin).
+__global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restrict__ ikeys,
+                                                         const uint32_t *__restrict__ iids, int64_t n,
+                                                         const uint32_t *__restrict__ bstart, int lo_bits,
+                                                         uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
+                                                         uint32_t *__restrict__ dir, uint32_t *__restrict__ flags) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ uint32_t sh[kWaves + 1];
+    const int T = blockIdx.y, sb = blockIdx.x;
+    if (sb == kHiBins - 1 && threadIdx.x == 0)
+        dir[int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1) + (int64_t(kHiBins) << lo_bits)] = uint32_t(n);
+    const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
+    const bool done = a.count <= uint32_t(kTile) && p2_fast(a, lds, sh);
+    if (threadIdx.x == 0) flags[int64_t(T) * kHiBins + sb] = done ? 0u : 1u;
+}
+
+// Pass 2, stable path for the super-bins the fast path left.
+__global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys,
+                                                         const uint32_t *__restrict__ iids, int64_t n,
+                                                         const uint32_t *__restrict__ bstart, int lo_bits,
+                                                         uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
+                                                         uint32_t *__restrict__ dir,
+                                                         const uint32_t *__restrict__ flags) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ uint32_t sh[kWaves + 1];
+    const int T = blockIdx.y, sb = blockIdx.x;
+    if (!flags[int64_t(T) * kHiBins + sb]) return;
+    const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
+    if (a.count > uint32_t(kTile))
+        p2_stable_chunked(a, lds, sh);
+    else
+        p2_stable_single(a, lds, sh);
 }
 
 }  // namespace
@@ -356,9 +511,10 @@ int table_dir_bits(int64_t n) {
     return b;
 }
 
+// tile histograms [L][tiles][256], super-bin starts [L][257], pass-2 flags [L][256]
 size_t table_build_scratch_bytes(int64_t L, int64_t n) {
     const int64_t nblk = (n + kTile - 1) / kTile;
-    return size_t(L) * nblk * kHiBins * 4 + size_t(L) * (kHiBins + 1) * 4;
+    return size_t(L) * nblk * kHiBins * 4 + size_t(L) * (kHiBins + 1) * 4 + size_t(L) * kHiBins * 4;
 }
 
 fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
@@ -370,6 +526,7 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     const int nblk = int((n + kTile - 1) / kTile);
     uint32_t *hist = scratch;
     uint32_t *bstart = scratch + size_t(L) * nblk * kHiBins;
+    uint32_t *flags = bstart + size_t(L) * (kHiBins + 1);
     hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
@@ -382,10 +539,15 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     if (marks) FCLSH_HIP(hipEventRecord(marks[2], st));
     const int lo_bits = dir_bits - kHiBits;
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
-    hipLaunchKernelGGL(p2_bucket_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
-                       lo_bits, tkeys, tids, dir);
+    const size_t lds_fast = (size_t(kTile) + 2 * (size_t(1) << lo_bits)) * 4;
+    hipLaunchKernelGGL(p2_fast_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds_fast, st, tmpk, tmpv, n, bstart,
+                       lo_bits, tkeys, tids, dir, flags);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
+    hipLaunchKernelGGL(p2_rest_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
+                       lo_bits, tkeys, tids, dir, flags);
+    FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
     return FCLSH_OK;
 }
 
