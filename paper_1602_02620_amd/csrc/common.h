@@ -71,7 +71,6 @@ struct DevBuf {
 struct HashPlan {
     int logD = 1, logV = 1, G = 1, V = 2, U = 64, t = 1, E = 0, W = 1;
     bool specific = true;        // at most one coordinate per Hadamard column
-    int blocks_per_part_cap = 2048;
     int32_t *seg = nullptr;      // [t][V+1] entry ranges per in-lane column k
     uint2 *gtab = nullptr;       // [t][E][G] (even representative of b mod P, coordinate)
 };
@@ -139,6 +138,21 @@ fclsh_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in,
 // optional) receives the sum.
 fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *total,
                                 Scratch &scr, hipStream_t st);
+
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn.  The
+// streaming kernels map workgroup b of a 1-D grid (a multiple of kXcds) to
+// work item (b % 8) * (grid / 8) + b / 8, so each XCD takes a contiguous range
+// of items in order: writes of neighbouring items that share cache lines (the
+// runs of one digit from neighbouring pass-1 tiles, the boundaries of
+// neighbouring super-bins, the row segments of neighbouring point groups)
+// meet in the same L2, which merges them before they go to HBM.
+constexpr int kXcds = 8;
+
+__device__ inline int64_t xcd_contiguous_item(unsigned b, unsigned grid) {
+    return int64_t(b % kXcds) * (grid / kXcds) + b / kXcds;
+}
+
+inline int64_t xcd_grid(int64_t nitems) { return (nitems + kXcds - 1) / kXcds * kXcds; }
 
 // Table build (tables.hip): keys [L][n] -> tables grouped by the top dir_bits
 // key bits, ids ascending per bin, plus the directory [L][2^dir_bits + 1].

@@ -15,10 +15,10 @@
 //   * each b_c enters the sketch as its even representative b''_c in [0, 2P)
 //     (b'' = b if b is even, else b + P), i.e. 2 * (b / 2 mod P); then
 //     S'' - F''_v = 2 * y with y = (S - F_v)/2 (mod P) and y < 2^42;
-//   * z = (S'' + 2^52) - F''_v holds 2y in the low 52 mantissa bits, so
-//     lo32(z) >> 1 = y mod 2^31 and hi32(z) & 0xFFFFF = y >> 31; since
-//     2^31 = 1 (mod P) the key is their sum, reduced by one conditional
-//     subtraction of P.
+//   * z = (S'' + 2^52) - F''_v = 2^52 + 2y exactly (the exponent word is
+//     fixed), so lo32(z) >> 1 = y mod 2^31 and hi32(z) - hi32(2^52) = y >> 31;
+//     since 2^31 = 1 (mod P) the key is their sum, reduced by one
+//     conditional subtraction of P.
 //
 // Layout.  A "unit" is one (point, part).  G lanes cooperate on a unit and
 // each holds V = D/G sketch entries in registers: lane sub-index s owns
@@ -34,6 +34,13 @@ namespace fclsh {
 namespace {
 
 constexpr double kTwo52 = 4503599627370496.0;
+constexpr uint32_t kHiWord52 = 0x43300000u;  // high word of 2^52 as a double
+
+// All ones if coordinate c (bit c & 31 of word c >> 5 of the staged point x)
+// is set, else zero.
+__device__ inline uint32_t coord_mask(const uint32_t *x, uint32_t c) {
+    return uint32_t(__builtin_amdgcn_sbfe(int32_t(x[c >> 5]), c & 31u, 1u));
+}
 
 // Shape of one launch: V = 2^LOGV sketch entries per lane, G lanes per unit
 // (point, part), U = 64/G units per wave.
@@ -114,7 +121,7 @@ __device__ inline void swap_f64(double &a, double &b) {
 template <int LOGD, int LOGV, int B>
 __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
     using S = Shape<LOGD, LOGV>;
-    if constexpr (B >= 0) {
+    if constexpr (B < S::LOGG) {
         constexpr int dist = S::U << B;
         if constexpr (S::swap_stage(B)) {
             constexpr int q = S::swap_reg(B);
@@ -132,19 +139,42 @@ __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
 #pragma unroll
             for (int k = 0; k < S::V; ++k) t[k] = fma(sgn, t[k], dpp_f64(t[k], dist));
         }
-        cross_stages<LOGD, LOGV, B - 1>(t, lane);
+        cross_stages<LOGD, LOGV, B + 1>(t, lane);
     }
 }
 
-// One workgroup of 4 waves per (part, slice of point groups); each wave
-// takes groups of U consecutive points in a grid-stride loop.  The part's
+// LDS staging of a block's keys: D-1 rows (row v-1 for v = 1..D-1) of
+// PB = 4U points.  Rows are PB + 1 words apart with PAD more words every 32
+// values of v, so that the 64 lanes of one staging store (rows that differ in
+// high index bits) fall into distinct bank pairs; PAD per Hadamard order from
+// a bank model of those stores.  Since v >> 5 is additive over the disjoint
+// bits v = vlane | vreg, a lane's 32 stores are one base plus constants.
+template <int LOGD>
+constexpr int stage_pad() { return LOGD == 9 ? 2 : 1; }
+
+template <int LOGD, int U>
+__device__ __host__ constexpr int stage_index(int row, int col) {
+    return row * (4 * U + 1) + ((row + 1) >> 5) * stage_pad<LOGD>() + col;
+}
+
+template <int LOGD, int U>
+constexpr size_t stage_words() {
+    return size_t(stage_index<LOGD, U>((1 << LOGD) - 2, 4 * U - 1)) + 1;
+}
+
+// One workgroup of 4 waves per (part, 4 consecutive point groups), in
+// XCD-contiguous order; each wave takes one group of U consecutive points and
+// the block writes the keys of its 4U points out together.  Short-lived
+// waves keep every SIMD full: a grid-stride loop over groups measured 1.9x
+// slower on the mid workload.  The part's
 // gather table (per in-lane column k and sub-lane s, the coordinate feeding
 // it and its even representative b'') is staged in LDS once per workgroup.
 template <int LOGD, int LOGV, bool SPECIFIC>
 __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restrict__ pts, int64_t m, int W,
                                                        const int32_t *__restrict__ seg,
                                                        const uint2 *__restrict__ gtab, int E,
-                                                       uint32_t *__restrict__ keys, int64_t key_stride) {
+                                                       uint32_t *__restrict__ keys, int64_t key_stride,
+                                                       int64_t nblk, int64_t nitems) {
     using S = Shape<LOGD, LOGV>;
     constexpr int V = S::V, G = S::G, U = S::U, D = S::D;
     extern __shared__ __align__(16) uint32_t lds[];
@@ -152,7 +182,11 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     const int wave = threadIdx.x >> 6;
     const int s = lane >> S::LOGU;
     const int u = lane & (U - 1);
-    const int p = blockIdx.y;
+    // work item: (part p, block of 4 point groups), XCD-contiguous
+    const int64_t witem = xcd_contiguous_item(blockIdx.x, gridDim.x);
+    if (witem >= nitems) return;  // grid padding
+    const int p = int(witem / nblk);
+    const int64_t g0 = (witem % nblk) * 4;
     const int stride = 2 * W + 1;
     uint2 *tab = reinterpret_cast<uint2 *>(lds);
     uint32_t *wx = lds + 2 * E * G + wave * U * stride;
@@ -166,80 +200,107 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     for (int b = 0; b < S::LOGG; ++b)
         if ((lane >> (S::LOGU + b)) & 1) vlane |= 1 << (S::swap_stage(b) ? S::swap_reg(b) : LOGV + b);
 
+    // The block's keys are staged in LDS as (D-1) rows of 4U points, then
+    // written out row by row: 4U consecutive points of a table per row
+    // segment instead of the U of one wave.
+    uint32_t *stage = lds + 2 * E * G + 4 * U * stride;
     const int64_t ngroups = (m + U - 1) / U;
-    for (int64_t grp = int64_t(blockIdx.x) * 4 + wave; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
+    {
+        const int64_t grp = g0 + wave;
         const int64_t base = grp * U;
-        for (int e = lane; e < U * W; e += 64) {
-            const int uu = e / W, w = e - uu * W;
-            const int64_t i = base + uu;
-            const uint64_t v = (i < m) ? pts[i * W + w] : 0ull;
-            wx[uu * stride + 2 * w] = uint32_t(v);
-            wx[uu * stride + 2 * w + 1] = uint32_t(v >> 32);
-        }
-        if (lane < U) wx[lane * stride + 2 * W] = 0u;
-        __asm__ volatile("" ::: "memory");
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t *myx = wx + u * stride;
-
-        // Sketch (Alg. 2)
-        double t[V];
-        if constexpr (SPECIFIC) {
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const uint2 en = tab[k * G + s];
-                const uint32_t bit = (myx[en.y >> 5] >> (en.y & 31)) & 1u;
-                t[k] = double(bit ? en.x : 0u);
+        if (grp < ngroups) {  // wave-uniform
+            for (int e = lane; e < U * W; e += 64) {
+                const int uu = e / W, w = e - uu * W;
+                const int64_t i = base + uu;
+                const uint64_t v = (i < m) ? pts[i * W + w] : 0ull;
+                wx[uu * stride + 2 * w] = uint32_t(v);
+                wx[uu * stride + 2 * w + 1] = uint32_t(v >> 32);
             }
-        } else {
-            const int32_t *sg = seg + p * (V + 1);
+            if (lane < U) wx[lane * stride + 2 * W] = 0u;
+            __asm__ volatile("" ::: "memory");
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t *myx = wx + u * stride;
+
+            // Sketch (Alg. 2)
+            double t[V];
+            if constexpr (SPECIFIC) {
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                double acc = 0.0;
-                const int e1 = sg[k + 1];
-                for (int e = sg[k]; e < e1; ++e) {
-                    const uint2 en = tab[e * G + s];
-                    const uint32_t bit = (myx[en.y >> 5] >> (en.y & 31)) & 1u;
-                    acc += double(bit ? en.x : 0u);
+                for (int k = 0; k < V; ++k) {
+                    const uint2 en = tab[k * G + s];
+                    t[k] = double(en.x & coord_mask(myx, en.y));
                 }
-                t[k] = acc;
-            }
-        }
-        __asm__ volatile("" ::: "memory");
-        __builtin_amdgcn_wave_barrier();
-
-        // Fast Hadamard transform (Alg. 2): in-register stages ...
+            } else {
+                const int32_t *sg = seg + p * (V + 1);
 #pragma unroll
-        for (int h = 1; h < V; h <<= 1) {
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                if (!(k & h)) {
-                    const double a = t[k], b = t[k | h];
-                    t[k] = a + b;
-                    t[k | h] = a - b;
+                for (int k = 0; k < V; ++k) {
+                    double acc = 0.0;
+                    const int e1 = sg[k + 1];
+                    for (int e = sg[k]; e < e1; ++e) {
+                        const uint2 en = tab[e * G + s];
+                        acc += double(en.x & coord_mask(myx, en.y));
+                    }
+                    t[k] = acc;
                 }
             }
-        }
-        // ... then the stages across the G lanes of a unit
-        cross_stages<LOGD, LOGV, S::LOGG - 1>(t, lane);
+            __asm__ volatile("" ::: "memory");
+            __builtin_amdgcn_wave_barrier();
 
-        // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
-        const double Sm = __shfl(t[0], u, 64) + kTwo52;
-        const int64_t i = base + u;
-        if (i < m) {
-            uint32_t *out = keys + (int64_t(p) * (D - 1) + vlane - 1) * key_stride + i;
+            // Fast Hadamard transform (Alg. 2): in-register stages ...
+#pragma unroll
+            for (int h = 1; h < V; h <<= 1) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    if (!(k & h)) {
+                        const double a = t[k], b = t[k | h];
+                        t[k] = a + b;
+                        t[k | h] = a - b;
+                    }
+                }
+            }
+            // ... then the stages across the G lanes of a unit, nearest partners
+            // first (the stages commute; this order keeps the register pressure of
+            // the DPP stages away from the key extraction)
+            cross_stages<LOGD, LOGV, 0>(t, lane);
+
+            // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
+            const double Sm = __shfl(t[0], u, 64) + kTwo52;
+            // stage_index(vlane + vr - 1, wave * U + u), split into a lane base and
+            // a per-register constant
+            constexpr int RS = 4 * U + 1, PAD = stage_pad<LOGD>();
+            const int sbase = (vlane - 1) * RS + (vlane >> 5) * PAD + wave * U + u;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                constexpr int dummy = 0;
-                (void)dummy;
                 const int vr = S::vreg(k);
                 if (vr == 0 && vlane == 0) continue;  // row 0: all-zero codeword, dropped
+                // z = 2^52 + 2y exactly, 2y < 2^44: the high word is the exponent
+                // word kHiWord52 plus 2y >> 32, so y mod P (2^31 = 1) is
+                // (lo >> 1) + hi - kHiWord52, below 2P
                 const double z = Sm - t[k];
                 const uint64_t zb = __double_as_longlong(z);
-                uint32_t y = (uint32_t(zb) >> 1) + (uint32_t(zb >> 32) & 0xFFFFFu);
-                y = min(y, y - kPrime);
-                out[int64_t(vr) * key_stride] = y;
+                const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
+                const uint32_t y = min(half + hi - kHiWord52, half + hi - (kHiWord52 + kPrime));
+                stage[sbase + vr * RS + (vr >> 5) * PAD] = y;
             }
         }
+        __syncthreads();
+        {
+            // thread t writes column t % PB of rows t / PB, t / PB + 256 / PB, ...
+            // (PB = 256 / G divides the block)
+            constexpr int PB = 4 * U;
+            constexpr int RSTEP = 256 / PB;
+            const int col = threadIdx.x % PB;
+            const int64_t i = g0 * U + col;
+            int row = threadIdx.x / PB;
+            if (i < m && row < D - 1) {
+                uint32_t *dst = keys + (int64_t(p) * (D - 1) + row) * key_stride + i;
+                const int64_t dstep = int64_t(RSTEP) * key_stride;
+                for (; row < D - 1; row += RSTEP) {
+                    *dst = stage[stage_index<LOGD, U>(row, col)];
+                    dst += dstep;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -248,19 +309,20 @@ fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t 
                       hipStream_t st) {
     using S = Shape<LOGD, LOGV>;
     const HashPlan &pl = ix.plan;
-    const size_t lds = size_t(pl.E) * S::G * 8 + size_t(4) * S::U * (2 * pl.W + 1) * 4;
+    const size_t lds = size_t(pl.E) * S::G * 8 + size_t(4) * S::U * (2 * pl.W + 1) * 4 +
+                       stage_words<LOGD, S::U>() * 4;
     if (lds > 160 * 1024) return fail(FCLSH_EUNSUPPORTED, "hash kernel LDS need %zu bytes", lds);
     const int64_t ngroups = (m + S::U - 1) / S::U;
-    int64_t nblk = (ngroups + 3) / 4;
-    const int64_t cap = int64_t(pl.blocks_per_part_cap);
-    if (nblk > cap) nblk = cap;
-    dim3 grid(unsigned(nblk), unsigned(pl.t));
+    const int64_t nblk = (ngroups + 3) / 4;  // blocks of 4 point groups per part
+    const int64_t nitems = nblk * pl.t;
+    const int64_t grid = xcd_grid(nitems);
+    if (grid > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "%lld points need too many workgroups", (long long)m);
     if (pl.specific)
-        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, true>), grid, dim3(256), lds, st, pts, m, pl.W, pl.seg,
-                           pl.gtab, pl.E, keys, key_stride);
+        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, true>), dim3(unsigned(grid)), dim3(256), lds, st, pts, m,
+                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems);
     else
-        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, false>), grid, dim3(256), lds, st, pts, m, pl.W, pl.seg,
-                           pl.gtab, pl.E, keys, key_stride);
+        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, false>), dim3(unsigned(grid)), dim3(256), lds, st, pts, m,
+                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
@@ -323,11 +385,6 @@ fclsh_status build_hash_plan(Index *ix) {
                 }
             }
     }
-    // One point group per wave: short-lived waves keep every SIMD full (a
-    // grid-stride loop over groups measured 1.9x slower on the mid workload,
-    // its waves serialising staging loads and compute).  The cap only bounds
-    // the grid for very large batches.
-    pl.blocks_per_part_cap = 1 << 30;
     FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.seg), seg.size() * 4, "hash plan"));
     FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.gtab), tab.size() * 4, "hash plan"));
     FCLSH_HIP(hipMemcpy(pl.seg, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));

@@ -25,11 +25,17 @@ namespace fclsh {
 
 namespace {
 
-constexpr int kNT = 512;                 // threads of the ranking kernels
-constexpr int kWaves = kNT / 64;
-constexpr int kItems = 16;               // entries per thread
-constexpr int kTile = kNT * kItems;      // 8192 entries per tile / chunk
+// pass 1 (tiles of the table, partitioned by the top kHiBits key bits)
+constexpr int kP1NT = 512;                 // threads of the pass-1 scatter
+constexpr int kP1Waves = kP1NT / 64;
+constexpr int kP1Items = 16;               // entries per thread
+constexpr int kP1Tile = kP1NT * kP1Items;  // entries per tile
 constexpr int kHistNT = 256;
+// pass 2 (one workgroup per super-bin)
+constexpr int kNT = 512;                   // threads of the pass-2 kernels
+constexpr int kWaves = kNT / 64;
+constexpr int kItems = 16;                 // entries per thread
+constexpr int kTile = kNT * kItems;        // 8192 entries: largest super-bin reordered in LDS
 constexpr int kHiBits = 8;
 constexpr int kHiBins = 1 << kHiBits;
 constexpr int kMaxLoBits = 11;
@@ -47,16 +53,20 @@ __device__ inline uint64_t lanemask_lt() {
 }
 
 // Lanes of the wave holding the same `bits`-bit digit as this lane (among the
-// lanes with ok set), from one ballot per digit bit.
+// lanes with ok set), from one ballot per digit bit: a lane differs from this
+// one if, for some bit, its ballot bit differs from this lane's bit.  The
+// sign-extended bit (0 or all ones) serves both the ballot and the XOR.
 __device__ inline uint64_t same_digit_lanes(uint32_t dg, int bits, bool ok) {
-    uint64_t same = __ballot(ok);
-    if (!same) return 0;  // a round without entries (wave-uniform)
+    const uint64_t act = __ballot(ok);
+    if (!act) return 0;  // a round without entries (wave-uniform)
+    uint32_t dlo = 0, dhi = 0;
     for (int b = 0; b < bits; ++b) {
-        const bool on = (dg >> b) & 1u;
-        const uint64_t bb = __ballot(on);
-        same &= on ? bb : ~bb;
+        const int32_t neg = int32_t(dg << (31 - b)) >> 31;
+        const uint64_t bb = __ballot(neg != 0);
+        dlo |= uint32_t(bb) ^ uint32_t(neg);
+        dhi |= uint32_t(bb >> 32) ^ uint32_t(neg);
     }
-    return same;
+    return act & ~((uint64_t(dhi) << 32) | dlo);
 }
 
 // Stable ranks of a wave's ITEMS rounds of 64 digits (round-major, then lane
@@ -116,10 +126,11 @@ __device__ inline uint32_t block_scan_u32(uint32_t v, uint32_t *sh, uint32_t *to
 
 // Turns the per-wave digit histograms wc[w][d] into per-wave exclusive
 // offsets and returns the per-digit totals in tot[d].
+template <int NT>
 __device__ inline void wave_offsets(uint32_t *wc, int R, uint32_t *tot) {
-    for (int d = threadIdx.x; d < R; d += kNT) {
+    for (int d = threadIdx.x; d < R; d += NT) {
         uint32_t run = 0;
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < NT / 64; ++w) {
             const uint32_t c = wc[w * R + d];
             wc[w * R + d] = run;
             run += c;
@@ -129,8 +140,9 @@ __device__ inline void wave_offsets(uint32_t *wc, int R, uint32_t *tot) {
 }
 
 // In place: cnt[d] := base + exclusive prefix of cnt over d < R.
+template <int NT>
 __device__ inline void digit_starts(uint32_t *cnt, int R, uint32_t base, uint32_t *sh) {
-    const int per = (R + kNT - 1) / kNT;
+    const int per = (R + NT - 1) / NT;
     const int d0 = threadIdx.x * per;
     uint32_t s = 0;
     for (int k = 0; k < per; ++k)
@@ -156,10 +168,20 @@ __global__ __launch_bounds__(kHistNT) void p1_hist_kernel(const uint32_t *__rest
     for (int i = threadIdx.x; i < HW * kHiBins; i += kHistNT) (&h[0][0])[i] = 0;
     __syncthreads();
     const uint32_t *kp = keys + int64_t(T) * n;
-    const int64_t beg = int64_t(blk) * kTile;
-    const int64_t end = min(n, beg + kTile);
-    for (int64_t e = beg + threadIdx.x; e < end; e += kHistNT)
-        atomicAdd(&h[wave][kp[e] >> (31 - kHiBits)], 1u);
+    const int64_t beg = int64_t(blk) * kP1Tile;
+    const int64_t end = min(n, beg + kP1Tile);
+    constexpr int PER = kP1Tile / kHistNT;  // keys per thread
+    if (end - beg == kP1Tile) {
+        // full tile: issue all loads before the counting
+        uint32_t k[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) k[j] = kp[beg + j * kHistNT + threadIdx.x];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) atomicAdd(&h[wave][k[j] >> (31 - kHiBits)], 1u);
+    } else {
+        for (int64_t e = beg + threadIdx.x; e < end; e += kHistNT)
+            atomicAdd(&h[wave][kp[e] >> (31 - kHiBits)], 1u);
+    }
     __syncthreads();
     uint32_t c = 0;
     for (int w = 0; w < HW; ++w) c += h[w][threadIdx.x];
@@ -185,50 +207,52 @@ __global__ __launch_bounds__(kHiBins) void p1_scan_kernel(uint32_t *__restrict__
     if (d == 0) bstart[int64_t(T) * (kHiBins + 1) + kHiBins] = uint32_t(n);
 }
 
-__global__ __launch_bounds__(kNT) void p1_scatter_kernel(const uint32_t *__restrict__ keys, int64_t n,
+__global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__restrict__ keys, int64_t n,
                                                          const uint32_t *__restrict__ offs, int nblk,
-                                                         uint32_t *__restrict__ okeys,
+                                                         int64_t nitems, uint32_t *__restrict__ okeys,
                                                          uint32_t *__restrict__ oids) {
-    __shared__ uint32_t wc[kWaves * kHiBins];
+    __shared__ uint32_t wc[kP1Waves * kHiBins];
     __shared__ uint32_t tot[kHiBins];
     __shared__ uint32_t gpos[kHiBins];
-    __shared__ uint32_t sk[kTile];
-    __shared__ uint16_t si[kTile];
-    __shared__ uint32_t sh[kWaves + 1];
+    __shared__ uint32_t sk[kP1Tile];
+    __shared__ uint16_t si[kP1Tile];
+    __shared__ uint32_t sh[kP1Waves + 1];
 
-    const int T = blockIdx.y, blk = blockIdx.x;
+    const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;  // padding of the grid to a multiple of kXcds
+    const int T = int(w / nblk), blk = int(w % nblk);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t toff = int64_t(T) * n;
-    const int64_t beg = int64_t(blk) * kTile;
-    const int cnt = int(min<int64_t>(kTile, n - beg));
-    for (int i = threadIdx.x; i < kWaves * kHiBins; i += kNT) wc[i] = 0;
-    for (int d = threadIdx.x; d < kHiBins; d += kNT) gpos[d] = offs[(int64_t(T) * nblk + blk) * kHiBins + d];
+    const int64_t beg = int64_t(blk) * kP1Tile;
+    const int cnt = int(min<int64_t>(kP1Tile, n - beg));
+    for (int i = threadIdx.x; i < kP1Waves * kHiBins; i += kP1NT) wc[i] = 0;
+    for (int d = threadIdx.x; d < kHiBins; d += kP1NT) gpos[d] = offs[(int64_t(T) * nblk + blk) * kHiBins + d];
     __syncthreads();
 
-    uint32_t rk[kItems], dg[kItems], rank[kItems];
-    bool ok[kItems];
+    uint32_t rk[kP1Items], dg[kP1Items], rank[kP1Items];
+    bool ok[kP1Items];
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const int e = wave * (64 * kItems) + it * 64 + lane;
+    for (int it = 0; it < kP1Items; ++it) {
+        const int e = wave * (64 * kP1Items) + it * 64 + lane;
         ok[it] = e < cnt;
         rk[it] = ok[it] ? keys[toff + beg + e] : 0u;
         dg[it] = rk[it] >> (31 - kHiBits);
     }
-    wave_stable_ranks<kItems>(dg, ok, kHiBits, wc + wave * kHiBins, rank);
+    wave_stable_ranks<kP1Items>(dg, ok, kHiBits, wc + wave * kHiBins, rank);
     __syncthreads();
-    wave_offsets(wc, kHiBins, tot);
+    wave_offsets<kP1NT>(wc, kHiBins, tot);
     __syncthreads();
-    digit_starts(tot, kHiBins, 0u, sh);  // tot := block-local start of each digit
+    digit_starts<kP1NT>(tot, kHiBins, 0u, sh);  // tot := block-local start of each digit
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < kP1Items; ++it) {
         if (ok[it]) {
             const uint32_t lp = tot[dg[it]] + wc[wave * kHiBins + dg[it]] + rank[it];
             sk[lp] = rk[it];
-            si[lp] = uint16_t(wave * (64 * kItems) + it * 64 + lane);
+            si[lp] = uint16_t(wave * (64 * kP1Items) + it * 64 + lane);
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kNT) {
+    for (int j = threadIdx.x; j < cnt; j += kP1NT) {
         const uint32_t key = sk[j];
         const uint32_t d = key >> (31 - kHiBits);
         const int64_t dst = toff + int64_t(gpos[d]) + (j - int64_t(tot[d]));
@@ -310,7 +334,7 @@ __device__ bool p2_fast(const P2Args &a, uint32_t *lds, uint32_t *sh) {
         start[i] = cnt[i];
     }
     if (block_max_u32(mx, sh) > kMaxFastBin) return false;
-    digit_starts(start, R, 0u, sh);
+    digit_starts<kNT>(start, R, 0u, sh);
     for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
     // ids into their bins, in slot order
 #pragma unroll
@@ -381,11 +405,11 @@ __device__ void p2_stable_single(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     }
     wave_stable_ranks<kItems>(dg, ok, a.lo_bits, wc + wave * R, rank);
     __syncthreads();
-    wave_offsets(wc, R, tot);
+    wave_offsets<kNT>(wc, R, tot);
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += kNT) start[i] = tot[i];
     __syncthreads();
-    digit_starts(start, R, 0u, sh);
+    digit_starts<kNT>(start, R, 0u, sh);
     for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
 #pragma unroll
     for (int it = 0; it < kItems; ++it)
@@ -415,7 +439,7 @@ __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) 
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < a.count; e += kNT) atomicAdd(&start[(a.kin[e] >> a.shift) & a.mask], 1u);
     __syncthreads();
-    digit_starts(start, R, 0u, sh);
+    digit_starts<kNT>(start, R, 0u, sh);
     for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
     for (uint32_t c0 = 0; c0 < a.count; c0 += kTile) {
         for (int i = threadIdx.x; i < kWaves * R; i += kNT) wc[i] = 0;
@@ -430,7 +454,7 @@ __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) 
         }
         wave_stable_ranks<kItems>(dg, ok, a.lo_bits, wc + wave * R, rank);
         __syncthreads();
-        wave_offsets(wc, R, tot);
+        wave_offsets<kNT>(wc, R, tot);
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < kItems; ++it)
@@ -471,10 +495,13 @@ __global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restr
                                                          const uint32_t *__restrict__ iids, int64_t n,
                                                          const uint32_t *__restrict__ bstart, int lo_bits,
                                                          uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
-                                                         uint32_t *__restrict__ dir, uint32_t *__restrict__ flags) {
+                                                         uint32_t *__restrict__ dir, uint32_t *__restrict__ flags,
+                                                         int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
-    const int T = blockIdx.y, sb = blockIdx.x;
+    const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;  // grid padding
+    const int T = int(w / kHiBins), sb = int(w % kHiBins);
     if (sb == kHiBins - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1) + (int64_t(kHiBins) << lo_bits)] = uint32_t(n);
     const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
@@ -488,10 +515,12 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
                                                          const uint32_t *__restrict__ bstart, int lo_bits,
                                                          uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
                                                          uint32_t *__restrict__ dir,
-                                                         const uint32_t *__restrict__ flags) {
+                                                         const uint32_t *__restrict__ flags, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
-    const int T = blockIdx.y, sb = blockIdx.x;
+    const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;  // grid padding
+    const int T = int(w / kHiBins), sb = int(w % kHiBins);
     if (!flags[int64_t(T) * kHiBins + sb]) return;
     const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
     if (a.count > uint32_t(kTile))
@@ -513,7 +542,7 @@ int table_dir_bits(int64_t n) {
 
 // tile histograms [L][tiles][256], super-bin starts [L][257], pass-2 flags [L][256]
 size_t table_build_scratch_bytes(int64_t L, int64_t n) {
-    const int64_t nblk = (n + kTile - 1) / kTile;
+    const int64_t nblk = (n + kP1Tile - 1) / kP1Tile;
     return size_t(L) * nblk * kHiBins * 4 + size_t(L) * (kHiBins + 1) * 4 + size_t(L) * kHiBins * 4;
 }
 
@@ -523,7 +552,7 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
     if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
-    const int nblk = int((n + kTile - 1) / kTile);
+    const int nblk = int((n + kP1Tile - 1) / kP1Tile);
     uint32_t *hist = scratch;
     uint32_t *bstart = scratch + size_t(L) * nblk * kHiBins;
     uint32_t *flags = bstart + size_t(L) * (kHiBins + 1);
@@ -533,19 +562,23 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins), 0, st, hist, nblk, n, bstart);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
-    hipLaunchKernelGGL(p1_scatter_kernel, dim3(nblk, unsigned(L)), dim3(kNT), 0, st, keys, n, hist, nblk, tmpk,
-                       tmpv);
+    const int64_t nitems = int64_t(nblk) * L;
+    const int64_t grid1 = xcd_grid(nitems);
+    if (grid1 > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "too many table tiles");
+    hipLaunchKernelGGL(p1_scatter_kernel, dim3(unsigned(grid1)), dim3(kP1NT), 0, st, keys, n, hist, nblk, nitems,
+                       tmpk, tmpv);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[2], st));
     const int lo_bits = dir_bits - kHiBits;
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
     const size_t lds_fast = (size_t(kTile) + 2 * (size_t(1) << lo_bits)) * 4;
-    hipLaunchKernelGGL(p2_fast_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds_fast, st, tmpk, tmpv, n, bstart,
-                       lo_bits, tkeys, tids, dir, flags);
+    const int64_t nitems2 = int64_t(kHiBins) * L;  // (table, super-bin) items, a multiple of kXcds
+    hipLaunchKernelGGL(p2_fast_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, tmpk, tmpv, n, bstart,
+                       lo_bits, tkeys, tids, dir, flags, nitems2);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
-    hipLaunchKernelGGL(p2_rest_kernel, dim3(kHiBins, unsigned(L)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
-                       lo_bits, tkeys, tids, dir, flags);
+    hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
+                       lo_bits, tkeys, tids, dir, flags, nitems2);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
     return FCLSH_OK;
