@@ -127,10 +127,10 @@ def main():
         "p1_hist_kernel": 4 * entries + 4 * L * nblk * 256,          # read keys, write tile histograms
         "p1_scan_kernel": 8 * L * nblk * 256,                        # read + write the histograms
         "p1_scatter_kernel": 12 * entries,                           # read key, write key + id
-        # pass 2: read + write key and id of each entry it reorders, its bins'
-        # directory entries, and the flags
-        "p2_fast_kernel": 16 * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries) + 4 * L * 256,
-        "p2_rest_kernel": 16 * rest_entries + dir_bytes * (rest_entries / entries) + 4 * L * 256,
+        # pass 2: read + write key and id of each entry it reorders and its
+        # bins' directory entries
+        "p2_fast_kernel": 16 * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries),
+        "p2_rest_kernel": 16 * rest_entries + dir_bytes * (rest_entries / entries) + 4,
     }
     dominant = max(phase_ms, key=phase_ms.get)
     achieved = kernel_bytes[dominant] / (phase_ms[dominant] * 1e-3) / 1e9

@@ -249,12 +249,17 @@ __global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
         const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
         const uint32_t *ids = a.tids + int64_t(T) * a.n;
         const int rq = query_radius(a, qi);
-        for (uint32_t j = lo; j < hi; ++j) {
-            const uint32_t key = bk[j];
-            if (key == qkey) {
-                const uint32_t id = ids[j];
-                if (near_in_table(a, qi, T, qkey, rq, key, id)) emit_pair(a, qi, id);
-            }
+        // the bin's keys in chunks of 8 independent loads, then the matches
+        for (uint32_t j0 = lo; j0 < hi; j0 += 8) {
+            uint32_t kk[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) kk[c] = j0 + c < hi ? bk[j0 + c] : ~qkey;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (kk[c] == qkey) {
+                    const uint32_t id = ids[j0 + c];
+                    if (near_in_table(a, qi, T, qkey, rq, qkey, id)) emit_pair(a, qi, id);
+                }
         }
     }
 }

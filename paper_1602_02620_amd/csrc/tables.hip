@@ -36,6 +36,7 @@ constexpr int kNT = 512;                   // threads of the pass-2 kernels
 constexpr int kWaves = kNT / 64;
 constexpr int kItems = 16;                 // entries per thread
 constexpr int kTile = kNT * kItems;        // 8192 entries: largest super-bin reordered in LDS
+constexpr int kRestBlocks = 1024;          // grid of the stable pass-2 kernel
 constexpr int kHiBits = 8;
 constexpr int kHiBins = 1 << kHiBits;
 constexpr int kMaxLoBits = 11;
@@ -189,9 +190,14 @@ __global__ __launch_bounds__(kHistNT) void p1_hist_kernel(const uint32_t *__rest
 }
 
 // Per table: hist[T][blk][d] := start (within the table) of tile blk's run of
-// digit d; bstart[T][d] = start of super-bin d, bstart[T][256] = n.
+// digit d; bstart[T][d] = start of super-bin d, bstart[T][256] = n; also
+// clears the count of super-bins left to the stable pass-2 kernel.  (A
+// "last block scans" fusion into the histogram kernel needs a device-scope
+// release per block, which writes back the L2 of the XCD; it measured 20x
+// slower than this separate launch.)
 __global__ __launch_bounds__(kHiBins) void p1_scan_kernel(uint32_t *__restrict__ hist, int nblk, int64_t n,
-                                                          uint32_t *__restrict__ bstart) {
+                                                          uint32_t *__restrict__ bstart,
+                                                          uint32_t *__restrict__ rest_count) {
     __shared__ uint32_t sh[kHiBins / 64 + 1];
     const int T = blockIdx.x, d = threadIdx.x;
     uint32_t *h = hist + int64_t(T) * nblk * kHiBins;
@@ -205,7 +211,9 @@ __global__ __launch_bounds__(kHiBins) void p1_scan_kernel(uint32_t *__restrict__
     for (int b = 0; b < nblk; ++b) h[int64_t(b) * kHiBins + d] += base;
     bstart[int64_t(T) * (kHiBins + 1) + d] = base;
     if (d == 0) bstart[int64_t(T) * (kHiBins + 1) + kHiBins] = uint32_t(n);
+    if (T == 0 && d == 0) *rest_count = 0;  // pass 2 appends from zero
 }
+
 
 __global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__restrict__ keys, int64_t n,
                                                          const uint32_t *__restrict__ offs, int nblk,
@@ -489,14 +497,15 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
     return a;
 }
 
-// Pass 2, fast path over every (table, super-bin); flags[T][sb] = 1 marks the
-// super-bins left to p2_rest_kernel (over kTile entries or a large bin).
+// Pass 2, fast path over every (table, super-bin); the super-bins it leaves
+// (over kTile entries, or a large bin) are appended to rest[] for
+// p2_rest_kernel.
 __global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restrict__ ikeys,
                                                          const uint32_t *__restrict__ iids, int64_t n,
                                                          const uint32_t *__restrict__ bstart, int lo_bits,
                                                          uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
-                                                         uint32_t *__restrict__ dir, uint32_t *__restrict__ flags,
-                                                         int64_t nitems) {
+                                                         uint32_t *__restrict__ dir, uint32_t *__restrict__ rest,
+                                                         uint32_t *__restrict__ rest_count, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
     const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
@@ -506,27 +515,30 @@ __global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restr
         dir[int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1) + (int64_t(kHiBins) << lo_bits)] = uint32_t(n);
     const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
     const bool done = a.count <= uint32_t(kTile) && p2_fast(a, lds, sh);
-    if (threadIdx.x == 0) flags[int64_t(T) * kHiBins + sb] = done ? 0u : 1u;
+    if (!done && threadIdx.x == 0) rest[atomicAdd(rest_count, 1u)] = uint32_t(w);
 }
 
-// Pass 2, stable path for the super-bins the fast path left.
+// Pass 2, stable path for the super-bins the fast path left: a fixed grid
+// works through the list (empty on uniform keys).
 __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys,
                                                          const uint32_t *__restrict__ iids, int64_t n,
                                                          const uint32_t *__restrict__ bstart, int lo_bits,
                                                          uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
-                                                         uint32_t *__restrict__ dir,
-                                                         const uint32_t *__restrict__ flags, int64_t nitems) {
+                                                         uint32_t *__restrict__ dir, const uint32_t *__restrict__ rest,
+                                                         const uint32_t *__restrict__ rest_count) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
-    const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
-    if (w >= nitems) return;  // grid padding
-    const int T = int(w / kHiBins), sb = int(w % kHiBins);
-    if (!flags[int64_t(T) * kHiBins + sb]) return;
-    const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
-    if (a.count > uint32_t(kTile))
-        p2_stable_chunked(a, lds, sh);
-    else
-        p2_stable_single(a, lds, sh);
+    const uint32_t nrest = *rest_count;
+    for (uint32_t i = blockIdx.x; i < nrest; i += gridDim.x) {
+        const uint32_t w = rest[i];
+        const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, int(w / kHiBins),
+                                 int(w % kHiBins));
+        if (a.count > uint32_t(kTile))
+            p2_stable_chunked(a, lds, sh);
+        else
+            p2_stable_single(a, lds, sh);
+        __syncthreads();  // LDS reuse by the next item
+    }
 }
 
 }  // namespace
@@ -540,10 +552,12 @@ int table_dir_bits(int64_t n) {
     return b;
 }
 
-// tile histograms [L][tiles][256], super-bin starts [L][257], pass-2 flags [L][256]
+// tile histograms [L][tiles][256], super-bin starts [L][257] (then one word:
+// the count of super-bins left to the stable pass-2 kernel), the list of those
+// super-bins [L][256]
 size_t table_build_scratch_bytes(int64_t L, int64_t n) {
     const int64_t nblk = (n + kP1Tile - 1) / kP1Tile;
-    return size_t(L) * nblk * kHiBins * 4 + size_t(L) * (kHiBins + 1) * 4 + size_t(L) * kHiBins * 4;
+    return size_t(L) * nblk * kHiBins * 4 + (size_t(L) * (kHiBins + 1) + 1) * 4 + size_t(L) * kHiBins * 4;
 }
 
 fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
@@ -555,11 +569,12 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     const int nblk = int((n + kP1Tile - 1) / kP1Tile);
     uint32_t *hist = scratch;
     uint32_t *bstart = scratch + size_t(L) * nblk * kHiBins;
-    uint32_t *flags = bstart + size_t(L) * (kHiBins + 1);
+    uint32_t *rest_count = bstart + size_t(L) * (kHiBins + 1);
+    uint32_t *rest = rest_count + 1;
     hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
-    hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins), 0, st, hist, nblk, n, bstart);
+    hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins), 0, st, hist, nblk, n, bstart, rest_count);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     const int64_t nitems = int64_t(nblk) * L;
@@ -574,11 +589,11 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
     const size_t lds_fast = (size_t(kTile) + 2 * (size_t(1) << lo_bits)) * 4;
     const int64_t nitems2 = int64_t(kHiBins) * L;  // (table, super-bin) items, a multiple of kXcds
     hipLaunchKernelGGL(p2_fast_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, tmpk, tmpv, n, bstart,
-                       lo_bits, tkeys, tids, dir, flags, nitems2);
+                       lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
-    hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds2, st, tmpk, tmpv, n, bstart,
-                       lo_bits, tkeys, tids, dir, flags, nitems2);
+    hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2, st,
+                       tmpk, tmpv, n, bstart, lo_bits, tkeys, tids, dir, rest, rest_count);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
     return FCLSH_OK;
