@@ -114,10 +114,10 @@ def main():
     phase_ms = {k: float(np.mean([run[k] for run in runs])) for k in runs[0]}
     nblk = (n + 8191) // 8192
     entries = n * L
-    # which super-bins (256 per table, by the top 8 key bits) pass 2's fast
-    # path leaves to its stable kernel: over 8192 entries, or a bin over 48
-    dir_bits = info["dir_bits"]
-    binsz = idx.directory().to(torch.int64).diff(dim=1).view(L, 256, -1)
+    # which groups (by the top group_bits key bits) pass 2's fast path leaves
+    # to its stable kernel: over 8192 entries, or a bin over 48
+    dir_bits, group_bits = info["dir_bits"], info["group_bits"]
+    binsz = idx.directory().to(torch.int64).diff(dim=1).view(L, 1 << group_bits, -1)
     sb_count, sb_max = binsz.sum(-1), binsz.amax(-1)
     rest = (sb_count > 8192) | (sb_max > 48)
     rest_entries = int(sb_count[rest].sum().item())
@@ -127,6 +127,8 @@ def main():
         "p1_hist_kernel": 4 * entries + 4 * L * nblk * 256,          # read keys, write tile histograms
         "p1_scan_kernel": 8 * L * nblk * 256,                        # read + write the histograms
         "p1_scatter_kernel": 12 * entries,                           # read key, write key + id
+        # split of the super-bins (large n only): read keys twice and ids once, write both
+        "p1b_split_kernel": (20 * entries + 4 * L * ((256 << (group_bits - 8)) + 1)) if group_bits > 8 else 0,
         # pass 2: read + write key and id of each entry it reorders and its
         # bins' directory entries
         "p2_fast_kernel": 16 * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries),
@@ -343,7 +345,7 @@ def verify_samples(checks):
 
 KERNEL_SOURCES = {"fht_hash_kernel": "hash.hip", "p1_hist_kernel": "tables.hip", "p1_scan_kernel": "tables.hip",
                   "p1_scatter_kernel": "tables.hip", "p2_fast_kernel": "tables.hip",
-                  "p2_rest_kernel": "tables.hip"}
+                  "p2_rest_kernel": "tables.hip", "p1b_split_kernel": "tables.hip"}
 
 
 def measured_traffic(kernel, n, d, r):

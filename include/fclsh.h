@@ -166,10 +166,13 @@ FCLSH_API const char *fclsh_last_error(void);
  * Hot-path pieces, exported for tests and measurement.
  * ------------------------------------------------------------------------- */
 
-/* Shape of a built index. Any output pointer may be NULL. */
+/* Shape of a built index. Any output pointer may be NULL.  dir_bits: the
+ * directory's bin width B (bins = top B key bits); group_bits: the key bits
+ * that form the groups of the table build's last pass (8, or more for large
+ * n, where a middle pass splits the 256 super-bins further). */
 FCLSH_API fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r,
                               int32_t *t, int32_t *r_part, int64_t *n,
-                              int32_t *L, int32_t *dir_bits);
+                              int32_t *L, int32_t *dir_bits, int32_t *group_bits);
 
 /* The parameters an index was built with (host arrays of d entries). */
 FCLSH_API fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col,
@@ -195,10 +198,11 @@ FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tk
 FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
 
 /* The same rebuild with HIP events recorded on `stream` around each kernel.
- * phase_ms[0..5] (host, nphase >= 6) receive the durations in ms of: the key
+ * phase_ms[0..6] (host, nphase >= 7) receive the durations in ms of: the key
  * computation of Alg. 2 for all points and tables, the pass-1 histogram, the
- * pass-1 scan, the pass-1 scatter, the pass-2 fast path and the pass-2
- * stable path (super-bins the fast path left) of the table build.
+ * pass-1 scan, the pass-1 scatter, the pass-1b split (0 when n is small
+ * enough not to need it), the pass-2 fast path and the pass-2 stable path
+ * (groups the fast path left) of the table build.
  * Errors: FCLSH_EINVAL for a short phase_ms, FCLSH_EDEVICE for HIP errors.
  * Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms,

@@ -73,7 +73,7 @@ def lib():
             "fclsh_build_index_with_params": [vp, i64, i32, i32, i32, i32, vp, vp, vp, u64, vp, P(vp)],
             "fclsh_query_batch": [vp, vp, i64, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_plain": [vp, vp, i64, i32, vp, vp, vp, i64, P(i64)],
-            "fclsh_index_info": [vp, P(i32), P(i32), P(i32), P(i32), P(i64), P(i32), P(i32)],
+            "fclsh_index_info": [vp, P(i32), P(i32), P(i32), P(i32), P(i64), P(i32), P(i32), P(i32)],
             "fclsh_index_params": [vp, vp, vp, vp],
             "fclsh_hash": [vp, vp, i64, vp, vp],
             "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
@@ -199,12 +199,13 @@ class Index:
 
     @property
     def info(self) -> dict:
-        d, r, t, rp, L, db = (ctypes.c_int32() for _ in range(6))
+        d, r, t, rp, L, db, gb = (ctypes.c_int32() for _ in range(7))
         n = ctypes.c_int64()
         _check(lib().fclsh_index_info(self._h, ctypes.byref(d), ctypes.byref(r), ctypes.byref(t),
-                                      ctypes.byref(rp), ctypes.byref(n), ctypes.byref(L), ctypes.byref(db)))
+                                      ctypes.byref(rp), ctypes.byref(n), ctypes.byref(L), ctypes.byref(db),
+                                      ctypes.byref(gb)))
         return {"d": d.value, "r": r.value, "t": t.value, "r_part": rp.value, "n": n.value, "L": L.value,
-                "dir_bits": db.value}
+                "dir_bits": db.value, "group_bits": gb.value}
 
     def params(self) -> dict:
         d = self.d
@@ -230,7 +231,7 @@ class Index:
         _check(lib().fclsh_index_rebuild(self._h, _stream_ptr(stream)))
 
     REBUILD_PHASES = ("fht_hash_kernel", "p1_hist_kernel", "p1_scan_kernel", "p1_scatter_kernel",
-                      "p2_fast_kernel", "p2_rest_kernel")
+                      "p1b_split_kernel", "p2_fast_kernel", "p2_rest_kernel")
 
     def rebuild_timed(self, stream=None) -> dict:
         """Rebuild with HIP events between the kernels: kernel name -> ms."""

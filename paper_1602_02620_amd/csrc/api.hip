@@ -54,8 +54,8 @@ uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 
 
 }  // namespace
 
-// hash, pass-1 histogram, pass-1 scan, pass-1 scatter, pass-2 fast, pass-2 stable
-constexpr int kRebuildPhases = 6;
+// hash, pass-1 histogram, pass-1 scan, pass-1 scatter, pass-1b split, pass-2 fast, pass-2 stable
+constexpr int kRebuildPhases = 7;
 
 struct IndexHandle {
     Index ix;
@@ -83,7 +83,7 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
     b += 2 * L * size_t(n) * 4;                          // table keys + ids
     b += L * ((size_t(1) << dir_bits) + 1) * 4;          // directories
     b += 3 * L * size_t(n) * 4;                          // build scratch: keys + 2 partition buffers
-    b += table_build_scratch_bytes(int64_t(L), n);       // histograms
+    b += table_build_scratch_bytes(int64_t(L), n, dir_bits);  // histograms, group starts, lists
     return b;
 }
 
@@ -97,7 +97,7 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->keys), size_t(L * ix.n) * 4, "build keys"));
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->tk), size_t(L * ix.n) * 4, "sort buffer"));
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->tv), size_t(L * ix.n) * 4, "sort buffer"));
-        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n),
+        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n, ix.dir_bits),
                             "table histograms"));
     }
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
@@ -291,7 +291,7 @@ void fclsh_index_free(fclsh_index idx) {
 }
 
 fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r, int32_t *t, int32_t *r_part, int64_t *n,
-                              int32_t *L, int32_t *dir_bits) {
+                              int32_t *L, int32_t *dir_bits, int32_t *group_bits) {
     if (!idx) return fail(FCLSH_EINVAL, "null index");
     const Index &ix = handle(idx)->ix;
     if (d) *d = ix.prm.d;
@@ -301,6 +301,7 @@ fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r, int32_t *
     if (n) *n = ix.n;
     if (L) *L = ix.prm.L();
     if (dir_bits) *dir_bits = ix.dir_bits;
+    if (group_bits) *group_bits = 8 + table_split_bits(ix.n, ix.dir_bits);
     return FCLSH_OK;
 }
 

@@ -156,14 +156,16 @@ inline int64_t xcd_grid(int64_t nitems) { return (nitems + kXcds - 1) / kXcds * 
 
 // Table build (tables.hip): keys [L][n] -> tables grouped by the top dir_bits
 // key bits, ids ascending per bin, plus the directory [L][2^dir_bits + 1].
+// keys is consumed (reused as a buffer).  marks (optional, 6 events) are
+// recorded on st after each of: pass-1 histogram, pass-1 scan, pass-1
+// scatter, pass-1b split (recorded also when the split is not needed),
+// pass-2 fast path, pass-2 stable path.
 int table_dir_bits(int64_t n);
-size_t table_build_scratch_bytes(int64_t L, int64_t n);
-// marks (optional, 5 events) are recorded on st after each of the five
-// kernels: pass-1 histogram, pass-1 scan, pass-1 scatter, pass-2 fast path,
-// pass-2 stable path.
-fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
-                                uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
-                                uint32_t *dir, hipStream_t st, hipEvent_t *marks = nullptr);
+int table_split_bits(int64_t n, int dir_bits);
+size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits);
+fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
+                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, hipStream_t st,
+                                hipEvent_t *marks = nullptr);
 
 // Device-side control block of one query batch.
 struct QueryCtrl {

@@ -289,12 +289,15 @@ __global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__res
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMaxFastBin = 48;
 
+// Pass 2 works on groups: the entries of a table that share their top gbits
+// key bits (gbits = 8, or 8 + S after the pass-1b split), a contiguous run
+// after the previous passes.
 struct P2Args {
-    const uint32_t *kin, *vin;  // the super-bin's input run (table offset applied)
-    uint32_t *okey, *oid;       // the super-bin's output run
-    uint32_t *dr;               // directory entries of the super-bin's bins
-    uint32_t count;             // entries in the super-bin
-    uint32_t bs;                // super-bin start within the table
+    const uint32_t *kin, *vin;  // the group's input run (table offset applied)
+    uint32_t *okey, *oid;       // the group's output run
+    uint32_t *dr;               // directory entries of the group's bins
+    uint32_t count;             // entries in the group
+    uint32_t bs;                // group start within the table
     int shift, lo_bits;
     uint32_t mask;
 };
@@ -478,66 +481,173 @@ __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) 
     }
 }
 
-__device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *bstart,
-                                 int lo_bits, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, int T, int sb) {
+__device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *gstart,
+                                 int gbits, int lo_bits, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, int T, int g) {
     const int64_t toff = int64_t(T) * n;
-    const uint32_t bs = bstart[int64_t(T) * (kHiBins + 1) + sb];
-    const uint32_t be = bstart[int64_t(T) * (kHiBins + 1) + sb + 1];
+    // group starts per table: 2^gbits + 1 (<= 4097), so the index fits 32
+    // bits and stays in scalar registers (a 64-bit product lands in vector
+    // registers, and the block-uniform loop exits of the fast path then
+    // become exec-masked)
+    const uint32_t gs = (1u << gbits) + 1u;
+    const uint32_t gi = uint32_t(T) * gs + uint32_t(g);
+    const uint32_t bs = gstart[gi];
+    const uint32_t be = gstart[gi + 1];
     P2Args a;
     a.kin = ikeys + toff + bs;
     a.vin = iids + toff + bs;
     a.okey = tkeys + toff + bs;
     a.oid = tids + toff + bs;
-    a.dr = dir + int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1) + (int64_t(sb) << lo_bits);
+    a.dr = dir + int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(g) << lo_bits);
     a.count = be - bs;
     a.bs = bs;
     a.lo_bits = lo_bits;
-    a.shift = 31 - kHiBits - lo_bits;
+    a.shift = 31 - gbits - lo_bits;
     a.mask = (1u << lo_bits) - 1u;
     return a;
 }
 
-// Pass 2, fast path over every (table, super-bin); the super-bins it leaves
-// (over kTile entries, or a large bin) are appended to rest[] for
-// p2_rest_kernel.
-__global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restrict__ ikeys,
-                                                         const uint32_t *__restrict__ iids, int64_t n,
-                                                         const uint32_t *__restrict__ bstart, int lo_bits,
-                                                         uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
+// Pass 2, fast path over every (table, group); the groups it leaves (over
+// kTile entries, or a large bin) are appended to rest[] for p2_rest_kernel.
+// (iids and tids may be the same array: the ids are then reordered in place,
+// each group reading its whole run into registers before writing it.)
+__global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
+                                                         int64_t n, const uint32_t *__restrict__ gstart, int gbits,
+                                                         int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids,
                                                          uint32_t *__restrict__ dir, uint32_t *__restrict__ rest,
                                                          uint32_t *__restrict__ rest_count, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
     const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
     if (w >= nitems) return;  // grid padding
-    const int T = int(w / kHiBins), sb = int(w % kHiBins);
-    if (sb == kHiBins - 1 && threadIdx.x == 0)
-        dir[int64_t(T) * ((int64_t(kHiBins) << lo_bits) + 1) + (int64_t(kHiBins) << lo_bits)] = uint32_t(n);
-    const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, T, sb);
+    const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
+    if (g == (1 << gbits) - 1 && threadIdx.x == 0)
+        dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
+    const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
     const bool done = a.count <= uint32_t(kTile) && p2_fast(a, lds, sh);
     if (!done && threadIdx.x == 0) rest[atomicAdd(rest_count, 1u)] = uint32_t(w);
 }
 
-// Pass 2, stable path for the super-bins the fast path left: a fixed grid
-// works through the list (empty on uniform keys).
-__global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys,
-                                                         const uint32_t *__restrict__ iids, int64_t n,
-                                                         const uint32_t *__restrict__ bstart, int lo_bits,
-                                                         uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tids,
+// Pass 2, stable path for the groups the fast path left: a fixed grid works
+// through the list (empty on uniform keys).  When the input ids are the
+// output id array (after the pass-1b split), a group taking the chunked
+// path first copies its ids to spare, which that path then reads.
+__global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
+                                                         int64_t n, const uint32_t *__restrict__ gstart, int gbits,
+                                                         int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids,
                                                          uint32_t *__restrict__ dir, const uint32_t *__restrict__ rest,
-                                                         const uint32_t *__restrict__ rest_count) {
+                                                         const uint32_t *__restrict__ rest_count,
+                                                         uint32_t *__restrict__ spare) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
     const uint32_t nrest = *rest_count;
     for (uint32_t i = blockIdx.x; i < nrest; i += gridDim.x) {
-        const uint32_t w = rest[i];
-        const P2Args a = p2_args(ikeys, iids, n, bstart, lo_bits, tkeys, tids, dir, int(w / kHiBins),
-                                 int(w % kHiBins));
-        if (a.count > uint32_t(kTile))
+        const int64_t w = rest[i];
+        const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
+        P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
+        if (a.count > uint32_t(kTile)) {
+            if (iids == tids) {
+                uint32_t *copy = spare + int64_t(T) * n + a.bs;
+                for (uint32_t e = threadIdx.x; e < a.count; e += kNT) copy[e] = a.vin[e];
+                __syncthreads();
+                a.vin = copy;
+            }
             p2_stable_chunked(a, lds, sh);
-        else
+        } else {
             p2_stable_single(a, lds, sh);
+        }
         __syncthreads();  // LDS reuse by the next item
+    }
+}
+
+// Pass 1b, for large tables: one workgroup per (table, super-bin) splits the
+// super-bin stably by the next sbits key bits into 2^sbits groups, so that
+// pass 2 sees groups of a few thousand entries.  A histogram of the
+// sub-digits gives the group starts (gstart, the pass-2 layout); the
+// super-bin is then moved chunk by chunk (wave-ballot ranks, LDS reorder)
+// with running group offsets, each sub-digit's run written contiguously.
+constexpr int kMaxSplitBits = 4;
+
+__global__ __launch_bounds__(kNT, 4) void p1b_split_kernel(const uint32_t *__restrict__ ikeys,
+                                                           const uint32_t *__restrict__ iids, int64_t n,
+                                                           const uint32_t *__restrict__ bstart, int sbits,
+                                                           uint32_t *__restrict__ okeys, uint32_t *__restrict__ oids,
+                                                           uint32_t *__restrict__ gstart, int64_t nitems) {
+    constexpr int MS = 1 << kMaxSplitBits;
+    __shared__ uint32_t sk[kTile];
+    __shared__ uint32_t sv[kTile];
+    __shared__ uint32_t wc[kWaves * MS];
+    __shared__ uint32_t cnt[MS], run[MS], ctot[MS], cst[MS];
+    const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;  // grid padding
+    const int T = int(w / kHiBins), sb = int(w % kHiBins);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int SB = 1 << sbits;
+    const int shift = 31 - kHiBits - sbits;
+    const uint32_t mask = uint32_t(SB - 1);
+    const uint32_t bs = bstart[int64_t(T) * (kHiBins + 1) + sb];
+    const uint32_t count = bstart[int64_t(T) * (kHiBins + 1) + sb + 1] - bs;
+    const int64_t off = int64_t(T) * n + bs;
+    const uint32_t *kin = ikeys + off, *vin = iids + off;
+    uint32_t *okey = okeys + off, *oid = oids + off;
+    if (threadIdx.x < MS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < count; e += kNT) atomicAdd(&cnt[(kin[e] >> shift) & mask], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t gs = (int64_t(kHiBins) << sbits) + 1;
+        uint32_t acc = 0;
+        for (int d = 0; d < SB; ++d) {
+            gstart[int64_t(T) * gs + (int64_t(sb) << sbits) + d] = bs + acc;
+            run[d] = acc;
+            acc += cnt[d];
+        }
+        if (sb == kHiBins - 1) gstart[int64_t(T) * gs + gs - 1] = uint32_t(n);
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < count; c0 += kTile) {
+        for (int i = threadIdx.x; i < kWaves * SB; i += kNT) wc[i] = 0;
+        __syncthreads();
+        uint32_t rk[kItems], rv[kItems], dg[kItems], rank[kItems];
+        bool ok[kItems];
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
+            ok[it] = e < count;
+            rk[it] = ok[it] ? kin[e] : 0u;
+            rv[it] = ok[it] ? vin[e] : 0u;
+            dg[it] = (rk[it] >> shift) & mask;
+        }
+        wave_stable_ranks<kItems>(dg, ok, sbits, wc + wave * SB, rank);
+        __syncthreads();
+        wave_offsets<kNT>(wc, SB, ctot);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            for (int d = 0; d < SB; ++d) {
+                cst[d] = acc;
+                acc += ctot[d];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kItems; ++it)
+            if (ok[it]) {
+                const uint32_t lp = cst[dg[it]] + wc[wave * SB + dg[it]] + rank[it];
+                sk[lp] = rk[it];
+                sv[lp] = rv[it];
+            }
+        __syncthreads();
+        const uint32_t chunk = min(uint32_t(kTile), count - c0);
+        for (uint32_t j = threadIdx.x; j < chunk; j += kNT) {
+            const uint32_t key = sk[j];
+            const uint32_t d = (key >> shift) & mask;
+            const uint32_t dst = run[d] + (j - cst[d]);
+            okey[dst] = key;
+            oid[dst] = sv[j];
+        }
+        __syncthreads();
+        if (threadIdx.x < SB) run[threadIdx.x] += ctot[threadIdx.x];
+        __syncthreads();
     }
 }
 
@@ -552,24 +662,38 @@ int table_dir_bits(int64_t n) {
     return b;
 }
 
-// tile histograms [L][tiles][256], super-bin starts [L][257] (then one word:
-// the count of super-bins left to the stable pass-2 kernel), the list of those
-// super-bins [L][256]
-size_t table_build_scratch_bytes(int64_t L, int64_t n) {
-    const int64_t nblk = (n + kP1Tile - 1) / kP1Tile;
-    return size_t(L) * nblk * kHiBins * 4 + (size_t(L) * (kHiBins + 1) + 1) * 4 + size_t(L) * kHiBins * 4;
+// Extra key bits by which pass 1b splits each super-bin, so that pass 2's
+// groups average at most 4096 entries (0 up to about a million points).
+int table_split_bits(int64_t n, int dir_bits) {
+    int sb = 0;
+    while (sb < kMaxSplitBits && (n >> (kHiBits + sb)) > 4096) ++sb;
+    return std::min(sb, dir_bits - kHiBits);
 }
 
-fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk,
-                                uint32_t *tmpv, uint32_t *scratch, uint32_t *tkeys, uint32_t *tids,
-                                uint32_t *dir, hipStream_t st, hipEvent_t *marks) {
+// tile histograms [L][tiles][256], super-bin starts [L][257], group starts
+// [L][(256 << S) + 1] (S > 0 only), the count of groups left to the stable
+// pass-2 kernel, and the list of those groups [L][256 << S]
+size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits) {
+    const int64_t nblk = (n + kP1Tile - 1) / kP1Tile;
+    const int S = table_split_bits(n, dir_bits);
+    const size_t groups = size_t(kHiBins) << S;
+    return 4 * (size_t(L) * nblk * kHiBins + size_t(L) * (kHiBins + 1) + (S ? size_t(L) * (groups + 1) : 0) + 1 +
+                size_t(L) * groups);
+}
+
+fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
+                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, hipStream_t st,
+                                hipEvent_t *marks) {
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
     if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
     const int nblk = int((n + kP1Tile - 1) / kP1Tile);
+    const int S = table_split_bits(n, dir_bits);
+    const int gbits = kHiBits + S, lo_bits = dir_bits - gbits;
     uint32_t *hist = scratch;
-    uint32_t *bstart = scratch + size_t(L) * nblk * kHiBins;
-    uint32_t *rest_count = bstart + size_t(L) * (kHiBins + 1);
+    uint32_t *bstart = hist + size_t(L) * nblk * kHiBins;
+    uint32_t *gstart = S ? bstart + size_t(L) * (kHiBins + 1) : bstart;
+    uint32_t *rest_count = S ? gstart + size_t(L) * ((size_t(kHiBins) << S) + 1) : bstart + size_t(L) * (kHiBins + 1);
     uint32_t *rest = rest_count + 1;
     hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
     FCLSH_HIP(hipGetLastError());
@@ -584,18 +708,29 @@ fclsh_status build_tables_2pass(const uint32_t *keys, int64_t L, int64_t n, int 
                        tmpk, tmpv);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[2], st));
-    const int lo_bits = dir_bits - kHiBits;
+    // pass 2 input: the pass-1 output, or after the split the hash-key buffer
+    // (keys) and the table id array (ids reordered in place)
+    const uint32_t *p2k = tmpk, *p2v = tmpv;
+    if (S) {
+        const int64_t nsb = int64_t(kHiBins) * L;
+        hipLaunchKernelGGL(p1b_split_kernel, dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk, tmpv, n, bstart, S, keys,
+                           tids, gstart, nsb);
+        FCLSH_HIP(hipGetLastError());
+        p2k = keys;
+        p2v = tids;
+    }
+    if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
     const size_t lds_fast = (size_t(kTile) + 2 * (size_t(1) << lo_bits)) * 4;
-    const int64_t nitems2 = int64_t(kHiBins) * L;  // (table, super-bin) items, a multiple of kXcds
-    hipLaunchKernelGGL(p2_fast_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, tmpk, tmpv, n, bstart,
+    const int64_t nitems2 = int64_t(L) << gbits;  // (table, group) items, a multiple of kXcds
+    hipLaunchKernelGGL(p2_fast_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n, gstart, gbits,
                        lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
     FCLSH_HIP(hipGetLastError());
-    if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
-    hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2, st,
-                       tmpk, tmpv, n, bstart, lo_bits, tkeys, tids, dir, rest, rest_count);
-    FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
+    hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2, st,
+                       p2k, p2v, n, gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, tmpv);
+    FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[5], st));
     return FCLSH_OK;
 }
 

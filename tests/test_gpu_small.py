@@ -307,3 +307,38 @@ def test_timed_rebuild_reports_every_kernel():
     tk1, ti1 = (as_u32(t) for t in idx.tables())
     assert np.array_equal(tk0, tk1) and np.array_equal(ti0, ti1)
     idx.close()
+
+
+@pytest.mark.parametrize("dup", [False, True], ids=["uniform", "heavy"])
+def test_split_pass_for_large_n(dup):
+    """Above about a million points the table build splits each super-bin
+    by more key bits before the last pass.  1.2 million points with only 7
+    tables (d=64, r=2) keep the oracle quick: every table entry and the
+    directory are compared.  With 400,000 copies of one point, the heavy
+    bins take the stable fallback, which then reorders the ids in place."""
+    rng = np.random.default_rng(40 + int(dup))
+    n, d, r, seed = 1_200_000, 64, 2, 95
+    pts = synth.uniform_points(n, d, rng)
+    if dup:
+        pts[::3] = pts[0]
+    _say(f"[split] n={n} dup={dup}")
+    idx = fc.Index(dev(pts), d, r, seed=seed)
+    inf = idx.info
+    assert inf["group_bits"] > 8
+    pr = oracle.derive_params(d, r, seed)
+    orc = OracleIndex(pts, pr, with_tables=False)
+    assert np.array_equal(as_u32(idx.hash(dev(pts))), orc.keys)
+    tk, ti = idx.tables()
+    wk, wi = orc.binned_tables(inf["dir_bits"])
+    assert np.array_equal(as_u32(tk), wk)
+    assert np.array_equal(as_u32(ti), wi)
+    db = inf["dir_bits"]
+    dr = as_u32(idx.directory())
+    for T in range(pr.L):
+        bins = np.sort(orc.keys[T] >> np.uint32(31 - db))
+        assert np.array_equal(dr[T], np.searchsorted(bins, np.arange((1 << db) + 1)).astype(np.uint32)), f"table {T}"
+    # the queries see the same tables: a few sampled answers against the scan
+    qs = pts[rng.choice(n, size=6, replace=False)]
+    want = oracle.brute_force(pts, d, qs, r).ids
+    assert_same_lists(csr_lists(*idx.query(dev(qs), r)), want)
+    idx.close()
