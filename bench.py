@@ -114,13 +114,16 @@ def main():
     phase_ms = {k: float(np.mean([run[k] for run in runs])) for k in runs[0]}
     nblk = (n + 8191) // 8192
     entries = n * L
-    # which groups (by the top group_bits key bits) pass 2's fast path leaves
-    # to its stable kernel: over 8192 entries, or a bin over 48
+    # how pass 2 treats the groups (entries sharing the top group_bits key
+    # bits): the group kernel takes every group of at most 4608 entries, by
+    # slot ranks when no bin holds over 48 entries, else by stable ballot
+    # ranks; larger groups go to the second kernel
     dir_bits, group_bits = info["dir_bits"], info["group_bits"]
     binsz = idx.directory().to(torch.int64).diff(dim=1).view(L, 1 << group_bits, -1)
     sb_count, sb_max = binsz.sum(-1), binsz.amax(-1)
-    rest = (sb_count > 8192) | (sb_max > 48)
+    rest = sb_count > 4608
     rest_entries = int(sb_count[rest].sum().item())
+    ballot_entries = int(sb_count[~rest & (sb_max > 48)].sum().item())
     dir_bytes = 4 * L * ((1 << dir_bits) + 1)
     kernel_bytes = {  # algorithmic bytes per launch
         "fht_hash_kernel": n * (W * 8 + 4 * L),                    # read the point, write its L keys
@@ -197,7 +200,7 @@ def main():
             "build_ms": ms_build, "build_entries_per_s": entries / (ms_build * 1e-3),
             "build_GBps_at_12B_per_entry": build_bytes / (ms_build * 1e-3) / 1e9,
             "kernel_ms": phase_ms,
-            "pass2_stable_share": rest_entries / entries,
+            "pass2_ballot_share": ballot_entries / entries, "pass2_rest_share": rest_entries / entries,
             "query_batch_ms": ms_query, "queries_per_s": nq / (ms_query * 1e-3),
             "reported_ids": total_ids,
             "plain_query_ms_p50": pct(lat_plain, 50), "plain_query_ms_p99": pct(lat_plain, 99),

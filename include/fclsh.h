@@ -201,8 +201,8 @@ FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
  * phase_ms[0..6] (host, nphase >= 7) receive the durations in ms of: the key
  * computation of Alg. 2 for all points and tables, the pass-1 histogram, the
  * pass-1 scan, the pass-1 scatter, the pass-1b split (0 when n is small
- * enough not to need it), the pass-2 fast path and the pass-2 stable path
- * (groups the fast path left) of the table build.
+ * enough not to need it), the pass-2 group kernel (every group of the
+ * table of at most 4608 entries) and the pass-2 kernel for larger groups.
  * Errors: FCLSH_EINVAL for a short phase_ms, FCLSH_EDEVICE for HIP errors.
  * Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms,

@@ -159,7 +159,7 @@ inline int64_t xcd_grid(int64_t nitems) { return (nitems + kXcds - 1) / kXcds * 
 // keys is consumed (reused as a buffer).  marks (optional, 6 events) are
 // recorded on st after each of: pass-1 histogram, pass-1 scan, pass-1
 // scatter, pass-1b split (recorded also when the split is not needed),
-// pass-2 fast path, pass-2 stable path.
+// pass-2 group kernel, pass-2 kernel for large groups.
 int table_dir_bits(int64_t n);
 int table_split_bits(int64_t n, int dir_bits);
 size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits);

@@ -35,7 +35,9 @@ constexpr int kHistNT = 256;
 constexpr int kNT = 512;                   // threads of the pass-2 kernels
 constexpr int kWaves = kNT / 64;
 constexpr int kItems = 16;                 // entries per thread
-constexpr int kTile = kNT * kItems;        // 8192 entries: largest super-bin reordered in LDS
+constexpr int kTile = kNT * kItems;        // 8192 entries: largest group reordered in LDS
+constexpr int kFastItems = 9;              // entries per thread in the pass-2 group kernel
+constexpr int kFastTile = kNT * kFastItems;  // 4608: largest group of the group kernel
 constexpr int kRestBlocks = 1024;          // grid of the stable pass-2 kernel
 constexpr int kHiBits = 8;
 constexpr int kHiBins = 1 << kHiBits;
@@ -76,10 +78,9 @@ __device__ inline uint64_t same_digit_lanes(uint32_t dg, int bits, bool ok) {
 // counter with an LDS atomic that returns the previous value; the atomics of
 // one wave execute in program order, so no round waits for the previous one.
 // wcw must hold zeros for all digits on entry and ends as the wave histogram.
-template <int ITEMS>
-__device__ inline void wave_stable_ranks(const uint32_t (&dg)[ITEMS], const bool (&ok)[ITEMS], int bits,
-                                         uint32_t *wcw, uint32_t (&rank)[ITEMS]) {
-    constexpr int GRP = ITEMS < 8 ? ITEMS : 8;  // rounds whose atomics are in flight together
+template <int ITEMS, int GRP, typename DigitOf, typename ValidOf>  // GRP: rounds with atomics in flight together
+__device__ inline void wave_stable_ranks_of(DigitOf digit, ValidOf ok, int bits, uint32_t *wcw,
+                                            uint32_t (&rank)[ITEMS]) {
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int g0 = 0; g0 < ITEMS; g0 += GRP) {
@@ -87,14 +88,25 @@ __device__ inline void wave_stable_ranks(const uint32_t (&dg)[ITEMS], const bool
 #pragma unroll
         for (int k = 0; k < GRP; ++k) {
             const int it = g0 + k;
-            const uint64_t same = same_digit_lanes(dg[it], bits, ok[it]);
+            if (it >= ITEMS) break;
+            const uint32_t dg = digit(it);
+            const bool v = ok(it);
+            const uint64_t same = same_digit_lanes(dg, bits, v);
             before[k] = uint32_t(__popcll(same & lt));
             lead[k] = same ? uint32_t(__builtin_ctzll(same)) : 0u;
-            old[k] = (ok[it] && before[k] == 0) ? atomicAdd(&wcw[dg[it]], uint32_t(__popcll(same))) : 0u;
+            old[k] = (v && before[k] == 0) ? atomicAdd(&wcw[dg], uint32_t(__popcll(same))) : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < GRP; ++k) rank[g0 + k] = __shfl(old[k], int(lead[k]), 64) + before[k];
+        for (int k = 0; k < GRP; ++k)
+            if (g0 + k < ITEMS) rank[g0 + k] = __shfl(old[k], int(lead[k]), 64) + before[k];
     }
+}
+
+template <int ITEMS>
+__device__ inline void wave_stable_ranks(const uint32_t (&dg)[ITEMS], const bool (&ok)[ITEMS], int bits,
+                                         uint32_t *wcw, uint32_t (&rank)[ITEMS]) {
+    wave_stable_ranks_of<ITEMS, (ITEMS < 8 ? ITEMS : 8)>([&](int it) { return dg[it]; },
+                                                          [&](int it) { return ok[it]; }, bits, wcw, rank);
 }
 
 // Block-wide exclusive scan; *total gets the sum.
@@ -259,35 +271,68 @@ __global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__res
             si[lp] = uint16_t(wave * (64 * kP1Items) + it * 64 + lane);
         }
     }
+    // gpos := table position of a digit's run minus its start in the tile,
+    // so the entry at tile position j goes to gpos[d] + j (mod 2^32, < n)
+    for (int d = threadIdx.x; d < kHiBins; d += kP1NT) gpos[d] -= tot[d];
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kP1NT) {
-        const uint32_t key = sk[j];
-        const uint32_t d = key >> (31 - kHiBits);
-        const int64_t dst = toff + int64_t(gpos[d]) + (j - int64_t(tot[d]));
-        okeys[dst] = key;
-        oids[dst] = uint32_t(beg + si[j]);
+    uint32_t *okt = okeys + toff, *oit = oids + toff;
+    const uint32_t b32 = uint32_t(beg);
+    if (cnt == kP1Tile) {
+        // full tile: all LDS reads first, then the stores
+        uint32_t kk[kP1Items], ii[kP1Items];
+#pragma unroll
+        for (int k = 0; k < kP1Items; ++k) {
+            kk[k] = sk[k * kP1NT + threadIdx.x];
+            ii[k] = si[k * kP1NT + threadIdx.x];
+        }
+#pragma unroll
+        for (int k = 0; k < kP1Items; ++k) {
+            const uint32_t o = gpos[kk[k] >> (31 - kHiBits)] + uint32_t(k * kP1NT + threadIdx.x);
+            okt[o] = kk[k];
+            oit[o] = b32 + ii[k];
+        }
+    } else {
+        for (int j = threadIdx.x; j < cnt; j += kP1NT) {
+            const uint32_t key = sk[j];
+            const uint32_t o = gpos[key >> (31 - kHiBits)] + uint32_t(j);
+            okt[o] = key;
+            oit[o] = b32 + si[j];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: one workgroup per (table, super-bin).
+// Pass 2: one workgroup per (table, group).
 //
-// Fast path (a super-bin of at most kTile entries whose bins all hold at most
-// kMaxFastBin entries -- the usual case): every entry takes a slot inside its
-// bin with one LDS atomic (slots in arbitrary order), the block scans the bin
-// counts into bin starts (the directory entries), the ids are placed in LDS
-// by slot, and each entry's final position is its bin start plus the number
-// of ids in its bin smaller than its own (ids are distinct; bins hold a
-// handful of entries).  Keys, then ids, are reordered through LDS and the
-// super-bin is written out contiguously.  The result equals the stable
-// reorder exactly.
+// A group of at most kFastTile entries (the usual case) is done by the group
+// kernel, which loads it once and counts its bins with LDS atomics; the
+// atomics also hand every entry a slot inside its bin, in arbitrary order.
+// The bin counts, scanned, are the bin starts (the directory entries).
 //
-// Otherwise the stable path: wave-ballot ranks in input order (pass 1 is
-// stable, so input order is id order), an LDS reorder, and for super-bins
-// over kTile entries a histogram read first and a chunk-by-chunk scatter with
-// running digit starts.
+// Slot branch, when no bin holds over kMaxFastBin entries: keys and ids are
+// placed in LDS by slot.  Then, walking the slots in order, each entry's
+// final position is its bin start plus the number of ids in its bin smaller
+// than its own (ids are distinct).  Neighbouring lanes hold neighbouring
+// slots, so they read the same few bins (LDS broadcasts) and loop about as
+// long as the largest of those bins; each writes its entry straight to its
+// final place, which lies inside the few cache lines the wave covers.
+//
+// Ballot branch, when a bin is larger (clustered data): stable ranks from
+// wave ballots in input order (passes 1 and 1b are stable, so input order is
+// id order), per-wave digit counters, and an LDS reorder.
+//
+// Either way the result equals the stable reorder exactly.  Groups over
+// kFastTile entries go to a second kernel: the same ballot ranks over a tile
+// of kTile entries, or for larger groups a histogram read first and a
+// chunk-by-chunk scatter with running digit starts.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMaxFastBin = 48;
+
+// Words of the group kernel's reorder region: two kFastTile buffers, which
+// also hold the stable branch's per-wave digit counters.
+__host__ __device__ constexpr int p2_region_a(int lo_bits) {
+    return 2 * kFastTile > (kWaves << lo_bits) ? 2 * kFastTile : (kWaves << lo_bits);
+}
 
 // Pass 2 works on groups: the entries of a table that share their top gbits
 // key bits (gbits = 8, or 8 + S after the pass-1b split), a contiguous run
@@ -315,80 +360,90 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t *sh) {
     return m;
 }
 
-// Fast path; returns false (having written nothing to the tables) when a bin
-// is too large for the per-entry rank count.
-__device__ bool p2_fast(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+// A group of at most kFastTile entries.  Entries are loaded wave-major (wave
+// w holds a contiguous run of the group, ipw rounds of 64), which the stable
+// branch needs and the fast branch does not mind.
+__device__ void p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
-    uint32_t *buf = lds;  // kTile words: ids in slot order, then keys, then ids in final order
-    uint32_t *cnt = lds + kTile;
-    uint32_t *start = cnt + R;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // region A: keys and ids in slot (fast) or final (stable) order; in the
+    // stable branch first the per-wave digit counters [kWaves][R]
+    uint32_t *bk = lds;
+    uint32_t *bv = lds + kFastTile;
+    uint32_t *cnt = lds + p2_region_a(a.lo_bits);  // R + 1 words: bin counts, then bin starts and the end
     for (int i = threadIdx.x; i < R; i += kNT) cnt[i] = 0;
+    if (threadIdx.x == 0) cnt[R] = a.count;
     __syncthreads();
-    uint32_t rk[kItems], rv[kItems], pos[kItems];
+    const uint32_t ipw = (a.count + kNT - 1) / kNT;  // rounds per wave, at most kFastItems
+    const uint32_t wbase = uint32_t(wave) * 64u * ipw + uint32_t(lane);
+    const auto ok = [&](int it) { return uint32_t(it) < ipw && wbase + uint32_t(it) * 64u < a.count; };
+    uint32_t rk[kFastItems], rv[kFastItems], pos[kFastItems];
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
-        const bool ok = e < a.count;
-        rk[it] = ok ? a.kin[e] : 0u;
-        rv[it] = ok ? a.vin[e] : 0u;
+    for (int it = 0; it < kFastItems; ++it) {
+        const uint32_t e = wbase + uint32_t(it) * 64u;
+        rk[it] = ok(it) ? a.kin[e] : 0u;
+        rv[it] = ok(it) ? a.vin[e] : 0u;
     }
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        if (uint32_t(it * kNT) >= a.count) break;  // block-uniform
-        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
-        pos[it] = e < a.count ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
-    }
+    for (int it = 0; it < kFastItems; ++it)
+        pos[it] = ok(it) ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
     __syncthreads();
     uint32_t mx = 0;
-    for (int i = threadIdx.x; i < R; i += kNT) {
-        mx = max(mx, cnt[i]);
-        start[i] = cnt[i];
+    for (int i = threadIdx.x; i < R; i += kNT) mx = max(mx, cnt[i]);
+    const bool fast = block_max_u32(mx, sh) <= kMaxFastBin;
+    if (!fast) {
+        for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // per-wave counters
     }
-    if (block_max_u32(mx, sh) > kMaxFastBin) return false;
-    digit_starts<kNT>(start, R, 0u, sh);
-    for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + start[i];
-    // ids into their bins, in slot order
+    digit_starts<kNT>(cnt, R, 0u, sh);  // ends with a barrier
+    for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + cnt[i];
+    if (fast) {
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        if (uint32_t(it * kNT) >= a.count) break;
-        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
-        if (e < a.count) {
-            pos[it] += start[(rk[it] >> a.shift) & a.mask];
-            buf[pos[it]] = rv[it];
+        for (int it = 0; it < kFastItems; ++it)
+            if (ok(it)) {
+                const uint32_t q = cnt[(rk[it] >> a.shift) & a.mask] + pos[it];
+                bk[q] = rk[it];
+                bv[q] = rv[it];
+            }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
+            const uint32_t k = bk[j], v = bv[j];
+            const uint32_t dg = (k >> a.shift) & a.mask;
+            const uint32_t b0 = cnt[dg], b1 = cnt[dg + 1];
+            uint32_t r = b0;
+            for (uint32_t q = b0; q < b1; ++q) r += bv[q] < v ? 1u : 0u;
+            a.okey[r] = k;
+            a.oid[r] = v;
+        }
+        return;
+    }
+    // stable branch: input order is id order; rank = bin start + entries of
+    // the bin in earlier waves + earlier entries of this wave
+    const auto digit = [&](int it) { return (rk[it] >> a.shift) & a.mask; };
+    wave_stable_ranks_of<kFastItems, 3>(digit, ok, a.lo_bits, lds + wave * R, pos);
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += kNT) {
+        uint32_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = lds[w * R + d];
+            lds[w * R + d] = run;
+            run += c;
         }
     }
     __syncthreads();
-    // final position = bin start + number of ids in the bin smaller than
-    // this one (ids are distinct): independent LDS reads, no serial chain
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        if (uint32_t(it * kNT) >= a.count) break;
-        const uint32_t e = uint32_t(it * kNT) + threadIdx.x;
-        if (e < a.count) {
-            const uint32_t dg = (rk[it] >> a.shift) & a.mask;
-            const uint32_t b0 = start[dg], m = cnt[dg];
-            uint32_t r = 0;
-            for (uint32_t k = 0; k < m; ++k) r += buf[b0 + k] < rv[it] ? 1u : 0u;
-            pos[it] = b0 + r;
+    for (int it = 0; it < kFastItems; ++it) pos[it] += cnt[digit(it)] + lds[wave * R + digit(it)];
+    __syncthreads();  // the counters' space becomes the reorder buffer
+#pragma unroll
+    for (int it = 0; it < kFastItems; ++it)
+        if (ok(it)) {
+            bk[pos[it]] = rk[it];
+            bv[pos[it]] = rv[it];
         }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
+        a.okey[j] = bk[j];
+        a.oid[j] = bv[j];
     }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        if (uint32_t(it * kNT) >= a.count) break;
-        if (uint32_t(it * kNT) + threadIdx.x < a.count) buf[pos[it]] = rk[it];
-    }
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < a.count; j += kNT) a.okey[j] = buf[j];
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        if (uint32_t(it * kNT) >= a.count) break;
-        if (uint32_t(it * kNT) + threadIdx.x < a.count) buf[pos[it]] = rv[it];
-    }
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < a.count; j += kNT) a.oid[j] = buf[j];
-    return true;
 }
 
 // Stable path for a super-bin of at most kTile entries.
@@ -486,7 +541,7 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
     const int64_t toff = int64_t(T) * n;
     // group starts per table: 2^gbits + 1 (<= 4097), so the index fits 32
     // bits and stays in scalar registers (a 64-bit product lands in vector
-    // registers, and the block-uniform loop exits of the fast path then
+    // registers, and the block-uniform loop exits of the group kernel then
     // become exec-masked)
     const uint32_t gs = (1u << gbits) + 1u;
     const uint32_t gi = uint32_t(T) * gs + uint32_t(g);
@@ -506,11 +561,11 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
     return a;
 }
 
-// Pass 2, fast path over every (table, group); the groups it leaves (over
-// kTile entries, or a large bin) are appended to rest[] for p2_rest_kernel.
+// Pass 2, group kernel over every (table, group); groups over kFastTile
+// entries are appended to rest[] for p2_rest_kernel.
 // (iids and tids may be the same array: the ids are then reordered in place,
 // each group reading its whole run into registers before writing it.)
-__global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
+__global__ __launch_bounds__(kNT, 6) void p2_fast_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
                                                          int64_t n, const uint32_t *__restrict__ gstart, int gbits,
                                                          int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids,
                                                          uint32_t *__restrict__ dir, uint32_t *__restrict__ rest,
@@ -523,12 +578,14 @@ __global__ __launch_bounds__(kNT, 4) void p2_fast_kernel(const uint32_t *__restr
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
     const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
-    const bool done = a.count <= uint32_t(kTile) && p2_fast(a, lds, sh);
-    if (!done && threadIdx.x == 0) rest[atomicAdd(rest_count, 1u)] = uint32_t(w);
+    if (a.count <= uint32_t(kFastTile))
+        p2_group(a, lds, sh);
+    else if (threadIdx.x == 0)
+        rest[atomicAdd(rest_count, 1u)] = uint32_t(w);
 }
 
-// Pass 2, stable path for the groups the fast path left: a fixed grid works
-// through the list (empty on uniform keys).  When the input ids are the
+// Pass 2, stable path for the groups the group kernel left: a fixed grid
+// works through the list (empty on uniform keys).  When the input ids are the
 // output id array (after the pass-1b split), a group taking the chunked
 // path first copies its ids to spare, which that path then reads.
 __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
@@ -721,7 +778,7 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     }
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
-    const size_t lds_fast = (size_t(kTile) + 2 * (size_t(1) << lo_bits)) * 4;
+    const size_t lds_fast = (size_t(p2_region_a(lo_bits)) + (size_t(1) << lo_bits) + 1) * 4;
     const int64_t nitems2 = int64_t(L) << gbits;  // (table, group) items, a multiple of kXcds
     hipLaunchKernelGGL(p2_fast_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n, gstart, gbits,
                        lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
