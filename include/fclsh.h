@@ -143,7 +143,8 @@ FCLSH_API fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, i
  * d_ids[d_offsets[i] .. d_offsets[i+1]).  *total_out (host) receives the
  * total number of reported ids.  If it exceeds ids_capacity the call returns
  * FCLSH_ECAPACITY with *total_out set and d_ids untouched (d_offsets is
- * written); retry with a larger buffer.
+ * written); fclsh_query_batch_finish then writes the ids into a larger
+ * buffer without recomputing them.
  * The call synchronises `stream` once, to read the result size.
  * Duplicate elimination: a verified near point is reported only from the
  * first table (in (part, v) order) whose mask it shares with the query;
@@ -224,6 +225,19 @@ FCLSH_API fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_quer
                                uint64_t *d_offsets, uint32_t *d_ids,
                                int64_t ids_capacity, int64_t *total_out);
 
+/* Completes the last fclsh_query_batch or fclsh_query_batch_radii call on
+ * `stream` that returned FCLSH_ECAPACITY: the pairs it found stay in the
+ * stream's workspace, and this call scatters and sorts them into d_ids
+ * (device, ids_capacity uint32) with no new verification.  d_offsets must be
+ * the offsets array that call wrote (its contents are used as written).
+ * *total_out (host) receives the total.  Errors: FCLSH_EINVAL if no such call
+ * is pending on `stream` (any other query call, reserve or collision count on
+ * the stream in between discards it) or d_offsets differs; FCLSH_ECAPACITY if
+ * ids_capacity is still too small (the batch stays pending).  Synchronises
+ * `stream`. */
+FCLSH_API fclsh_status fclsh_query_batch_finish(fclsh_index idx, void *stream, const uint64_t *d_offsets,
+                                                uint32_t *d_ids, int64_t ids_capacity, int64_t *total_out);
+
 /* ---------------------------------------------------------------------------
  * Batching and serving (batched execution of Strategy 2 for many queries).
  * ------------------------------------------------------------------------- */
@@ -244,9 +258,10 @@ FCLSH_API fclsh_status fclsh_query_reserve(fclsh_index idx, int64_t max_nq, int6
                                            int64_t spill_capacity, void *stream);
 
 /* The batched pipeline without any host synchronisation or allocation:
- * hash, bucket lookup, verification by persistent waves that pull work from
- * device queues (a bucket larger than the tuned tile is split into
- * tile-sized chunks), CSR offsets and per-query sorting, all enqueued on
+ * hash, bucket lookup, verification by persistent waves that stride over the
+ * (query, table) items and then over a device queue of chunks of the larger
+ * buckets (a bucket larger than the tuned tile is split into tile-sized
+ * chunks), CSR offsets and per-query sorting, all enqueued on
  * `stream`.  The workspace of `stream` must have been reserved for nq
  * queries.  r_query applies to all queries unless d_radii (device, nq int32)
  * is given.  Outputs as fclsh_query_batch, plus d_result (device, 2 uint64):

@@ -34,7 +34,7 @@ EXPORTS = [
     "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_index_rebuild_timed", "fclsh_query_collisions", "fclsh_query_plain",
     "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
-    "fclsh_autotune",
+    "fclsh_autotune", "fclsh_query_batch_finish",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -81,6 +81,7 @@ def lib():
             "fclsh_index_rebuild_timed": [vp, vp, P(ctypes.c_float), i32],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
+            "fclsh_query_batch_finish": [vp, vp, vp, vp, i64, P(i64)],
             "fclsh_query_reserve": [vp, i64, i64, i64, vp],
             "fclsh_query_batch_async": [vp, vp, i64, i32, vp, vp, vp, vp, i64, vp],
             "fclsh_query_graph_create": [vp, vp, i64, i32, vp, vp, vp, i64, vp, vp, P(vp)],
@@ -180,6 +181,7 @@ class Index:
         self._h = h
         self.d = d
         self.device = pts.device
+        self._ids_per_query = 64.0  # sizes the id buffer of the next batch
         del torch
 
     @classmethod
@@ -267,23 +269,42 @@ class Index:
         _memcpy_d2d(out.data_ptr(), dp, inf["L"] * nb * 4)
         return out
 
-    def _run_query(self, fn, queries, r: int, ids_capacity=None, stream=None):
+    def _default_capacity(self, nq: int) -> int:
+        # ids per query seen in the last batch, with a margin, at least 64
+        return max(1024, int(nq * self._ids_per_query) + 1)
+
+    def _collect(self, st, offsets, ids, total, nq, stream, finish: bool, explicit: bool):
+        """Result of a batch call: on FCLSH_ECAPACITY with a library-sized
+        buffer, the pending batch is finished into a buffer of the reported
+        size (no recomputation)."""
+        torch = _torch()
+        if st == FCLSH_ECAPACITY and not explicit:
+            if not finish:
+                return None
+            ids = torch.empty(max(total.value, 1), dtype=torch.int32, device=offsets.device)
+            st = lib().fclsh_query_batch_finish(self._h, _stream_ptr(stream), ctypes.c_void_p(offsets.data_ptr()),
+                                                ctypes.c_void_p(ids.data_ptr()), ids.numel(), ctypes.byref(total))
+        _check(st)
+        if nq:
+            self._ids_per_query = max(64.0, 1.25 * total.value / nq)
+        return offsets, ids[:total.value]
+
+    def _run_query(self, fn, queries, r: int, ids_capacity=None, stream=None, finish=True):
         torch = _torch()
         q = _dev_words(queries, self.d, "queries")
         nq = q.shape[0]
         offsets = torch.empty(nq + 1, dtype=torch.int64, device=q.device)
-        cap = int(ids_capacity) if ids_capacity is not None else max(1024, 64 * nq)
+        cap = int(ids_capacity) if ids_capacity is not None else self._default_capacity(nq)
         total = ctypes.c_int64()
         for _ in range(2):
             ids = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
             st = fn(self._h, ctypes.c_void_p(q.data_ptr()), nq, r, _stream_ptr(stream),
                     ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(ids.data_ptr()), cap,
                     ctypes.byref(total))
-            if st == FCLSH_ECAPACITY and ids_capacity is None:
-                cap = total.value
-                continue
-            _check(st)
-            return offsets, ids[:total.value]
+            res = self._collect(st, offsets, ids, total, nq, stream, finish, ids_capacity is not None)
+            if res is not None:
+                return res
+            cap = total.value  # the plain path answers again into a larger buffer
         raise FclshError(FCLSH_ECAPACITY, "result did not fit after resizing")
 
     def query(self, queries, r: int, ids_capacity=None, stream=None):
@@ -292,7 +313,7 @@ class Index:
 
     def query_plain(self, queries, r: int, ids_capacity=None, stream=None):
         """Same answers via one launch sequence per query (the unbatched baseline)."""
-        return self._run_query(lib().fclsh_query_plain, queries, r, ids_capacity, stream)
+        return self._run_query(lib().fclsh_query_plain, queries, r, ids_capacity, stream, finish=False)
 
     def query_radii(self, queries, radii, ids_capacity=None, stream=None):
         """Exact r-NN reporting with one radius per query (int32 CUDA tensor)."""
@@ -304,20 +325,23 @@ class Index:
             raise ValueError("one radius per query")
         rmax = int(rad.max().item()) if nq else 0
         offsets = torch.empty(nq + 1, dtype=torch.int64, device=q.device)
-        cap = int(ids_capacity) if ids_capacity is not None else max(1024, 64 * nq)
+        cap = int(ids_capacity) if ids_capacity is not None else self._default_capacity(nq)
         total = ctypes.c_int64()
-        for _ in range(2):
-            ids = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
-            st = lib().fclsh_query_batch_radii(self._h, ctypes.c_void_p(q.data_ptr()), nq,
-                                               ctypes.c_void_p(rad.data_ptr()), rmax, _stream_ptr(stream),
-                                               ctypes.c_void_p(offsets.data_ptr()),
-                                               ctypes.c_void_p(ids.data_ptr()), cap, ctypes.byref(total))
-            if st == FCLSH_ECAPACITY and ids_capacity is None:
-                cap = total.value
-                continue
-            _check(st)
-            return offsets, ids[:total.value]
-        raise FclshError(FCLSH_ECAPACITY, "result did not fit after resizing")
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
+        st = lib().fclsh_query_batch_radii(self._h, ctypes.c_void_p(q.data_ptr()), nq,
+                                           ctypes.c_void_p(rad.data_ptr()), rmax, _stream_ptr(stream),
+                                           ctypes.c_void_p(offsets.data_ptr()),
+                                           ctypes.c_void_p(ids.data_ptr()), cap, ctypes.byref(total))
+        return self._collect(st, offsets, ids, total, nq, stream, True, ids_capacity is not None)
+
+    def query_finish(self, offsets, ids, stream=None) -> int:
+        """fclsh_query_batch_finish: after a batch call with an explicit
+        ids_capacity failed with FCLSH_ECAPACITY, writes its ids into `ids`
+        (int32 CUDA tensor); returns the total."""
+        total = ctypes.c_int64()
+        _check(lib().fclsh_query_batch_finish(self._h, _stream_ptr(stream), ctypes.c_void_p(offsets.data_ptr()),
+                                              ctypes.c_void_p(ids.data_ptr()), ids.numel(), ctypes.byref(total)))
+        return total.value
 
     def reserve(self, max_nq: int, pair_capacity: int, spill_capacity: int = 1 << 16, stream=None):
         """Size the stream's query workspace for the asynchronous / graph path."""

@@ -375,6 +375,16 @@ fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries, int64
                        ids_capacity, total_out);
 }
 
+fclsh_status fclsh_query_batch_finish(fclsh_index idx, void *stream, const uint64_t *d_offsets, uint32_t *d_ids,
+                                      int64_t ids_capacity, int64_t *total_out) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    IndexHandle *h = handle(idx);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return query_finish(h->ix, *h->workspace(st), st, d_offsets, d_ids, ids_capacity, total_out);
+}
+
 fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries, int64_t nq, void *stream,
                                     uint64_t *d_collisions) {
     if (!idx) return fail(FCLSH_EINVAL, "null index");

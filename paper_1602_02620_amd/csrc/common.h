@@ -169,9 +169,7 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
 
 // Device-side control block of one query batch.
 struct QueryCtrl {
-    unsigned long long item_head;   // next (query, table) item to verify
     unsigned long long spills;      // spill chunks recorded
-    unsigned long long spill_head;  // next spill chunk to verify
     unsigned long long pairs;       // reported (query, id) pairs
     unsigned long long total;       // pairs, as published with the offsets
     uint32_t status;                // kQuery*Overflow bits
@@ -190,6 +188,10 @@ struct QueryWorkspace {
     uint32_t *pq = nullptr, *pid = nullptr, *sorttmp = nullptr;
     uint4 *spill = nullptr;
     int64_t cap_items = 0, cap_q = 0, cap_pairs = 0, cap_spill = 0;
+    // a synchronous batch whose ids did not fit the caller's buffer: its
+    // pairs stay here until the next query call on the stream
+    int64_t pending_nq = -1, pending_total = 0;
+    const uint64_t *pending_offsets = nullptr;
 };
 
 fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills);
@@ -200,6 +202,8 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
 fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                          const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap,
                          int64_t *total_out);
+fclsh_status query_finish(Index &ix, QueryWorkspace &ws, hipStream_t st, const uint64_t *offsets, uint32_t *ids,
+                          int64_t ids_cap, int64_t *total_out);
 fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                          hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
 fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq,

@@ -121,7 +121,10 @@ __device__ inline int hamming(const uint64_t *x, const uint64_t *q, int W, uint6
 }
 
 // Records (qi, id) for the lanes of the wave that call it together: one
-// atomic per wave for the pair slots (the first active lane takes them).
+// atomic per wave for the pair slots (the first active lane takes them) and
+// one per distinct query for the per-query counts (the calling lanes mostly
+// share one or two queries, whose counters would otherwise take one atomic
+// per lane on the same address).
 __device__ inline void emit_pair(const VerifyArgs &a, int64_t qi, uint32_t id) {
     const int lane = threadIdx.x & 63;
     const uint64_t act = __ballot(1);
@@ -131,7 +134,14 @@ __device__ inline void emit_pair(const VerifyArgs &a, int64_t qi, uint32_t id) {
     base = __shfl(base, leader, 64);
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const unsigned long long slot = base + __popcll(act & lt);
-    atomicAdd(&a.qcount[qi], 1u);
+    const uint32_t q32 = uint32_t(qi);  // nq * L < 2^32
+    for (uint64_t rem = act; rem;) {
+        const int l = __builtin_ctzll(rem);
+        const uint32_t q0 = uint32_t(__shfl(int(q32), l, 64));
+        const uint64_t same = __ballot(q32 == q0) & rem;
+        if (lane == l) atomicAdd(&a.qcount[q0], uint32_t(__popcll(same)));
+        rem &= ~same;
+    }
     if (slot < (unsigned long long)a.pair_cap) {
         a.out_q[slot] = uint32_t(qi);
         a.out_id[slot] = id;
@@ -214,20 +224,19 @@ __global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill,
     }
 }
 
-// S2 + S3, pass 1: waves claim 64 (query, table) items per atomic, a lane
-// per item.  The lane probes the directory; a bin of at most kLaneBin entries
-// is scanned and verified by the lane alone, a larger one is cut into
-// `tile`-entry chunks on the spill queue.  Every wave leaves once the counter
-// passes the number of items.
+// S2 + S3, pass 1: a lane per (query, table) item; wave g takes the rounds
+// of 64 items g, g + G, g + 2G, ... (G waves in the grid; no claim counter,
+// which would serialise one atomic per round on one address).  The lane
+// probes the directory; a bin of at most kLaneBin entries is scanned and
+// verified by the lane alone, a larger one is cut into `tile`-entry chunks on
+// the spill queue.
 __global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long items = (unsigned long long)(a.nq * a.L);
     const int64_t nb = int64_t(1) << a.dir_bits;
-    for (;;) {
-        unsigned long long it0 = 0;
-        if (lane == 0) it0 = atomicAdd(&a.ctrl->item_head, 64ull);
-        it0 = __shfl(it0, 0, 64);
-        if (it0 >= items) break;
+    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
+    for (unsigned long long it0 = ((unsigned long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 64;
+         it0 < items; it0 += nw * 64) {
         const unsigned long long it = it0 + lane;
         if (it >= items) continue;
         const int64_t qi = int64_t(it) / a.L;
@@ -264,17 +273,16 @@ __global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
     }
 }
 
-// S3, pass 2: persistent waves drain the spill queue (every wave leaves once
-// the counter passes the number of recorded chunks; with no chunks, at once).
+// S3, pass 2: persistent waves verify the recorded chunks, wave g taking
+// chunks g, g + G, g + 2G, ... (G waves in the grid).  The chunks of one
+// batch number up to the hundreds of thousands: a shared claim counter would
+// serialise that many atomics on one address, while the fixed stride spreads
+// the chunks' uneven costs over tens of chunks per wave.
 __global__ __launch_bounds__(256) void verify_spill_kernel(VerifyArgs a) {
-    const int lane = threadIdx.x & 63;
     const unsigned long long nsp = min((unsigned long long)a.spill_cap, a.ctrl->spills);
-    if (nsp == 0) return;
-    for (;;) {
-        unsigned long long k = 0;
-        if (lane == 0) k = atomicAdd(&a.ctrl->spill_head, 1ull);
-        k = __shfl(k, 0, 64);
-        if (k >= nsp) break;
+    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
+    for (unsigned long long k = (unsigned long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); k < nsp;
+         k += nw) {
         const uint4 r = a.spill[k];
         const int64_t qi = int64_t(r.x) / a.L;
         const int T = int(int64_t(r.x) - qi * a.L);
@@ -431,6 +439,7 @@ uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 
 }  // namespace
 
 fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills) {
+    ws.pending_nq = -1;  // buffers may be replaced: nothing pending survives
     const int64_t items = nq * L;
     if (items > ws.cap_items || !ws.qkeys) {
         FCLSH_TRY(regrow(&ws.qkeys, items, "query keys"));
@@ -493,10 +502,39 @@ fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *que
 // synchronisation (the workspace must already hold nq queries, ws.cap_pairs
 // pairs and ws.cap_spill spill chunks).  Outputs: offsets[nq+1], ids (up to
 // ids_cap), and ws.ctrl->{total, status}.
+namespace {
+
+// Clears the id-buffer overflow flag and the per-query fill counters, so that
+// the pairs of the last batch can be scattered into a new id buffer.
+__global__ void rearm_scatter_kernel(QueryCtrl *ctrl, uint32_t *qfill, int64_t nq) {
+    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i0 == 0) ctrl->status &= ~kQueryIdsOverflow;
+    for (int64_t i = i0; i < nq; i += int64_t(gridDim.x) * blockDim.x) qfill[i] = 0;
+}
+
+// Pairs into the per-query segments of ids, then each segment sorted.
+fclsh_status launch_scatter_sort(Index &ix, QueryWorkspace &ws, int64_t nq, const uint64_t *offsets, uint32_t *ids,
+                                 int64_t ids_cap, hipStream_t st) {
+    hipLaunchKernelGGL(scatter_pairs_kernel, dim3(grid_for(ws.cap_pairs, 256, 4096)), dim3(256), 0, st, ws.pq,
+                       ws.pid, ws.ctrl, ws.cap_pairs, offsets, ws.qfill, ids, ids_cap);
+    FCLSH_HIP(hipGetLastError());
+    const int idbits = std::max(1, ilog2_ceil(uint64_t(ix.n)));
+    for (int64_t q0 = 0; q0 < nq; q0 += 65535) {
+        const int64_t qn = std::min<int64_t>(65535, nq - q0);
+        hipLaunchKernelGGL(segment_sort_kernel, dim3(unsigned(qn)), dim3(kSortNT), 0, st, offsets + q0, ws.ctrl,
+                           ids, ws.sorttmp, idbits);
+        FCLSH_HIP(hipGetLastError());
+    }
+    return FCLSH_OK;
+}
+
+}  // namespace
+
 fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                                const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids,
                                int64_t ids_cap) {
     const int L = ix.prm.L();
+    ws.pending_nq = -1;
     const QueryTuning &tu = ix.tuning;
     if (nq * L > ws.cap_items || nq + 1 > ws.cap_q || !ws.ctrl || !ws.pq || !ws.spill)
         return fail(FCLSH_EINVAL, "query workspace not reserved for %lld queries", (long long)nq);
@@ -549,18 +587,27 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     hipLaunchKernelGGL(finish_offsets_kernel, dim3(1), dim3(1), 0, st, offsets, nq, ws.ctrl, ws.cap_pairs,
                        ws.cap_spill, ids_cap);
     FCLSH_HIP(hipGetLastError());
-    if (nq > 0 && ids_cap > 0) {
-        hipLaunchKernelGGL(scatter_pairs_kernel, dim3(grid_for(ws.cap_pairs, 256, 4096)), dim3(256), 0, st, ws.pq,
-                           ws.pid, ws.ctrl, ws.cap_pairs, offsets, ws.qfill, ids, ids_cap);
-        FCLSH_HIP(hipGetLastError());
-        const int idbits = std::max(1, ilog2_ceil(uint64_t(ix.n)));
-        for (int64_t q0 = 0; q0 < nq; q0 += 65535) {
-            const int64_t qn = std::min<int64_t>(65535, nq - q0);
-            hipLaunchKernelGGL(segment_sort_kernel, dim3(unsigned(qn)), dim3(kSortNT), 0, st, offsets + q0, ws.ctrl,
-                               ids, ws.sorttmp, idbits);
-            FCLSH_HIP(hipGetLastError());
-        }
-    }
+    if (nq > 0 && ids_cap > 0) FCLSH_TRY(launch_scatter_sort(ix, ws, nq, offsets, ids, ids_cap, st));
+    return FCLSH_OK;
+}
+
+// Finishes the pending synchronous batch of the workspace into a larger id
+// buffer: the stored pairs are scattered and sorted again, with no
+// recomputation.
+fclsh_status query_finish(Index &ix, QueryWorkspace &ws, hipStream_t st, const uint64_t *offsets, uint32_t *ids,
+                          int64_t ids_cap, int64_t *total_out) {
+    if (ws.pending_nq < 0) return fail(FCLSH_EINVAL, "no batch on this stream is waiting for a larger id buffer");
+    if (offsets != ws.pending_offsets) return fail(FCLSH_EINVAL, "offsets differ from those of the pending batch");
+    *total_out = ws.pending_total;
+    if (ids_cap < ws.pending_total)
+        return fail(FCLSH_ECAPACITY, "%lld ids do not fit the output capacity %lld", (long long)ws.pending_total,
+                    (long long)ids_cap);
+    const int64_t nq = ws.pending_nq;
+    ws.pending_nq = -1;
+    hipLaunchKernelGGL(rearm_scatter_kernel, dim3(grid_for(nq, 256, 1024)), dim3(256), 0, st, ws.ctrl, ws.qfill, nq);
+    FCLSH_HIP(hipGetLastError());
+    if (nq > 0 && ids_cap > 0) FCLSH_TRY(launch_scatter_sort(ix, ws, nq, offsets, ids, ids_cap, st));
+    FCLSH_HIP(hipStreamSynchronize(st));
     return FCLSH_OK;
 }
 
@@ -586,9 +633,13 @@ fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
     if (h.status & (kQueryPairOverflow | kQuerySpillOverflow))
         return fail(FCLSH_ENOMEM, "query buffers kept overflowing");
     *total_out = int64_t(h.total);
-    if (h.status & kQueryIdsOverflow)
+    if (h.status & kQueryIdsOverflow) {
+        ws.pending_nq = nq;
+        ws.pending_total = int64_t(h.total);
+        ws.pending_offsets = offsets;
         return fail(FCLSH_ECAPACITY, "%lld ids do not fit the output capacity %lld", (long long)h.total,
                     (long long)ids_cap);
+    }
     return FCLSH_OK;
 }
 
@@ -612,6 +663,7 @@ fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
         run += got;
         off[size_t(i) + 1] = uint64_t(run);
     }
+    ws.pending_nq = -1;  // per-query batches above; nothing to finish for the whole
     FCLSH_HIP(hipMemcpyAsync(offsets, off.data(), off.size() * 8, hipMemcpyHostToDevice, st));
     FCLSH_HIP(hipStreamSynchronize(st));
     *total_out = run;

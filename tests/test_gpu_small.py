@@ -263,6 +263,56 @@ def test_radius_and_capacity_errors():
     idx.close()
 
 
+def test_finish_after_capacity_error():
+    """A batch whose ids overflow the buffer is finished into a larger one
+    from the pairs it already found (fclsh_query_batch_finish)."""
+    import ctypes
+    w = synth.learned_code(0.001)  # 10,000 points in 10 clusters: hundreds of neighbours per query
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=5)
+    bf = oracle.brute_force(w.points, w.d, w.queries, w.r)
+    total_want = sum(len(x) for x in bf.ids)
+    assert total_want > 64 * len(w.queries)
+    # the binding's first buffer (64 ids per query) overflows; it finishes
+    offs, ids = idx.query(dev(w.queries), w.r)
+    assert_same_lists(csr_lists(offs, ids), bf.ids)
+    # through the C-ABI: too small, still too small, then large enough
+    L = fc.lib()
+    q = dev(w.queries)
+    nq = q.shape[0]
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    small = torch.empty(8, dtype=torch.int32, device="cuda")
+    total = ctypes.c_int64()
+    st = L.fclsh_query_batch(idx._h, ctypes.c_void_p(q.data_ptr()), nq, w.r, stream,
+                             ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(small.data_ptr()), 8,
+                             ctypes.byref(total))
+    assert st == fc.FCLSH_ECAPACITY and total.value == total_want
+    st = L.fclsh_query_batch_finish(idx._h, stream, ctypes.c_void_p(offsets.data_ptr()),
+                                    ctypes.c_void_p(small.data_ptr()), 8, ctypes.byref(total))
+    assert st == fc.FCLSH_ECAPACITY
+    other = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    big = torch.full((total_want,), -1, dtype=torch.int32, device="cuda")
+    st = L.fclsh_query_batch_finish(idx._h, stream, ctypes.c_void_p(other.data_ptr()),
+                                    ctypes.c_void_p(big.data_ptr()), total_want, ctypes.byref(total))
+    assert st == fc.FCLSH_EINVAL
+    assert idx.query_finish(offsets, big) == total_want
+    assert_same_lists(csr_lists(offsets, big), bf.ids)
+    # nothing is pending any more
+    with pytest.raises(fc.FclshError) as e:
+        idx.query_finish(offsets, big)
+    assert e.value.status == fc.FCLSH_EINVAL
+    # another call on the stream discards a pending batch
+    st = L.fclsh_query_batch(idx._h, ctypes.c_void_p(q.data_ptr()), nq, w.r, stream,
+                             ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(small.data_ptr()), 8,
+                             ctypes.byref(total))
+    assert st == fc.FCLSH_ECAPACITY
+    idx.query(q[:1], w.r)
+    with pytest.raises(fc.FclshError) as e:
+        idx.query_finish(offsets, big)
+    assert e.value.status == fc.FCLSH_EINVAL
+    idx.close()
+
+
 def test_bad_build_arguments():
     x = dev(synth.uniform_points(10, 64, np.random.default_rng(1)))
     with pytest.raises(fc.FclshError) as e:
