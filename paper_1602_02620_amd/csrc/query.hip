@@ -120,31 +120,70 @@ __device__ inline int hamming(const uint64_t *x, const uint64_t *q, int W, uint6
     return dist;
 }
 
-// Records (qi, id) for the lanes of the wave that call it together: one
-// atomic per wave for the pair slots (the first active lane takes them) and
-// one per distinct query for the per-query counts (the calling lanes mostly
-// share one or two queries, whose counters would otherwise take one atomic
-// per lane on the same address).
-__device__ inline void emit_pair(const VerifyArgs &a, int64_t qi, uint32_t id) {
+// Reported pairs are staged per wave in LDS (kPairBuf of them) and copied to
+// the pair buffer when the stage is full and when the wave ends, each copy
+// reserving exactly its slots with one atomic.  A batch reports up to millions
+// of pairs, and one counter shared by every emitting wave round serialised
+// that many atomics on one address.  The stage count is read and written with
+// wavefront-scope atomics: lanes that skipped an earlier emission must still
+// see its count.
+constexpr uint32_t kPairBuf = 256;
+constexpr int kVerifyWaves = 4;  // waves per verification workgroup
+
+struct PairStage {
+    uint32_t *q, *id, *count;  // this wave's slice of the workgroup's LDS
+};
+
+__device__ inline uint32_t stage_count(const PairStage &ps) {
+    return __hip_atomic_load(ps.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Copies the c staged pairs out; called by the active lanes of the wave.
+__device__ inline void flush_pairs(const VerifyArgs &a, const PairStage &ps, uint32_t c) {
     const int lane = threadIdx.x & 63;
     const uint64_t act = __ballot(1);
     const int leader = __builtin_ctzll(act);
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(&a.ctrl->pairs, (unsigned long long)__popcll(act));
-    base = __shfl(base, leader, 64);
+    const uint32_t k = uint32_t(__popcll(act));
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const unsigned long long slot = base + __popcll(act & lt);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned long long base = 0;
+    if (lane == leader && c) base = atomicAdd(&a.ctrl->pairs, (unsigned long long)c);
+    base = __shfl(base, leader, 64);
+    for (uint32_t j = uint32_t(__popcll(act & lt)); j < c; j += k) {
+        const unsigned long long slot = base + j;
+        if (slot < (unsigned long long)a.pair_cap) {
+            a.out_q[slot] = ps.q[j];
+            a.out_id[slot] = ps.id[j];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+// Records (qi, id) for the lanes of the wave that call it together, plus one
+// count atomic per distinct query among them (the calling lanes mostly share
+// one or two queries).
+__device__ inline void emit_pair(const VerifyArgs &a, const PairStage &ps, int64_t qi, uint32_t id) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t act = __ballot(1);
+    const uint32_t n = uint32_t(__popcll(act));
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint32_t c = stage_count(ps);
+    if (c + n > kPairBuf) {
+        flush_pairs(a, ps, c);
+        c = 0;
+    }
+    const uint32_t j = c + uint32_t(__popcll(act & lt));
     const uint32_t q32 = uint32_t(qi);  // nq * L < 2^32
+    ps.q[j] = q32;
+    ps.id[j] = id;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __hip_atomic_store(ps.count, c + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     for (uint64_t rem = act; rem;) {
         const int l = __builtin_ctzll(rem);
         const uint32_t q0 = uint32_t(__shfl(int(q32), l, 64));
         const uint64_t same = __ballot(q32 == q0) & rem;
         if (lane == l) atomicAdd(&a.qcount[q0], uint32_t(__popcll(same)));
         rem &= ~same;
-    }
-    if (slot < (unsigned long long)a.pair_cap) {
-        a.out_q[slot] = uint32_t(qi);
-        a.out_id[slot] = id;
     }
 }
 
@@ -161,7 +200,8 @@ __device__ inline bool near_in_table(const VerifyArgs &a, int64_t qi, int T, uin
 
 // Whole wave, uniform arguments: entries [j0, j1) of table T (absolute
 // positions), a lane per entry.
-__device__ inline void verify_range(const VerifyArgs &a, int64_t qi, int T, uint32_t j0, uint32_t j1) {
+__device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, int64_t qi, int T, uint32_t j0,
+                                    uint32_t j1) {
     const int lane = threadIdx.x & 63;
     const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
     const uint32_t *ids = a.tids + int64_t(T) * a.n;
@@ -173,7 +213,7 @@ __device__ inline void verify_range(const VerifyArgs &a, int64_t qi, int T, uint
             const uint32_t key = bk[j];
             if (key == qkey) {
                 const uint32_t id = ids[j];
-                if (near_in_table(a, qi, T, qkey, rq, key, id)) emit_pair(a, qi, id);
+                if (near_in_table(a, qi, T, qkey, rq, key, id)) emit_pair(a, ps, qi, id);
             }
         }
     }
@@ -230,31 +270,51 @@ __global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill,
 // probes the directory; a bin of at most kLaneBin entries is scanned and
 // verified by the lane alone, a larger one is cut into `tile`-entry chunks on
 // the spill queue.
-__global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
-    const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyArgs a) {
+    __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const PairStage ps{stq[wave], sti[wave], &stc[wave]};
+    if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     const unsigned long long items = (unsigned long long)(a.nq * a.L);
     const int64_t nb = int64_t(1) << a.dir_bits;
-    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
-    for (unsigned long long it0 = ((unsigned long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 64;
-         it0 < items; it0 += nw * 64) {
+    const unsigned long long nw = (unsigned long long)gridDim.x * kVerifyWaves;
+    for (unsigned long long it0 = ((unsigned long long)blockIdx.x * kVerifyWaves + wave) * 64; it0 < items;
+         it0 += nw * 64) {
         const unsigned long long it = it0 + lane;
-        if (it >= items) continue;
-        const int64_t qi = int64_t(it) / a.L;
+        const bool valid = it < items;
+        const int64_t qi = valid ? int64_t(it) / a.L : 0;
         const int T = int(int64_t(it) - qi * a.L);
-        const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
-        const uint32_t *dr = a.dir + int64_t(T) * (nb + 1);
-        const uint32_t bin = qkey >> (31 - a.dir_bits);
-        const uint32_t lo = dr[bin], hi = dr[bin + 1];
-        if (hi - lo > kLaneBin) {
-            const uint32_t nch = (hi - lo + a.tile - 1) / a.tile;
-            const unsigned long long at = atomicAdd(&a.ctrl->spills, (unsigned long long)nch);
+        uint32_t qkey = 0, lo = 0, hi = 0;
+        if (valid) {
+            qkey = a.qkeys[int64_t(T) * a.nq + qi];
+            const uint32_t *dr = a.dir + int64_t(T) * (nb + 1);
+            const uint32_t bin = qkey >> (31 - a.dir_bits);
+            lo = dr[bin];
+            hi = dr[bin + 1];
+        }
+        // bins over kLaneBin entries go to the spill queue: the wave's
+        // chunk counts are summed (exclusive prefix across lanes) and
+        // reserved with one atomic
+        const uint32_t nch = (valid && hi - lo > kLaneBin) ? (hi - lo + a.tile - 1) / a.tile : 0u;
+        uint32_t pre = nch;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = uint32_t(__shfl_up(int(pre), o, 64));
+            if (lane >= o) pre += y;
+        }
+        const uint32_t wtot = uint32_t(__shfl(int(pre), 63, 64));
+        pre -= nch;
+        if (wtot) {
+            unsigned long long at = 0;
+            if (lane == 0) at = atomicAdd(&a.ctrl->spills, (unsigned long long)wtot);
+            at = __shfl(at, 0, 64) + pre;
             for (uint32_t c = 0; c < nch; ++c)
                 if (at + c < (unsigned long long)a.spill_cap) {
                     const uint32_t b = lo + c * a.tile;
                     a.spill[at + c] = make_uint4(uint32_t(it), b, min(hi, b + a.tile), 0u);
                 }
-            continue;
         }
+        if (!valid || nch) continue;
         const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
         const uint32_t *ids = a.tids + int64_t(T) * a.n;
         const int rq = query_radius(a, qi);
@@ -267,10 +327,11 @@ __global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
             for (int c = 0; c < 8; ++c)
                 if (kk[c] == qkey) {
                     const uint32_t id = ids[j0 + c];
-                    if (near_in_table(a, qi, T, qkey, rq, qkey, id)) emit_pair(a, qi, id);
+                    if (near_in_table(a, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
                 }
         }
     }
+    flush_pairs(a, ps, stage_count(ps));
 }
 
 // S3, pass 2: persistent waves verify the recorded chunks, wave g taking
@@ -278,16 +339,20 @@ __global__ __launch_bounds__(256) void verify_items_kernel(VerifyArgs a) {
 // batch number up to the hundreds of thousands: a shared claim counter would
 // serialise that many atomics on one address, while the fixed stride spreads
 // the chunks' uneven costs over tens of chunks per wave.
-__global__ __launch_bounds__(256) void verify_spill_kernel(VerifyArgs a) {
+__global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyArgs a) {
+    __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const PairStage ps{stq[wave], sti[wave], &stc[wave]};
+    if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     const unsigned long long nsp = min((unsigned long long)a.spill_cap, a.ctrl->spills);
-    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
-    for (unsigned long long k = (unsigned long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); k < nsp;
-         k += nw) {
+    const unsigned long long nw = (unsigned long long)gridDim.x * kVerifyWaves;
+    for (unsigned long long k = (unsigned long long)blockIdx.x * kVerifyWaves + wave; k < nsp; k += nw) {
         const uint4 r = a.spill[k];
         const int64_t qi = int64_t(r.x) / a.L;
         const int T = int(int64_t(r.x) - qi * a.L);
-        verify_range(a, qi, T, r.y, r.z);
+        verify_range(a, ps, qi, T, r.y, r.z);
     }
+    flush_pairs(a, ps, stage_count(ps));
 }
 
 __global__ void widen_counts_kernel(const uint32_t *__restrict__ c32, int64_t nq, uint64_t *__restrict__ c64) {
@@ -574,11 +639,11 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.tile = uint32_t(tu.tile);
     const unsigned vblocks = unsigned(std::max(1, tu.blocks_per_cu * ix.num_cus));
     if (nq > 0) {
-        // the item pass needs no more waves than 64-item claims
-        const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 256));
-        hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(256), 0, st, a);
+        // the item pass needs no more waves than rounds of 64 items
+        const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 64 * kVerifyWaves));
+        hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(64 * kVerifyWaves), 0, st, a);
         FCLSH_HIP(hipGetLastError());
-        hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(64 * kVerifyWaves), 0, st, a);
         FCLSH_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(widen_counts_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.qcount, nq, ws.qcount64);
