@@ -102,10 +102,30 @@ struct VerifyArgs {
     int64_t pair_cap;
     uint32_t *qcount;
     uint32_t tile;
+    int table_major;  // item numbering, see item_coords
 };
+
+// (query, table) of a verification item.  Large batches number the items
+// table-major (it = T * nq + qi), so that neighbouring lanes read
+// neighbouring query keys of one table ([L][nq] layout); small batches
+// number them query-major (it = qi * L + T), which touches fewer distinct
+// directory lines per wave when the query keys are few anyway.  nq * L < 2^32.
+__device__ inline void item_coords(const VerifyArgs &a, uint32_t it, int64_t &qi, int &T) {
+    if (a.table_major) {
+        const uint32_t t = it / uint32_t(a.nq);
+        T = int(t);
+        qi = int64_t(it - t * uint32_t(a.nq));
+    } else {
+        const uint32_t q = it / uint32_t(a.L);
+        qi = int64_t(q);
+        T = int(it - q * uint32_t(a.L));
+    }
+}
 
 // Bins of at most this many entries are scanned by one lane.
 constexpr uint32_t kLaneBin = 32;
+// Batches of more queries number their items table-major.
+constexpr int64_t kTableMajorBatch = 2048;
 
 __device__ inline int query_radius(const VerifyArgs &a, int64_t qi) { return a.rq_vec ? a.rq_vec[qi] : a.rq; }
 
@@ -282,8 +302,9 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
          it0 += nw * 64) {
         const unsigned long long it = it0 + lane;
         const bool valid = it < items;
-        const int64_t qi = valid ? int64_t(it) / a.L : 0;
-        const int T = int(int64_t(it) - qi * a.L);
+        int64_t qi = 0;
+        int T = 0;
+        if (valid) item_coords(a, uint32_t(it), qi, T);
         uint32_t qkey = 0, lo = 0, hi = 0;
         if (valid) {
             qkey = a.qkeys[int64_t(T) * a.nq + qi];
@@ -348,8 +369,9 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyA
     const unsigned long long nw = (unsigned long long)gridDim.x * kVerifyWaves;
     for (unsigned long long k = (unsigned long long)blockIdx.x * kVerifyWaves + wave; k < nsp; k += nw) {
         const uint4 r = a.spill[k];
-        const int64_t qi = int64_t(r.x) / a.L;
-        const int T = int(int64_t(r.x) - qi * a.L);
+        int64_t qi;
+        int T;
+        item_coords(a, r.x, qi, T);
         verify_range(a, ps, qi, T, r.y, r.z);
     }
     flush_pairs(a, ps, stage_count(ps));
@@ -637,6 +659,7 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.pair_cap = ws.cap_pairs;
     a.qcount = ws.qcount;
     a.tile = uint32_t(tu.tile);
+    a.table_major = nq > kTableMajorBatch ? 1 : 0;
     const unsigned vblocks = unsigned(std::max(1, tu.blocks_per_cu * ix.num_cus));
     if (nq > 0) {
         // the item pass needs no more waves than rounds of 64 items
