@@ -207,23 +207,63 @@ __global__ __launch_bounds__(kHistNT) void p1_hist_kernel(const uint32_t *__rest
 // "last block scans" fusion into the histogram kernel needs a device-scope
 // release per block, which writes back the L2 of the XCD; it measured 20x
 // slower than this separate launch.)
-__global__ __launch_bounds__(kHiBins) void p1_scan_kernel(uint32_t *__restrict__ hist, int nblk, int64_t n,
-                                                          uint32_t *__restrict__ bstart,
-                                                          uint32_t *__restrict__ rest_count) {
-    __shared__ uint32_t sh[kHiBins / 64 + 1];
-    const int T = blockIdx.x, d = threadIdx.x;
-    uint32_t *h = hist + int64_t(T) * nblk * kHiBins;
-    uint32_t run = 0;
-    for (int b = 0; b < nblk; ++b) {
-        const uint32_t c = h[int64_t(b) * kHiBins + d];
-        h[int64_t(b) * kHiBins + d] = run;
+constexpr int kScanSeg = 4;  // tile segments per table in the scan (kHiBins threads each)
+
+__global__ __launch_bounds__(kHiBins * kScanSeg) void p1_scan_kernel(uint32_t *__restrict__ hist, int nblk, int64_t n,
+                                                                    uint32_t *__restrict__ bstart,
+                                                                    uint32_t *__restrict__ rest_count) {
+    __shared__ uint32_t segsum[kScanSeg][kHiBins];
+    __shared__ uint32_t dbase[kHiBins];
+    __shared__ uint32_t sh[kHiBins * kScanSeg / 64 + 1];
+    const int T = blockIdx.x, d = threadIdx.x % kHiBins, seg = threadIdx.x / kHiBins;
+    const int per = (nblk + kScanSeg - 1) / kScanSeg;
+    const int b0 = min(nblk, seg * per), b1 = min(nblk, b0 + per);
+    uint32_t *h = hist + int64_t(T) * nblk * kHiBins + d;
+    // pass 1: this segment's count of digit d, 8 independent loads at a time
+    uint32_t s = 0;
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = h[int64_t(b + k) * kHiBins];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += c[k];
+    }
+    for (; b < b1; ++b) s += h[int64_t(b) * kHiBins];
+    segsum[seg][d] = s;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;  // digit d: earlier segments, all segments
+    for (int k = 0; k < kScanSeg; ++k) {
+        const uint32_t v = segsum[k][d];
+        pre += k < seg ? v : 0u;
+        tot += v;
+    }
+    // digit starts: exclusive scan over d of the digit totals (segment 0's
+    // threads come first in thread order and carry them)
+    const uint32_t ex = block_scan_u32(seg == 0 ? tot : 0u, sh, nullptr);
+    if (seg == 0) dbase[d] = ex;
+    __syncthreads();
+    // pass 2: run starts of digit d in this segment's tiles
+    uint32_t run = dbase[d] + pre;
+    b = b0;
+    for (; b + 8 <= b1; b += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = h[int64_t(b + k) * kHiBins];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            h[int64_t(b + k) * kHiBins] = run;
+            run += c[k];
+        }
+    }
+    for (; b < b1; ++b) {
+        const uint32_t c = h[int64_t(b) * kHiBins];
+        h[int64_t(b) * kHiBins] = run;
         run += c;
     }
-    const uint32_t base = block_scan_u32(run, sh, nullptr);
-    for (int b = 0; b < nblk; ++b) h[int64_t(b) * kHiBins + d] += base;
-    bstart[int64_t(T) * (kHiBins + 1) + d] = base;
-    if (d == 0) bstart[int64_t(T) * (kHiBins + 1) + kHiBins] = uint32_t(n);
-    if (T == 0 && d == 0) *rest_count = 0;  // pass 2 appends from zero
+    if (seg == 0) bstart[int64_t(T) * (kHiBins + 1) + d] = dbase[d];
+    if (threadIdx.x == 0) bstart[int64_t(T) * (kHiBins + 1) + kHiBins] = uint32_t(n);
+    if (T == 0 && threadIdx.x == 0) *rest_count = 0;  // pass 2 appends from zero
 }
 
 
@@ -755,7 +795,8 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
-    hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins), 0, st, hist, nblk, n, bstart, rest_count);
+    hipLaunchKernelGGL(p1_scan_kernel, dim3(unsigned(L)), dim3(kHiBins * kScanSeg), 0, st, hist, nblk, n, bstart,
+                       rest_count);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     const int64_t nitems = int64_t(nblk) * L;
