@@ -688,7 +688,18 @@ __global__ __launch_bounds__(kNT, 4) void p1b_split_kernel(const uint32_t *__res
     uint32_t *okey = okeys + off, *oid = oids + off;
     if (threadIdx.x < MS) cnt[threadIdx.x] = 0;
     __syncthreads();
-    for (uint32_t e = threadIdx.x; e < count; e += kNT) atomicAdd(&cnt[(kin[e] >> shift) & mask], 1u);
+    {
+        // sub-digit histogram, 16 independent loads in flight per thread
+        uint32_t e = threadIdx.x;
+        for (; e + 15u * kNT < count; e += 16u * kNT) {
+            uint32_t kk[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) kk[u] = kin[e + uint32_t(u) * kNT];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) atomicAdd(&cnt[(kk[u] >> shift) & mask], 1u);
+        }
+        for (; e < count; e += kNT) atomicAdd(&cnt[(kin[e] >> shift) & mask], 1u);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t gs = (int64_t(kHiBins) << sbits) + 1;
@@ -735,12 +746,29 @@ __global__ __launch_bounds__(kNT, 4) void p1b_split_kernel(const uint32_t *__res
             }
         __syncthreads();
         const uint32_t chunk = min(uint32_t(kTile), count - c0);
-        for (uint32_t j = threadIdx.x; j < chunk; j += kNT) {
-            const uint32_t key = sk[j];
-            const uint32_t d = (key >> shift) & mask;
-            const uint32_t dst = run[d] + (j - cst[d]);
-            okey[dst] = key;
-            oid[dst] = sv[j];
+        if (chunk == uint32_t(kTile)) {
+            // full chunk: all LDS reads first, then the stores
+            uint32_t kk[kItems], vv[kItems];
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                kk[k] = sk[k * kNT + threadIdx.x];
+                vv[k] = sv[k * kNT + threadIdx.x];
+            }
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const uint32_t d = (kk[k] >> shift) & mask;
+                const uint32_t dst = run[d] + (uint32_t(k * kNT) + threadIdx.x - cst[d]);
+                okey[dst] = kk[k];
+                oid[dst] = vv[k];
+            }
+        } else {
+            for (uint32_t j = threadIdx.x; j < chunk; j += kNT) {
+                const uint32_t key = sk[j];
+                const uint32_t d = (key >> shift) & mask;
+                const uint32_t dst = run[d] + (j - cst[d]);
+                okey[dst] = key;
+                oid[dst] = sv[j];
+            }
         }
         __syncthreads();
         if (threadIdx.x < SB) run[threadIdx.x] += ctot[threadIdx.x];
