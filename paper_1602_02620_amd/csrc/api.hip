@@ -150,13 +150,17 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tids), size_t(L * n) * 4, "table ids")) ||
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dir),
                        size_t(L) * ((size_t(1) << ix.dir_bits) + 1) * 4, "directory")) ||
-        (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dpart), size_t(ix.prm.d) * 4, "params")) ||
-        (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dcol), size_t(ix.prm.d) * 4, "params")))
+        (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dpc), size_t(ix.prm.d) * 4, "params")))
         return bail(s);
     if ((s = build_hash_plan(&ix))) return bail(s);
-    if (hipMemcpy(ix.dpart, ix.prm.part.data(), size_t(ix.prm.d) * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ix.dcol, ix.prm.col.data(), size_t(ix.prm.d) * 4, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(FCLSH_EDEVICE, "parameter upload failed"));
+    {
+        // (part, column) of each coordinate in one word for the dedupe test:
+        // parts and columns (< 2^kMaxLogD) each fit 16 bits
+        std::vector<uint32_t> pc(size_t(ix.prm.d));
+        for (int c = 0; c < ix.prm.d; ++c) pc[size_t(c)] = uint32_t(ix.prm.part[c]) << 16 | uint32_t(ix.prm.col[c]);
+        if (hipMemcpy(ix.dpc, pc.data(), pc.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(FCLSH_EDEVICE, "parameter upload failed"));
+    }
     const int64_t total = n * ix.W;
     unsigned g = unsigned(std::min<int64_t>((total + 255) / 256, 65536));
     hipLaunchKernelGGL(copy_points_kernel, dim3(g), dim3(256), 0, st, d_points, ix.pts, total, ix.W,

@@ -96,8 +96,7 @@ struct Index {
     uint32_t *tids = nullptr;  // [L][n]
     uint32_t *dir = nullptr;   // [L][2^dir_bits + 1]
     // per-index device copies of part/col for the duplicate-elimination rule
-    int32_t *dpart = nullptr;
-    int32_t *dcol = nullptr;
+    uint32_t *dpc = nullptr;  // part(c) << 16 | column(c) per coordinate
     std::vector<DevBuf> owned;
     size_t bytes_owned = 0;
 };

@@ -40,9 +40,10 @@ namespace {
 
 // First table (in (part, v) order) where x and q share the masked value, or
 // -1 if there is none (then d(x, q) exceeds what the family covers).
+// pc[c] = part(c) << 16 | column(c) (the verification kernels stage it in
+// LDS).
 __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t *__restrict__ q, int W,
-                                  const int32_t *__restrict__ part, const int32_t *__restrict__ col, int t,
-                                  int mbits, int Lp, uint64_t last_mask) {
+                                  const uint32_t *__restrict__ pc, int t, int mbits, int Lp, uint64_t last_mask) {
     for (int p = 0; p < t; ++p) {
         uint32_t B[kMaxLogD];
 #pragma unroll
@@ -53,8 +54,9 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
             while (diff) {
                 const int c = w * 64 + __builtin_ctzll(diff);
                 diff &= diff - 1;
-                if (part[c] != p) continue;
-                const uint32_t uc = uint32_t(col[c]);
+                const uint32_t pcc = pc[c];
+                if (int(pcc >> 16) != p) continue;
+                const uint32_t uc = pcc & 0xFFFFu;
                 // constrain the basis to v with <v, uc> = 0: the odd vector
                 // with the lowest leading bit is dropped and XORed into the
                 // other odd ones (their leading bits are higher, so they stay
@@ -84,9 +86,9 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
 
 struct VerifyArgs {
     const uint64_t *pts;
-    int W, t, mbits, Lp, L;
+    int W, d, t, mbits, Lp, L;
     uint64_t last_mask;
-    const int32_t *part, *col;
+    const uint32_t *pc;  // part << 16 | column per coordinate (global; staged in LDS per workgroup)
     const uint64_t *queries;
     int64_t nq;
     const int32_t *rq_vec;  // per-query radius, or null: rq for all
@@ -209,33 +211,45 @@ __device__ inline void emit_pair(const VerifyArgs &a, const PairStage &ps, int64
 
 // Checks one bin entry j of table T against query qi: same key, within the
 // query's radius, and T is the first table the two share (dedupe).
-__device__ inline bool near_in_table(const VerifyArgs &a, int64_t qi, int T, uint32_t qkey, int rq, uint32_t key,
-                                     uint32_t id) {
+__device__ inline bool near_in_table(const VerifyArgs &a, const uint32_t *spc, int64_t qi, int T, uint32_t qkey,
+                                     int rq, uint32_t key, uint32_t id) {
     if (key != qkey) return false;
     const uint64_t *xp = a.pts + int64_t(id) * a.W;
     const uint64_t *qp = a.queries + qi * a.W;
     if (hamming(xp, qp, a.W, a.last_mask) > rq) return false;
-    return first_shared_table(xp, qp, a.W, a.part, a.col, a.t, a.mbits, a.Lp, a.last_mask) == T;
+    return first_shared_table(xp, qp, a.W, spc, a.t, a.mbits, a.Lp, a.last_mask) == T;
+}
+
+// Stages the per-coordinate (part, column) words in the workgroup's LDS.
+__device__ inline const uint32_t *stage_pc(const VerifyArgs &a, uint32_t *spc) {
+    for (int i = threadIdx.x; i < a.d; i += blockDim.x) spc[i] = a.pc[i];
+    __syncthreads();
+    return spc;
 }
 
 // Whole wave, uniform arguments: entries [j0, j1) of table T (absolute
 // positions), a lane per entry.
-__device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, int64_t qi, int T, uint32_t j0,
-                                    uint32_t j1) {
+__device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, const uint32_t *spc, int64_t qi,
+                                    int T, uint32_t j0, uint32_t j1) {
     const int lane = threadIdx.x & 63;
     const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
     const uint32_t *ids = a.tids + int64_t(T) * a.n;
     const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
     const int rq = query_radius(a, qi);
-    for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
-        const uint32_t j = b0 + lane;
-        if (j < j1) {
-            const uint32_t key = bk[j];
-            if (key == qkey) {
-                const uint32_t id = ids[j];
-                if (near_in_table(a, qi, T, qkey, rq, key, id)) emit_pair(a, ps, qi, id);
-            }
+    // four rounds of 64 entries at a time: their keys and ids are loaded
+    // together (independent loads), then the matches are verified
+    constexpr int R4 = 4;
+    for (uint32_t b0 = j0; b0 < j1; b0 += 64 * R4) {
+        uint32_t key[R4], id[R4];
+#pragma unroll
+        for (int k = 0; k < R4; ++k) {
+            const uint32_t j = b0 + uint32_t(k) * 64u + uint32_t(lane);
+            key[k] = j < j1 ? bk[j] : ~qkey;
+            id[k] = j < j1 ? ids[j] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < R4; ++k)
+            if (key[k] == qkey && near_in_table(a, spc, qi, T, qkey, rq, key[k], id[k])) emit_pair(a, ps, qi, id[k]);
     }
 }
 
@@ -292,6 +306,8 @@ __global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill,
 // the spill queue.
 __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyArgs a) {
     __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
+    extern __shared__ uint32_t dyn_pc[];
+    const uint32_t *spc = stage_pc(a, dyn_pc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const PairStage ps{stq[wave], sti[wave], &stc[wave]};
     if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -348,7 +364,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
             for (int c = 0; c < 8; ++c)
                 if (kk[c] == qkey) {
                     const uint32_t id = ids[j0 + c];
-                    if (near_in_table(a, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
+                    if (near_in_table(a, spc, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
                 }
         }
     }
@@ -362,6 +378,8 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
 // the chunks' uneven costs over tens of chunks per wave.
 __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyArgs a) {
     __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
+    extern __shared__ uint32_t dyn_pc[];
+    const uint32_t *spc = stage_pc(a, dyn_pc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const PairStage ps{stq[wave], sti[wave], &stc[wave]};
     if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -372,7 +390,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyA
         int64_t qi;
         int T;
         item_coords(a, r.x, qi, T);
-        verify_range(a, ps, qi, T, r.y, r.z);
+        verify_range(a, ps, spc, qi, T, r.y, r.z);
     }
     flush_pairs(a, ps, stage_count(ps));
 }
@@ -639,8 +657,8 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.Lp = ix.prm.Lp();
     a.L = L;
     a.last_mask = last_word_mask(ix.prm.d);
-    a.part = ix.dpart;
-    a.col = ix.dcol;
+    a.pc = ix.dpc;
+    a.d = ix.prm.d;
     a.queries = queries;
     a.nq = nq;
     a.rq_vec = rq_vec;
@@ -664,9 +682,10 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     if (nq > 0) {
         // the item pass needs no more waves than rounds of 64 items
         const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 64 * kVerifyWaves));
-        hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(64 * kVerifyWaves), 0, st, a);
+        const size_t pc_lds = size_t(ix.prm.d) * 4;  // staged (part, column) words, d <= 4096
+        hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
         FCLSH_HIP(hipGetLastError());
-        hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(64 * kVerifyWaves), 0, st, a);
+        hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
         FCLSH_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(widen_counts_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.qcount, nq, ws.qcount64);
