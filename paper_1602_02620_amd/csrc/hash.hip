@@ -230,16 +230,18 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
                     t[k] = double(en.x & coord_mask(myx, en.y));
                 }
             } else {
+                // integer sums (at most d terms below 2^31: exact in 64
+                // bits), one conversion per column
                 const int32_t *sg = seg + p * (V + 1);
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
-                    double acc = 0.0;
+                    uint64_t acc = 0;
                     const int e1 = sg[k + 1];
                     for (int e = sg[k]; e < e1; ++e) {
                         const uint2 en = tab[e * G + s];
-                        acc += double(en.x & coord_mask(myx, en.y));
+                        acc += en.x & coord_mask(myx, en.y);
                     }
-                    t[k] = acc;
+                    t[k] = double(acc);
                 }
             }
             __asm__ volatile("" ::: "memory");
