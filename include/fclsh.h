@@ -204,6 +204,10 @@ FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
  * pass-1 scan, the pass-1 scatter, the pass-1b split (0 when n is small
  * enough not to need it), the pass-2 group kernel (every group of the
  * table of at most 4608 entries) and the pass-2 kernel for larger groups.
+ * The group kernel has a full form and a slot-only form (faster, but it
+ * leaves groups with a bin over 48 entries to the second kernel); a rebuild
+ * uses the slot-only form when the index's previous build sent at most 1 %
+ * of the groups off its slot branch.  Both give identical tables.
  * Errors: FCLSH_EINVAL for a short phase_ms, FCLSH_EDEVICE for HIP errors.
  * Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms,

@@ -104,8 +104,15 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
     FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
-                                 st, marks ? marks + 2 : nullptr));
+                                 ix.p2_slot_only, st, marks ? marks + 2 : nullptr));
     FCLSH_HIP(hipStreamSynchronize(st));
+    // pass 2's form for the next rebuild: slot-only while at most 1 % of the
+    // groups leave the slot branch (identical tables either way)
+    uint32_t cnt[2] = {0, 0};
+    FCLSH_HIP(hipMemcpy(cnt, table_build_counts(h->aux, L, ix.n, ix.dir_bits), sizeof cnt, hipMemcpyDeviceToHost));
+    const int64_t groups = L << (8 + table_split_bits(ix.n, ix.dir_bits));
+    const int64_t off_slot = ix.p2_slot_only ? int64_t(cnt[0]) : int64_t(cnt[1]) + int64_t(cnt[0]);
+    ix.p2_slot_only = off_slot * 100 <= groups;
     return FCLSH_OK;
 }
 

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kHiBins * kScanSeg) void p1_scan_kernel(uint32_t *_
     }
     if (seg == 0) bstart[int64_t(T) * (kHiBins + 1) + d] = dbase[d];
     if (threadIdx.x == 0) bstart[int64_t(T) * (kHiBins + 1) + kHiBins] = uint32_t(n);
-    if (T == 0 && threadIdx.x == 0) *rest_count = 0;  // pass 2 appends from zero
+    if (T == 0 && threadIdx.x < 2) rest_count[threadIdx.x] = 0;  // pass 2's counters start at zero
 }
 
 
@@ -403,7 +403,13 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t *sh) {
 // A group of at most kFastTile entries.  Entries are loaded wave-major (wave
 // w holds a contiguous run of the group, ipw rounds of 64), which the stable
 // branch needs and the fast branch does not mind.
-__device__ void p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+// Returns kGroupSlot or kGroupBallot for the branch taken.  SLOT_ONLY: a
+// group with a bin over kMaxFastBin is left untouched for the second kernel
+// (kGroupLeft) instead of taking the ballot branch.
+constexpr int kGroupLeft = 0, kGroupSlot = 1, kGroupBallot = 2;
+
+template <bool SLOT_ONLY>
+__device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // region A: keys and ids in slot (fast) or final (stable) order; in the
@@ -431,6 +437,7 @@ __device__ void p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     uint32_t mx = 0;
     for (int i = threadIdx.x; i < R; i += kNT) mx = max(mx, cnt[i]);
     const bool fast = block_max_u32(mx, sh) <= kMaxFastBin;
+    if (SLOT_ONLY && !fast) return kGroupLeft;
     if (!fast) {
         for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // per-wave counters
     }
@@ -454,7 +461,7 @@ __device__ void p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
             a.okey[r] = k;
             a.oid[r] = v;
         }
-        return;
+        return kGroupSlot;
     }
     // stable branch: input order is id order; rank = bin start + entries of
     // the bin in earlier waves + earlier entries of this wave
@@ -484,6 +491,7 @@ __device__ void p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
         a.okey[j] = bk[j];
         a.oid[j] = bv[j];
     }
+    return kGroupBallot;
 }
 
 // Stable path for a super-bin of at most kTile entries.
@@ -602,14 +610,19 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
 }
 
 // Pass 2, group kernel over every (table, group); groups over kFastTile
-// entries are appended to rest[] for p2_rest_kernel.
+// entries (and, in the slot-only form, groups with a large bin) are appended
+// to rest[] for p2_rest_kernel.  counts[0] = listed groups, counts[1] =
+// groups that took the ballot branch.  The slot-only form (52 VGPRs, 4
+// workgroups per CU) is chosen for a rebuild when the previous build sent
+// at most 1 % of the groups off the slot branch; the full form needs 68
+// VGPRs (3 per CU).
 // (iids and tids may be the same array: the ids are then reordered in place,
 // each group reading its whole run into registers before writing it.)
-__global__ __launch_bounds__(kNT, 6) void p2_fast_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
-                                                         int64_t n, const uint32_t *__restrict__ gstart, int gbits,
-                                                         int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids,
-                                                         uint32_t *__restrict__ dir, uint32_t *__restrict__ rest,
-                                                         uint32_t *__restrict__ rest_count, int64_t nitems) {
+template <bool SLOT_ONLY>
+__global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
+    const uint32_t *__restrict__ ikeys, const uint32_t *iids, int64_t n, const uint32_t *__restrict__ gstart,
+    int gbits, int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
+    uint32_t *__restrict__ rest, uint32_t *__restrict__ counts, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
     const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
@@ -618,10 +631,11 @@ __global__ __launch_bounds__(kNT, 6) void p2_fast_kernel(const uint32_t *__restr
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
     const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
-    if (a.count <= uint32_t(kFastTile))
-        p2_group(a, lds, sh);
-    else if (threadIdx.x == 0)
-        rest[atomicAdd(rest_count, 1u)] = uint32_t(w);
+    const int how = a.count <= uint32_t(kFastTile) ? p2_group<SLOT_ONLY>(a, lds, sh) : kGroupLeft;
+    if (threadIdx.x == 0) {
+        if (how == kGroupLeft) rest[atomicAdd(counts, 1u)] = uint32_t(w);
+        if (how == kGroupBallot) atomicAdd(counts + 1, 1u);
+    }
 }
 
 // Pass 2, stable path for the groups the group kernel left: a fixed grid
@@ -802,13 +816,20 @@ size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits) {
     const int64_t nblk = (n + kP1Tile - 1) / kP1Tile;
     const int S = table_split_bits(n, dir_bits);
     const size_t groups = size_t(kHiBins) << S;
-    return 4 * (size_t(L) * nblk * kHiBins + size_t(L) * (kHiBins + 1) + (S ? size_t(L) * (groups + 1) : 0) + 1 +
+    return 4 * (size_t(L) * nblk * kHiBins + size_t(L) * (kHiBins + 1) + (S ? size_t(L) * (groups + 1) : 0) + 2 +
                 size_t(L) * groups);
 }
 
+const uint32_t *table_build_counts(const uint32_t *scratch, int64_t L, int64_t n, int dir_bits) {
+    const int64_t nblk = (n + kP1Tile - 1) / kP1Tile;
+    const int S = table_split_bits(n, dir_bits);
+    return scratch + size_t(L) * nblk * kHiBins + size_t(L) * (kHiBins + 1) +
+           (S ? size_t(L) * ((size_t(kHiBins) << S) + 1) : 0);
+}
+
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
-                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, hipStream_t st,
-                                hipEvent_t *marks) {
+                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, bool slot_only,
+                                hipStream_t st, hipEvent_t *marks) {
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
     if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
@@ -819,7 +840,7 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     uint32_t *bstart = hist + size_t(L) * nblk * kHiBins;
     uint32_t *gstart = S ? bstart + size_t(L) * (kHiBins + 1) : bstart;
     uint32_t *rest_count = S ? gstart + size_t(L) * ((size_t(kHiBins) << S) + 1) : bstart + size_t(L) * (kHiBins + 1);
-    uint32_t *rest = rest_count + 1;
+    uint32_t *rest = rest_count + 2;
     hipLaunchKernelGGL(p1_hist_kernel, dim3(nblk, unsigned(L)), dim3(kHistNT), 0, st, keys, n, hist, nblk);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
@@ -849,8 +870,12 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
     const size_t lds_fast = (size_t(p2_region_a(lo_bits)) + (size_t(1) << lo_bits) + 1) * 4;
     const int64_t nitems2 = int64_t(L) << gbits;  // (table, group) items, a multiple of kXcds
-    hipLaunchKernelGGL(p2_fast_kernel, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n, gstart, gbits,
-                       lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
+    if (slot_only)
+        hipLaunchKernelGGL(p2_fast_kernel<true>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
+                           gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
+    else
+        hipLaunchKernelGGL(p2_fast_kernel<false>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
+                           gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
     hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2, st,

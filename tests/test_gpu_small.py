@@ -263,6 +263,31 @@ def test_radius_and_capacity_errors():
     idx.close()
 
 
+def test_rebuild_slot_only_with_large_bins():
+    """A first build takes pass 2's full group kernel; when it sent at most
+    1 % of the groups off the slot branch, a rebuild takes the slot-only form,
+    which leaves the groups with a large bin to the second kernel.  Here 60
+    copies of one point put one large bin in every table (1 of 256 groups),
+    so the rebuild exercises that fallback.  Both builds equal the oracle."""
+    rng = np.random.default_rng(41)
+    n, d, r = 20000, 64, 4
+    pts = synth.uniform_points(n, d, rng)
+    pts[1:61] = pts[0]  # 61 equal points: equal keys in every table
+    idx = fc.Index(dev(pts), d, r, seed=41)
+    orc = OracleIndex(pts, oracle.derive_params(d, r, 41), with_tables=False)
+    db = idx.info["dir_bits"]
+    assert idx.info["group_bits"] == 8
+    wk, wi = orc.binned_tables(db)
+    for build in ("first build", "rebuild", "second rebuild"):
+        if build != "first build":
+            idx.rebuild()
+        _say(f"[slot-only] {build}")
+        tk, ti = idx.tables()
+        assert np.array_equal(as_u32(tk), wk), build
+        assert np.array_equal(as_u32(ti), wi), build
+    idx.close()
+
+
 def test_finish_after_capacity_error():
     """A batch whose ids overflow the buffer is finished into a larger one
     from the pairs it already found (fclsh_query_batch_finish)."""
