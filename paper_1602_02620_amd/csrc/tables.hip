@@ -7,18 +7,22 @@
 // bucket of k.  B is about log2(n) - 2, so a bin holds a handful of entries
 // besides the bucket itself.
 //
-// Built in two stable passes per table:
+// Built in two stable passes per table (three for large n):
 //   pass 1  global partition by the top 8 key bits into 256 "super-bins":
 //           per-tile digit histograms, a per-table scan, and a scatter that
 //           ranks each tile's keys stably with wave ballots and writes every
 //           digit's run contiguously through an LDS reorder buffer;
-//   pass 2  one workgroup per (table, super-bin): a stable reorder by the
-//           next B - 8 key bits in LDS, written back contiguously, which also
-//           yields the directory entries of the super-bin's bins.
+//   pass 1b (large n) a stable split of every super-bin by S more key bits
+//           into groups of a few thousand entries;
+//   pass 2  one workgroup per (table, group): a reorder by the remaining
+//           key bits in LDS, ids ascending per bin, written back
+//           contiguously, which also yields the directory entries of the
+//           group's bins.
 // Scattered 4-byte stores are far slower than coalesced ones on this GPU, so
-// both passes stage their output in LDS first.
+// every pass stages its output in LDS first.
 // Ids are implicit in pass 1 (a point's index), so the keys written by the
-// hash kernel are read twice and each table entry is written twice.
+// hash kernel are read twice and each table entry is written twice (three
+// times with pass 1b).
 #include "common.h"
 
 namespace fclsh {
@@ -31,7 +35,7 @@ constexpr int kP1Waves = kP1NT / 64;
 constexpr int kP1Items = 16;               // entries per thread
 constexpr int kP1Tile = kP1NT * kP1Items;  // entries per tile
 constexpr int kHistNT = 256;
-// pass 2 (one workgroup per super-bin)
+// pass 1b and pass 2 (one workgroup per super-bin or group)
 constexpr int kNT = 512;                   // threads of the pass-2 kernels
 constexpr int kWaves = kNT / 64;
 constexpr int kItems = 16;                 // entries per thread
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(kHistNT) void p1_hist_kernel(const uint32_t *__rest
 
 // Per table: hist[T][blk][d] := start (within the table) of tile blk's run of
 // digit d; bstart[T][d] = start of super-bin d, bstart[T][256] = n; also
-// clears the count of super-bins left to the stable pass-2 kernel.  (A
+// clears pass 2's two group counters.  (A
 // "last block scans" fusion into the histogram kernel needs a device-scope
 // release per block, which writes back the L2 of the XCD; it measured 20x
 // slower than this separate launch.)
@@ -494,7 +498,7 @@ __device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     return kGroupBallot;
 }
 
-// Stable path for a super-bin of at most kTile entries.
+// Stable path for a group of at most kTile entries.
 __device__ void p2_stable_single(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     // region A (kTile*2 words): first the per-wave counters [kWaves][R], then
@@ -542,7 +546,7 @@ __device__ void p2_stable_single(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     }
 }
 
-// Stable path for a super-bin of more than kTile entries.
+// Stable path for a group of more than kTile entries.
 __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     uint32_t *wc = lds;
