@@ -460,8 +460,13 @@ __device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
             const uint32_t k = bk[j], v = bv[j];
             const uint32_t dg = (k >> a.shift) & a.mask;
             const uint32_t b0 = cnt[dg], b1 = cnt[dg + 1];
-            uint32_t r = b0;
-            for (uint32_t q = b0; q < b1; ++q) r += bv[q] < v ? 1u : 0u;
+            // ids of the bin smaller than v: four independent reads per step
+            uint32_t r = b0, q = b0;
+            for (; q + 4 <= b1; q += 4) {
+                const uint32_t x0 = bv[q], x1 = bv[q + 1], x2 = bv[q + 2], x3 = bv[q + 3];
+                r += uint32_t(x0 < v) + uint32_t(x1 < v) + uint32_t(x2 < v) + uint32_t(x3 < v);
+            }
+            for (; q < b1; ++q) r += bv[q] < v ? 1u : 0u;
             a.okey[r] = k;
             a.oid[r] = v;
         }
