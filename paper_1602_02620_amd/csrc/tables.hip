@@ -295,11 +295,14 @@ __global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__res
 
     uint32_t rk[kP1Items], dg[kP1Items], rank[kP1Items];
     bool ok[kP1Items];
+    // every lane loads (the index clamped to the tile's last entry); entries
+    // past the end are marked invalid and never used
+    const uint32_t *kt = keys + toff + beg;
 #pragma unroll
     for (int it = 0; it < kP1Items; ++it) {
         const int e = wave * (64 * kP1Items) + it * 64 + lane;
         ok[it] = e < cnt;
-        rk[it] = ok[it] ? keys[toff + beg + e] : 0u;
+        rk[it] = kt[min(e, cnt - 1)];
         dg[it] = rk[it] >> (31 - kHiBits);
     }
     wave_stable_ranks<kP1Items>(dg, ok, kHiBits, wc + wave * kHiBins, rank);
