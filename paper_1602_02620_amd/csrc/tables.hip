@@ -688,16 +688,21 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
 // sub-digits gives the group starts (gstart, the pass-2 layout); the
 // super-bin is then moved chunk by chunk (wave-ballot ranks, LDS reorder)
 // with running group offsets, each sub-digit's run written contiguously.
+// Chunks are 4096 entries (8 per thread; 80 VGPRs and 33 KB of LDS: 3
+// workgroups per CU) up to 8 sub-digits, and 8192 (2 per CU) for 16, which
+// keeps every chunk's runs at 512 entries or more.
 constexpr int kMaxSplitBits = 4;
 
-__global__ __launch_bounds__(kNT, 4) void p1b_split_kernel(const uint32_t *__restrict__ ikeys,
+template <int ITEMS>
+__global__ __launch_bounds__(kNT, ITEMS <= 8 ? 6 : 4) void p1b_split_kernel(const uint32_t *__restrict__ ikeys,
                                                            const uint32_t *__restrict__ iids, int64_t n,
                                                            const uint32_t *__restrict__ bstart, int sbits,
                                                            uint32_t *__restrict__ okeys, uint32_t *__restrict__ oids,
                                                            uint32_t *__restrict__ gstart, int64_t nitems) {
     constexpr int MS = 1 << kMaxSplitBits;
-    __shared__ uint32_t sk[kTile];
-    __shared__ uint32_t sv[kTile];
+    constexpr int CHUNK = kNT * ITEMS;
+    __shared__ uint32_t sk[CHUNK];
+    __shared__ uint32_t sv[CHUNK];
     __shared__ uint32_t wc[kWaves * MS];
     __shared__ uint32_t cnt[MS], run[MS], ctot[MS], cst[MS];
     const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
@@ -738,20 +743,20 @@ __global__ __launch_bounds__(kNT, 4) void p1b_split_kernel(const uint32_t *__res
         if (sb == kHiBins - 1) gstart[int64_t(T) * gs + gs - 1] = uint32_t(n);
     }
     __syncthreads();
-    for (uint32_t c0 = 0; c0 < count; c0 += kTile) {
+    for (uint32_t c0 = 0; c0 < count; c0 += CHUNK) {
         for (int i = threadIdx.x; i < kWaves * SB; i += kNT) wc[i] = 0;
         __syncthreads();
-        uint32_t rk[kItems], rv[kItems], dg[kItems], rank[kItems];
-        bool ok[kItems];
+        uint32_t rk[ITEMS], rv[ITEMS], dg[ITEMS], rank[ITEMS];
+        bool ok[ITEMS];
 #pragma unroll
-        for (int it = 0; it < kItems; ++it) {
-            const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint32_t e = c0 + uint32_t(wave * (64 * ITEMS) + it * 64 + lane);
             ok[it] = e < count;
             rk[it] = ok[it] ? kin[e] : 0u;
             rv[it] = ok[it] ? vin[e] : 0u;
             dg[it] = (rk[it] >> shift) & mask;
         }
-        wave_stable_ranks<kItems>(dg, ok, sbits, wc + wave * SB, rank);
+        wave_stable_ranks<ITEMS>(dg, ok, sbits, wc + wave * SB, rank);
         __syncthreads();
         wave_offsets<kNT>(wc, SB, ctot);
         __syncthreads();
@@ -764,24 +769,24 @@ __global__ __launch_bounds__(kNT, 4) void p1b_split_kernel(const uint32_t *__res
         }
         __syncthreads();
 #pragma unroll
-        for (int it = 0; it < kItems; ++it)
+        for (int it = 0; it < ITEMS; ++it)
             if (ok[it]) {
                 const uint32_t lp = cst[dg[it]] + wc[wave * SB + dg[it]] + rank[it];
                 sk[lp] = rk[it];
                 sv[lp] = rv[it];
             }
         __syncthreads();
-        const uint32_t chunk = min(uint32_t(kTile), count - c0);
-        if (chunk == uint32_t(kTile)) {
+        const uint32_t chunk = min(uint32_t(CHUNK), count - c0);
+        if (chunk == uint32_t(CHUNK)) {
             // full chunk: all LDS reads first, then the stores
-            uint32_t kk[kItems], vv[kItems];
+            uint32_t kk[ITEMS], vv[ITEMS];
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) {
+            for (int k = 0; k < ITEMS; ++k) {
                 kk[k] = sk[k * kNT + threadIdx.x];
                 vv[k] = sv[k * kNT + threadIdx.x];
             }
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) {
+            for (int k = 0; k < ITEMS; ++k) {
                 const uint32_t d = (kk[k] >> shift) & mask;
                 const uint32_t dst = run[d] + (uint32_t(k * kNT) + threadIdx.x - cst[d]);
                 okey[dst] = kk[k];
@@ -872,8 +877,12 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     const uint32_t *p2k = tmpk, *p2v = tmpv;
     if (S) {
         const int64_t nsb = int64_t(kHiBins) * L;
-        hipLaunchKernelGGL(p1b_split_kernel, dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk, tmpv, n, bstart, S, keys,
-                           tids, gstart, nsb);
+        if (S <= 3)
+            hipLaunchKernelGGL(p1b_split_kernel<8>, dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk, tmpv, n, bstart, S,
+                               keys, tids, gstart, nsb);
+        else
+            hipLaunchKernelGGL(p1b_split_kernel<16>, dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk, tmpv, n, bstart, S,
+                               keys, tids, gstart, nsb);
         FCLSH_HIP(hipGetLastError());
         p2k = keys;
         p2v = tids;
