@@ -90,19 +90,39 @@ def main():
         idx.close()
         return
 
-    def step():
-        idx.rebuild()
-        return idx.query(qs, r)
+    # a step enqueues the rebuild and the query batch without host waits
+    # (fclsh_index_rebuild_async, fclsh_query_batch_async) into buffers sized
+    # from one synchronous batch; every step's status is checked after the
+    # timed block
+    stage("sizing the step's buffers from a synchronous batch")
+    offs0, _ = idx.query(qs, r)
+    total0 = int(offs0[-1].item())
+    offs_buf = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    ids_buf = torch.empty(max(total0, 1), dtype=torch.int32, device=dev)
+    res_buf = torch.zeros((max(args.steps, args.warmup), 2), dtype=torch.int64, device=dev)
+    idx.reserve(nq, pair_capacity=max(2 * total0, 1 << 16), spill_capacity=1 << 16)
+
+    def step(k=0):
+        idx.rebuild_async()
+        idx.query_async(qs, r, offs_buf, ids_buf, res_buf[k])
+        return offs_buf, ids_buf
+
+    def check_steps(count):
+        res = res_buf[:count].cpu().numpy()
+        if (res[:, 1] != 0).any() or (res[:, 0] != total0).any():
+            raise RuntimeError(f"a benchmark step overflowed or changed its answer: {res.tolist()}")
 
     stage(f"{args.warmup} warmup + {args.steps} timed steps")
-    for _ in range(args.warmup):
-        step()
+    for k in range(args.warmup):
+        step(k)
     torch.cuda.synchronize()
+    check_steps(args.warmup)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        offs, ids = step()
+    for k in range(args.steps):
+        offs, ids = step(k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    check_steps(args.steps)
     ms_step = (t1 - t0) * 1e3 / args.steps
     total_ids = int(offs[-1].item())
 

@@ -198,6 +198,14 @@ FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tk
  * step alone: hash + table build), for timing.  Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream);
 
+/* The same rebuild, enqueued on `stream` without waiting for it: later work
+ * on `stream` (queries, table reads) sees the new tables.  It may wait for
+ * the previous build of the index to finish (it reads that build's pass-2
+ * counters, see fclsh_index_rebuild_timed).  The index must not be used on
+ * another stream until `stream` has passed this point.  Errors as
+ * fclsh_index_rebuild. */
+FCLSH_API fclsh_status fclsh_index_rebuild_async(fclsh_index idx, void *stream);
+
 /* The same rebuild with HIP events recorded on `stream` around each kernel.
  * phase_ms[0..6] (host, nphase >= 7) receive the durations in ms of: the key
  * computation of Alg. 2 for all points and tables, the pass-1 histogram, the

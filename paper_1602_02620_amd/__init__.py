@@ -34,7 +34,7 @@ EXPORTS = [
     "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_index_rebuild_timed", "fclsh_query_collisions", "fclsh_query_plain",
     "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
-    "fclsh_autotune", "fclsh_query_batch_finish",
+    "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -78,6 +78,7 @@ def lib():
             "fclsh_hash": [vp, vp, i64, vp, vp],
             "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
             "fclsh_index_rebuild": [vp, vp],
+            "fclsh_index_rebuild_async": [vp, vp],
             "fclsh_index_rebuild_timed": [vp, vp, P(ctypes.c_float), i32],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
@@ -231,6 +232,10 @@ class Index:
 
     def rebuild(self, stream=None):
         _check(lib().fclsh_index_rebuild(self._h, _stream_ptr(stream)))
+
+    def rebuild_async(self, stream=None):
+        """fclsh_index_rebuild_async: enqueue the rebuild on the stream."""
+        _check(lib().fclsh_index_rebuild_async(self._h, _stream_ptr(stream)))
 
     REBUILD_PHASES = ("fht_hash_kernel", "p1_hist_kernel", "p1_scan_kernel", "p1_scatter_kernel",
                       "p1b_split_kernel", "p2_fast_kernel", "p2_rest_kernel")

@@ -65,6 +65,11 @@ struct IndexHandle {
     uint32_t *tk = nullptr;
     uint32_t *tv = nullptr;
     uint32_t *aux = nullptr;
+    // pass 2's counters of the last build, copied to pinned host memory
+    // behind an event (read before the next build chooses its pass-2 form)
+    uint32_t *host_cnt = nullptr;
+    hipEvent_t cnt_ev = nullptr;
+    bool cnt_pending = false;
     QueryWorkspace *workspace(hipStream_t st) {
         std::lock_guard<std::mutex> g(mu);
         auto it = ws.find(st);
@@ -90,7 +95,24 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
 // Hash + table build on st, then a synchronisation.  marks (optional,
 // kRebuildPhases + 1 events): before the hash, after the hash, then after
 // each table kernel.
-static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *marks = nullptr) {
+// Pass 2's form for the next build, from the counters of the last one:
+// slot-only while at most 1 % of the groups left the slot branch (identical
+// tables either way).  Waits for the last build's counters if needed.
+static fclsh_status take_build_counts(IndexHandle *h) {
+    if (!h->cnt_pending) return FCLSH_OK;
+    FCLSH_HIP(hipEventSynchronize(h->cnt_ev));
+    h->cnt_pending = false;
+    Index &ix = h->ix;
+    const int64_t groups = int64_t(ix.prm.L()) << (8 + table_split_bits(ix.n, ix.dir_bits));
+    const int64_t off_slot =
+        ix.p2_slot_only ? int64_t(h->host_cnt[0]) : int64_t(h->host_cnt[1]) + int64_t(h->host_cnt[0]);
+    ix.p2_slot_only = off_slot * 100 <= groups;
+    return FCLSH_OK;
+}
+
+// Enqueues hash + table build on st; sync = wait for it (and take the
+// counters) before returning.
+static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *marks = nullptr, bool sync = true) {
     Index &ix = h->ix;
     const int64_t L = ix.prm.L();
     if (!h->keys) {
@@ -100,19 +122,31 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n, ix.dir_bits),
                             "table histograms"));
     }
+    if (!h->host_cnt) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&h->host_cnt), 2 * sizeof(uint32_t), hipHostMallocDefault) !=
+            hipSuccess) {
+            h->host_cnt = nullptr;
+            return fail(FCLSH_ENOMEM, "pinned host allocation failed");
+        }
+        if (hipEventCreateWithFlags(&h->cnt_ev, hipEventDisableTiming) != hipSuccess) {
+            h->cnt_ev = nullptr;
+            return fail(FCLSH_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    FCLSH_TRY(take_build_counts(h));
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
     FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
                                  ix.p2_slot_only, st, marks ? marks + 2 : nullptr));
-    FCLSH_HIP(hipStreamSynchronize(st));
-    // pass 2's form for the next rebuild: slot-only while at most 1 % of the
-    // groups leave the slot branch (identical tables either way)
-    uint32_t cnt[2] = {0, 0};
-    FCLSH_HIP(hipMemcpy(cnt, table_build_counts(h->aux, L, ix.n, ix.dir_bits), sizeof cnt, hipMemcpyDeviceToHost));
-    const int64_t groups = L << (8 + table_split_bits(ix.n, ix.dir_bits));
-    const int64_t off_slot = ix.p2_slot_only ? int64_t(cnt[0]) : int64_t(cnt[1]) + int64_t(cnt[0]);
-    ix.p2_slot_only = off_slot * 100 <= groups;
+    FCLSH_HIP(hipMemcpyAsync(h->host_cnt, table_build_counts(h->aux, L, ix.n, ix.dir_bits), 2 * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, st));
+    FCLSH_HIP(hipEventRecord(h->cnt_ev, st));
+    h->cnt_pending = true;
+    if (sync) {
+        FCLSH_HIP(hipStreamSynchronize(st));
+        FCLSH_TRY(take_build_counts(h));
+    }
     return FCLSH_OK;
 }
 
@@ -297,6 +331,9 @@ void fclsh_index_free(fclsh_index idx) {
         ws_release(*kv.second);
         delete kv.second;
     }
+    if (h->cnt_ev) (void)hipEventSynchronize(h->cnt_ev);
+    if (h->cnt_ev) (void)hipEventDestroy(h->cnt_ev);
+    if (h->host_cnt) (void)hipHostFree(h->host_cnt);
     dev_free_all(&h->ix);
     delete h;
 }
@@ -348,6 +385,11 @@ fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const
 fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream) {
     if (!idx) return fail(FCLSH_EINVAL, "null index");
     return hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream));
+}
+
+fclsh_status fclsh_index_rebuild_async(fclsh_index idx, void *stream) {
+    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    return hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream), nullptr, false);
 }
 
 fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms, int32_t nphase) {

@@ -278,13 +278,22 @@ def test_rebuild_slot_only_with_large_bins():
     db = idx.info["dir_bits"]
     assert idx.info["group_bits"] == 8
     wk, wi = orc.binned_tables(db)
-    for build in ("first build", "rebuild", "second rebuild"):
-        if build != "first build":
+    for build in ("first build", "rebuild", "second rebuild", "async rebuilds"):
+        if build == "async rebuilds":
+            # enqueued without host waits; the table reads follow on the stream
+            idx.rebuild_async()
+            idx.rebuild_async()
+        elif build != "first build":
             idx.rebuild()
         _say(f"[slot-only] {build}")
         tk, ti = idx.tables()
         assert np.array_equal(as_u32(tk), wk), build
         assert np.array_equal(as_u32(ti), wi), build
+    # a query enqueued right after an asynchronous rebuild sees the new tables
+    qs = pts[[0, 100, 5000]]
+    idx.rebuild_async()
+    offs, ids = idx.query(dev(qs), r)
+    assert_same_lists(csr_lists(offs, ids), oracle.brute_force(pts, d, qs, r).ids)
     idx.close()
 
 
