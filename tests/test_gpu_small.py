@@ -393,22 +393,24 @@ def test_timed_rebuild_reports_every_kernel():
     idx.close()
 
 
-@pytest.mark.parametrize("dup", [False, True], ids=["uniform", "heavy"])
-def test_split_pass_for_large_n(dup):
+@pytest.mark.parametrize("n,dup,split", [(1_200_000, False, 1), (1_200_000, True, 1), (4_500_000, False, 3)],
+                         ids=["uniform", "heavy", "three_bits"])
+def test_split_pass_for_large_n(n, dup, split):
     """Above about a million points the table build splits each super-bin
-    by more key bits before the last pass.  1.2 million points with only 7
-    tables (d=64, r=2) keep the oracle quick: every table entry and the
-    directory are compared.  With 400,000 copies of one point, the heavy
-    bins take the stable fallback, which then reorders the ids in place."""
-    rng = np.random.default_rng(40 + int(dup))
-    n, d, r, seed = 1_200_000, 64, 2, 95
+    by more key bits before the last pass.  Only 7 tables (d=64, r=2) keep
+    the oracle quick: every table entry and the directory are compared.
+    With 400,000 copies of one point, the heavy bins take the stable
+    fallback, which then reorders the ids in place.  4.5 million points
+    split by 3 bits (8 sub-digits, the split's 4096-entry chunks)."""
+    rng = np.random.default_rng(40 + int(dup) + n % 7)
+    d, r, seed = 64, 2, 95
     pts = synth.uniform_points(n, d, rng)
     if dup:
         pts[::3] = pts[0]
     _say(f"[split] n={n} dup={dup}")
     idx = fc.Index(dev(pts), d, r, seed=seed)
     inf = idx.info
-    assert inf["group_bits"] > 8
+    assert inf["group_bits"] == 8 + split
     pr = oracle.derive_params(d, r, seed)
     orc = OracleIndex(pts, pr, with_tables=False)
     assert np.array_equal(as_u32(idx.hash(dev(pts))), orc.keys)
