@@ -221,6 +221,7 @@ def main():
             "build_GBps_at_12B_per_entry": build_bytes / (ms_build * 1e-3) / 1e9,
             "kernel_ms": phase_ms,
             "pass2_ballot_share": ballot_entries / entries, "pass2_rest_share": rest_entries / entries,
+            "pass2_form": idx.build_mode,
             "query_batch_ms": ms_query, "queries_per_s": nq / (ms_query * 1e-3),
             "reported_ids": total_ids,
             "plain_query_ms_p50": pct(lat_plain, 50), "plain_query_ms_p99": pct(lat_plain, 99),

@@ -213,13 +213,28 @@ FCLSH_API fclsh_status fclsh_index_rebuild_async(fclsh_index idx, void *stream);
  * enough not to need it), the pass-2 group kernel (every group of the
  * table of at most 4608 entries) and the pass-2 kernel for larger groups.
  * The group kernel has a full form and a slot-only form (faster, but it
- * leaves groups with a bin over 48 entries to the second kernel); a rebuild
- * uses the slot-only form when the index's previous build sent at most 1 %
- * of the groups off its slot branch.  Both give identical tables.
+ * leaves groups with a bin over 48 entries to the second kernel) and a
+ * slot-all form; fclsh_index_build_mode tells which the rebuild takes.  All
+ * give identical tables.
  * Errors: FCLSH_EINVAL for a short phase_ms, FCLSH_EDEVICE for HIP errors.
  * Synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms,
                                                  int32_t nphase);
+
+/* The form of pass 2's group kernel that the index's next rebuild takes,
+ * written to *mode (host):
+ *   0  full: slot and ballot branches (every index's first build);
+ *   1  slot-only: groups with a bin over 48 entries go to the second kernel;
+ *   2  slot-all: the slot branch for every group up to 4608 entries, bin
+ *      sizes not checked (its ranking is right for any bin, slow on large
+ *      ones).
+ * A rebuild hashes the same points with the same functions as the last
+ * build, whose pass-2 counters decide: slot-all when no group left the slot
+ * branch, slot-only when at most 1 % did, else full.  Every form gives the
+ * same tables.  Waits for the last build's counters if an asynchronous
+ * rebuild is still running.  Errors: FCLSH_EINVAL (null argument),
+ * FCLSH_EDEVICE. */
+FCLSH_API fclsh_status fclsh_index_build_mode(fclsh_index idx, int32_t *mode);
 
 /* Per-query diagnostics of Sec. 4.1: #Collisions (summed sizes of the query's
  * L buckets) for each query, written to device d_collisions[nq] (uint64).

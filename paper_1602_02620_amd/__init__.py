@@ -34,7 +34,7 @@ EXPORTS = [
     "fclsh_index_tables", "fclsh_index_rebuild", "fclsh_index_rebuild_timed", "fclsh_query_collisions", "fclsh_query_plain",
     "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
-    "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async",
+    "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -80,6 +80,7 @@ def lib():
             "fclsh_index_rebuild": [vp, vp],
             "fclsh_index_rebuild_async": [vp, vp],
             "fclsh_index_rebuild_timed": [vp, vp, P(ctypes.c_float), i32],
+            "fclsh_index_build_mode": [vp, P(i32)],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_batch_finish": [vp, vp, vp, vp, i64, P(i64)],
@@ -236,6 +237,15 @@ class Index:
     def rebuild_async(self, stream=None):
         """fclsh_index_rebuild_async: enqueue the rebuild on the stream."""
         _check(lib().fclsh_index_rebuild_async(self._h, _stream_ptr(stream)))
+
+    BUILD_MODES = ("full", "slot_only", "slot_all")
+
+    @property
+    def build_mode(self) -> str:
+        """fclsh_index_build_mode: pass 2's form in the next rebuild."""
+        m = ctypes.c_int32()
+        _check(lib().fclsh_index_build_mode(self._h, ctypes.byref(m)))
+        return self.BUILD_MODES[m.value]
 
     REBUILD_PHASES = ("fht_hash_kernel", "p1_hist_kernel", "p1_scan_kernel", "p1_scatter_kernel",
                       "p1b_split_kernel", "p2_fast_kernel", "p2_rest_kernel")

@@ -70,6 +70,7 @@ struct IndexHandle {
     uint32_t *host_cnt = nullptr;
     hipEvent_t cnt_ev = nullptr;
     bool cnt_pending = false;
+    BuildMode cnt_mode = BuildMode::kFull;  // form of the build the counters come from
     QueryWorkspace *workspace(hipStream_t st) {
         std::lock_guard<std::mutex> g(mu);
         auto it = ws.find(st);
@@ -95,18 +96,28 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
 // Hash + table build on st, then a synchronisation.  marks (optional,
 // kRebuildPhases + 1 events): before the hash, after the hash, then after
 // each table kernel.
-// Pass 2's form for the next build, from the counters of the last one:
-// slot-only while at most 1 % of the groups left the slot branch (identical
-// tables either way).  Waits for the last build's counters if needed.
+// The next build's pass-2 form (BuildMode), from pass 2's counters of the
+// last build.  A rebuild hashes the index's own points with its fixed hash
+// functions, so its groups and bins are those of the last build, whose
+// counters therefore predict it exactly:
+//   no group sent off the slot branch  -> kSlotAll
+//   at most 1 % of the groups          -> kSlotOnly
+//   more                               -> kFull.
+// (A kSlotAll build does not look at bin sizes: it keeps its form.)  Waits
+// for the last build's counters if needed.
 static fclsh_status take_build_counts(IndexHandle *h) {
     if (!h->cnt_pending) return FCLSH_OK;
     FCLSH_HIP(hipEventSynchronize(h->cnt_ev));
     h->cnt_pending = false;
     Index &ix = h->ix;
+    if (h->cnt_mode == BuildMode::kSlotAll) return FCLSH_OK;
     const int64_t groups = int64_t(ix.prm.L()) << (8 + table_split_bits(ix.n, ix.dir_bits));
-    const int64_t off_slot =
-        ix.p2_slot_only ? int64_t(h->host_cnt[0]) : int64_t(h->host_cnt[1]) + int64_t(h->host_cnt[0]);
-    ix.p2_slot_only = off_slot * 100 <= groups;
+    // groups listed for the second kernel + groups that took the ballot
+    // branch (none in a slot-only build)
+    const int64_t off_slot = int64_t(h->host_cnt[0]) + int64_t(h->host_cnt[1]);
+    ix.build_mode = off_slot == 0              ? BuildMode::kSlotAll
+                    : off_slot * 100 <= groups ? BuildMode::kSlotOnly
+                                               : BuildMode::kFull;
     return FCLSH_OK;
 }
 
@@ -138,7 +149,8 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
     FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
-                                 ix.p2_slot_only, st, marks ? marks + 2 : nullptr));
+                                 ix.build_mode, st, marks ? marks + 2 : nullptr));
+    h->cnt_mode = ix.build_mode;
     FCLSH_HIP(hipMemcpyAsync(h->host_cnt, table_build_counts(h->aux, L, ix.n, ix.dir_bits), 2 * sizeof(uint32_t),
                              hipMemcpyDeviceToHost, st));
     FCLSH_HIP(hipEventRecord(h->cnt_ev, st));
@@ -385,6 +397,14 @@ fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const
 fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream) {
     if (!idx) return fail(FCLSH_EINVAL, "null index");
     return hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream));
+}
+
+fclsh_status fclsh_index_build_mode(fclsh_index idx, int32_t *mode) {
+    if (!idx || !mode) return fail(FCLSH_EINVAL, "null argument");
+    IndexHandle *h = handle(idx);
+    FCLSH_TRY(take_build_counts(h));
+    *mode = int32_t(h->ix.build_mode);
+    return FCLSH_OK;
 }
 
 fclsh_status fclsh_index_rebuild_async(fclsh_index idx, void *stream) {

@@ -81,11 +81,19 @@ struct QueryTuning {
     int blocks_per_cu = 8;   // persistent workgroups per CU
 };
 
+// Pass 2's group kernel form of a build (identical tables in every one):
+//   kFull      slot and ballot branches (every index's first build);
+//   kSlotOnly  slot branch, groups with a bin over kMaxFastBin entries left
+//              to the second kernel;
+//   kSlotAll   slot branch for every group up to the tile, bin sizes not
+//              checked (right for any bin, slow on large ones).
+enum class BuildMode { kFull, kSlotOnly, kSlotAll };
+
 struct Index {
     Params prm;
     QueryTuning tuning;
     int num_cus = 256;
-    bool p2_slot_only = false;  // pass-2 kernel form for the next build (see build_tables_2pass)
+    BuildMode build_mode = BuildMode::kFull;  // for the next build (see build_tables_2pass)
     int W = 1;
     int64_t n = 0;
     int dir_bits = 1;
@@ -163,10 +171,8 @@ inline int64_t xcd_grid(int64_t nitems) { return (nitems + kXcds - 1) / kXcds * 
 int table_dir_bits(int64_t n);
 int table_split_bits(int64_t n, int dir_bits);
 size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits);
-// slot_only picks pass 2's slot-only group kernel (large-bin groups go to the
-// second kernel) over the full one (ballot branch in the same kernel).
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
-                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, bool slot_only,
+                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
                                 hipStream_t st, hipEvent_t *marks = nullptr);
 // Pass 2's counters in the scratch after a build: [0] groups listed for the
 // second kernel, [1] groups that took the ballot branch.

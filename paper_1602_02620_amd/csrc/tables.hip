@@ -415,7 +415,10 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t *sh) {
 // (kGroupLeft) instead of taking the ballot branch.
 constexpr int kGroupLeft = 0, kGroupSlot = 1, kGroupBallot = 2;
 
-template <bool SLOT_ONLY>
+// ANY_BIN (with SLOT_ONLY): the slot branch takes every group of at most
+// kFastTile entries without looking at its bin sizes (its ranking is right
+// for any bin, only slower on a large one), which saves a block reduction.
+template <bool SLOT_ONLY, bool ANY_BIN = false>
 __device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -441,9 +444,12 @@ __device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
     for (int it = 0; it < kFastItems; ++it)
         pos[it] = ok(it) ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
     __syncthreads();
-    uint32_t mx = 0;
-    for (int i = threadIdx.x; i < R; i += kNT) mx = max(mx, cnt[i]);
-    const bool fast = block_max_u32(mx, sh) <= kMaxFastBin;
+    bool fast = true;
+    if constexpr (!ANY_BIN) {
+        uint32_t mx = 0;
+        for (int i = threadIdx.x; i < R; i += kNT) mx = max(mx, cnt[i]);
+        fast = block_max_u32(mx, sh) <= kMaxFastBin;
+    }
     if (SLOT_ONLY && !fast) return kGroupLeft;
     if (!fast) {
         for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // per-wave counters
@@ -624,13 +630,13 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
 // Pass 2, group kernel over every (table, group); groups over kFastTile
 // entries (and, in the slot-only form, groups with a large bin) are appended
 // to rest[] for p2_rest_kernel.  counts[0] = listed groups, counts[1] =
-// groups that took the ballot branch.  The slot-only form (52 VGPRs, 4
+// groups that took the ballot branch.  The slot-only form (51 VGPRs, 4
 // workgroups per CU) is chosen for a rebuild when the previous build sent
-// at most 1 % of the groups off the slot branch; the full form needs 68
-// VGPRs (3 per CU).
+// at most 1 % of the groups off the slot branch, with ANY_BIN (60 VGPRs)
+// when it sent none; the full form needs 68 VGPRs (3 per CU).
 // (iids and tids may be the same array: the ids are then reordered in place,
 // each group reading its whole run into registers before writing it.)
-template <bool SLOT_ONLY>
+template <bool SLOT_ONLY, bool ANY_BIN = false>
 __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const uint32_t *__restrict__ ikeys, const uint32_t *iids, int64_t n, const uint32_t *__restrict__ gstart,
     int gbits, int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
@@ -643,7 +649,7 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
     const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
-    const int how = a.count <= uint32_t(kFastTile) ? p2_group<SLOT_ONLY>(a, lds, sh) : kGroupLeft;
+    const int how = a.count <= uint32_t(kFastTile) ? p2_group<SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
     if (threadIdx.x == 0) {
         if (how == kGroupLeft) rest[atomicAdd(counts, 1u)] = uint32_t(w);
         if (how == kGroupBallot) atomicAdd(counts + 1, 1u);
@@ -845,7 +851,7 @@ const uint32_t *table_build_counts(const uint32_t *scratch, int64_t L, int64_t n
 }
 
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
-                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, bool slot_only,
+                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
                                 hipStream_t st, hipEvent_t *marks) {
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
@@ -891,7 +897,10 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
     const size_t lds_fast = (size_t(p2_region_a(lo_bits)) + (size_t(1) << lo_bits) + 1) * 4;
     const int64_t nitems2 = int64_t(L) << gbits;  // (table, group) items, a multiple of kXcds
-    if (slot_only)
+    if (mode == BuildMode::kSlotAll)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<true, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
+                           st, p2k, p2v, n, gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
+    else if (mode == BuildMode::kSlotOnly)
         hipLaunchKernelGGL(p2_fast_kernel<true>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
                            gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
     else

@@ -278,6 +278,7 @@ def test_rebuild_slot_only_with_large_bins():
     db = idx.info["dir_bits"]
     assert idx.info["group_bits"] == 8
     wk, wi = orc.binned_tables(db)
+    assert idx.build_mode == "slot_only"
     for build in ("first build", "rebuild", "second rebuild", "async rebuilds"):
         if build == "async rebuilds":
             # enqueued without host waits; the table reads follow on the stream
@@ -289,11 +290,48 @@ def test_rebuild_slot_only_with_large_bins():
         tk, ti = idx.tables()
         assert np.array_equal(as_u32(tk), wk), build
         assert np.array_equal(as_u32(ti), wi), build
+        assert idx.build_mode == "slot_only", build
     # a query enqueued right after an asynchronous rebuild sees the new tables
     qs = pts[[0, 100, 5000]]
     idx.rebuild_async()
     offs, ids = idx.query(dev(qs), r)
     assert_same_lists(csr_lists(offs, ids), oracle.brute_force(pts, d, qs, r).ids)
+    idx.close()
+
+
+@pytest.mark.parametrize("n", [300_000, 8192 * 3 + 77], ids=["many_tiles", "ragged"])
+def test_rebuild_slot_all(n):
+    """Uniform keys: the first build sends no group off the slot branch, so
+    rebuilds take pass 2's slot branch for every group without checking bin
+    sizes.  Tables and directory equal the oracle's after each of them,
+    synchronous or not, and so do query answers."""
+    rng = np.random.default_rng(43 + n % 5)
+    d, r, seed = 64, 4, 43
+    pts = synth.uniform_points(n, d, rng)
+    idx = fc.Index(dev(pts), d, r, seed=seed)
+    pr = oracle.derive_params(d, r, seed)
+    orc = OracleIndex(pts, pr, with_tables=False)
+    db = idx.info["dir_bits"]
+    wk, wi = orc.binned_tables(db)
+    assert idx.build_mode == "slot_all"
+    for build in ("rebuild", "second rebuild", "async rebuilds"):
+        if build == "async rebuilds":
+            idx.rebuild_async()
+            idx.rebuild_async()
+        else:
+            idx.rebuild()
+        _say(f"[slot-all] n={n} {build}")
+        tk, ti = idx.tables()
+        assert np.array_equal(as_u32(tk), wk), build
+        assert np.array_equal(as_u32(ti), wi), build
+        assert idx.build_mode == "slot_all", build
+    dr = as_u32(idx.directory())
+    for T in range(pr.L):
+        bins = np.sort(orc.keys[T] >> np.uint32(31 - db))
+        assert np.array_equal(dr[T], np.searchsorted(bins, np.arange((1 << db) + 1)).astype(np.uint32)), f"table {T}"
+    qs = pts[rng.choice(n, size=5, replace=False)]
+    idx.rebuild_async()
+    assert_same_lists(csr_lists(*idx.query(dev(qs), r)), oracle.brute_force(pts, d, qs, r).ids)
     idx.close()
 
 
@@ -418,6 +456,15 @@ def test_split_pass_for_large_n(n, dup, split):
     wk, wi = orc.binned_tables(inf["dir_bits"])
     assert np.array_equal(as_u32(tk), wk)
     assert np.array_equal(as_u32(ti), wi)
+    # a rebuild in the form the first build's counters chose gives the same
+    # tables (uniform keys: the slot-all form)
+    mode = idx.build_mode
+    assert dup or mode == "slot_all"
+    _say(f"[split] rebuild ({mode})")
+    idx.rebuild()
+    tk, ti = idx.tables()
+    assert np.array_equal(as_u32(tk), wk), mode
+    assert np.array_equal(as_u32(ti), wi), mode
     db = inf["dir_bits"]
     dr = as_u32(idx.directory())
     for T in range(pr.L):
