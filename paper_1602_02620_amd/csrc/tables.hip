@@ -63,17 +63,35 @@ __device__ inline uint64_t lanemask_lt() {
 // lanes with ok set), from one ballot per digit bit: a lane differs from this
 // one if, for some bit, its ballot bit differs from this lane's bit.  The
 // sign-extended bit (0 or all ones) serves both the ballot and the XOR.
-__device__ inline uint64_t same_digit_lanes(uint32_t dg, int bits, bool ok) {
-    const uint64_t act = __ballot(ok);
-    if (!act) return 0;  // a round without entries (wave-uniform)
-    uint32_t dlo = 0, dhi = 0;
+// Four VALU instructions per bit: the bit field extract, the compare that
+// makes the ballot, and one three-input bit operation (acc | (neg ^ ballot),
+// truth table 0xde) per half of the mask.  Written with the builtins because
+// the plain expressions compile to six (a second shift for the compare, and
+// separate XORs and ORs).
+// N rounds at once, bit-major, so that the compares of one round fill the
+// wait between another round's compare and the reads of its ballot.
+template <int N>
+__device__ inline void same_digit_lanes(const uint32_t (&dg)[N], int bits, const bool (&ok)[N],
+                                        uint64_t (&same)[N]) {
+    uint32_t dlo[N], dhi[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) dlo[k] = dhi[k] = 0;
     for (int b = 0; b < bits; ++b) {
-        const int32_t neg = int32_t(dg << (31 - b)) >> 31;
-        const uint64_t bb = __ballot(neg != 0);
-        dlo |= uint32_t(bb) ^ uint32_t(neg);
-        dhi |= uint32_t(bb >> 32) ^ uint32_t(neg);
+        int32_t neg[N];
+        uint64_t bb[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            neg[k] = __builtin_amdgcn_sbfe(int32_t(dg[k]), b, 1);
+            bb[k] = __builtin_amdgcn_uicmp(uint32_t(neg[k]), 0u, 33);  // 33: not equal
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            dlo[k] = __builtin_amdgcn_bitop3_b32(uint32_t(neg[k]), dlo[k], uint32_t(bb[k]), 0xde);
+            dhi[k] = __builtin_amdgcn_bitop3_b32(uint32_t(neg[k]), dhi[k], uint32_t(bb[k] >> 32), 0xde);
+        }
     }
-    return act & ~((uint64_t(dhi) << 32) | dlo);
+#pragma unroll
+    for (int k = 0; k < N; ++k) same[k] = __ballot(ok[k]) & ~((uint64_t(dhi[k]) << 32) | dlo[k]);
 }
 
 // Stable ranks of a wave's ITEMS rounds of 64 digits (round-major, then lane
@@ -90,15 +108,20 @@ __device__ inline void wave_stable_ranks_of(DigitOf digit, ValidOf ok, int bits,
     for (int g0 = 0; g0 < ITEMS; g0 += GRP) {
         uint32_t before[GRP], lead[GRP], old[GRP];
 #pragma unroll
-        for (int k = 0; k < GRP; ++k) {
-            const int it = g0 + k;
-            if (it >= ITEMS) break;
-            const uint32_t dg = digit(it);
-            const bool v = ok(it);
-            const uint64_t same = same_digit_lanes(dg, bits, v);
-            before[k] = uint32_t(__popcll(same & lt));
-            lead[k] = same ? uint32_t(__builtin_ctzll(same)) : 0u;
-            old[k] = (v && before[k] == 0) ? atomicAdd(&wcw[dg], uint32_t(__popcll(same))) : 0u;
+        for (int k = 0; k < GRP; k += 2) {  // two rounds at a time
+            if (g0 + k >= ITEMS) break;
+            const bool two = k + 1 < GRP && g0 + k + 1 < ITEMS;
+            const uint32_t dg[2] = {digit(g0 + k), two ? digit(g0 + k + 1) : 0u};
+            const bool v[2] = {ok(g0 + k), two && ok(g0 + k + 1)};
+            uint64_t same[2];
+            same_digit_lanes<2>(dg, bits, v, same);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !two) break;
+                before[k + h] = uint32_t(__popcll(same[h] & lt));
+                lead[k + h] = same[h] ? uint32_t(__builtin_ctzll(same[h])) : 0u;
+                old[k + h] = (v[h] && before[k + h] == 0) ? atomicAdd(&wcw[dg[h]], uint32_t(__popcll(same[h]))) : 0u;
+            }
         }
 #pragma unroll
         for (int k = 0; k < GRP; ++k)
