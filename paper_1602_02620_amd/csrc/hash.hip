@@ -36,10 +36,17 @@ namespace {
 constexpr double kTwo52 = 4503599627370496.0;
 constexpr uint32_t kHiWord52 = 0x43300000u;  // high word of 2^52 as a double
 
-// All ones if coordinate c (bit c & 31 of word c >> 5 of the staged point x)
-// is set, else zero.
-__device__ inline uint32_t coord_mask(const uint32_t *x, uint32_t c) {
-    return uint32_t(__builtin_amdgcn_sbfe(int32_t(x[c >> 5]), c & 31u, 1u));
+// A coordinate c as the gather table holds it: the byte offset of its dword
+// in the staged point (4 * (c >> 5)) times 32, plus its bit (c & 31).  The
+// dword's address is then one shift from the entry, and the bit field
+// extract reads the entry as its offset (the hardware uses its low 5 bits).
+__host__ __device__ constexpr uint32_t coord_entry(uint32_t c) { return ((c >> 5) << 7) | (c & 31u); }
+
+// All ones if the coordinate of entry e is set in the staged point x, else
+// zero.
+__device__ inline uint32_t coord_mask(const uint32_t *x, uint32_t e) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(x) + (e >> 5));
+    return uint32_t(__builtin_amdgcn_sbfe(int32_t(w), e, 1u));
 }
 
 // Shape of one launch: V = 2^LOGV sketch entries per lane, G lanes per unit
@@ -347,7 +354,7 @@ fclsh_status build_hash_plan(Index *ix) {
     pl.t = p.t;
     pl.W = ix->W;
     const int G = pl.G, V = pl.V;
-    const int32_t zero_slot = 64 * ix->W;  // coordinate reading the staged zero dword
+    const uint32_t zero_slot = coord_entry(uint32_t(64 * ix->W));  // reads the staged zero dword
 
     // column -> coordinates of each part
     std::vector<std::vector<std::vector<int32_t>>> lists(p.t, std::vector<std::vector<int32_t>>(D));
@@ -372,7 +379,7 @@ fclsh_status build_hash_plan(Index *ix) {
     }
     pl.E = std::max(E, 1);
     std::vector<uint32_t> tab(size_t(p.t) * pl.E * G * 2, 0);
-    for (size_t i = 0; i < tab.size(); i += 2) tab[i + 1] = uint32_t(zero_slot);
+    for (size_t i = 0; i < tab.size(); i += 2) tab[i + 1] = zero_slot;
     for (int q = 0; q < p.t; ++q) {
         const int32_t *sq = &seg[size_t(q) * (V + 1)];
         for (int k = 0; k < V; ++k)
@@ -383,7 +390,7 @@ fclsh_status build_hash_plan(Index *ix) {
                     const int c = lst[a];
                     const uint64_t b = p.b[c];
                     tab[at] = uint32_t((b & 1) ? b + kPrime : b);  // even representative, < 2^32
-                    tab[at + 1] = uint32_t(c);
+                    tab[at + 1] = coord_entry(uint32_t(c));
                 }
             }
     }
