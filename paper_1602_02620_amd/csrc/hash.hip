@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
                                                        const int32_t *__restrict__ seg,
                                                        const uint2 *__restrict__ gtab, int E,
                                                        uint32_t *__restrict__ keys, int64_t key_stride,
-                                                       int64_t nblk, int64_t nitems) {
+                                                       int64_t nblk, int64_t nitems, int rounds) {
     using S = Shape<LOGD, LOGV>;
     constexpr int V = S::V, G = S::G, U = S::U, D = S::D;
     extern __shared__ __align__(16) uint32_t lds[];
@@ -189,11 +189,12 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     const int wave = threadIdx.x >> 6;
     const int s = lane >> S::LOGU;
     const int u = lane & (U - 1);
-    // work item: (part p, block of 4 point groups), XCD-contiguous
+    // work item: (part p, `rounds` consecutive blocks of 4 point groups),
+    // XCD-contiguous
     const int64_t witem = xcd_contiguous_item(blockIdx.x, gridDim.x);
     if (witem >= nitems) return;  // grid padding
     const int p = int(witem / nblk);
-    const int64_t g0 = (witem % nblk) * 4;
+    const int64_t c0 = (witem % nblk) * 4 * rounds;  // the item's first point group
     const int stride = 2 * W + 1;
     uint2 *tab = reinterpret_cast<uint2 *>(lds);
     uint32_t *wx = lds + 2 * E * G + wave * U * stride;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     // segment instead of the U of one wave.
     uint32_t *stage = lds + 2 * E * G + 4 * U * stride;
     const int64_t ngroups = (m + U - 1) / U;
-    {
+    for (int64_t g0 = c0; g0 < c0 + 4 * rounds && g0 < ngroups; g0 += 4) {  // workgroup-uniform
         const int64_t grp = g0 + wave;
         const int64_t base = grp * U;
         if (grp < ngroups) {  // wave-uniform
@@ -313,6 +314,14 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     }
 }
 
+// Rounds of 4 point groups per workgroup (the gather table is staged once
+// for all of them), by measurement: short-lived workgroups (D' below 512)
+// gain from several rounds, the 512-column kernel loses (hash times in ms
+// for 1 / 2 / 4 / 8 rounds: D' = 512, 1M points: 0.68 / 0.79 / 0.75 / 0.76;
+// D' = 128, 10M points: 1.45 / 1.36 / 1.33 / 1.31; D' = 128 with several
+// coordinates per column, 4M points: 2.55 / 2.46 / 2.56 / 2.57).
+inline int hash_rounds(int logD, bool specific) { return logD >= 9 ? 1 : specific ? 4 : 2; }
+
 template <int LOGD, int LOGV>
 fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys, int64_t key_stride,
                       hipStream_t st) {
@@ -322,16 +331,17 @@ fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t 
                        stage_words<LOGD, S::U>() * 4;
     if (lds > 160 * 1024) return fail(FCLSH_EUNSUPPORTED, "hash kernel LDS need %zu bytes", lds);
     const int64_t ngroups = (m + S::U - 1) / S::U;
-    const int64_t nblk = (ngroups + 3) / 4;  // blocks of 4 point groups per part
+    const int rounds = hash_rounds(LOGD, pl.specific);
+    const int64_t nblk = (ngroups + 4 * rounds - 1) / (4 * rounds);  // work items per part
     const int64_t nitems = nblk * pl.t;
     const int64_t grid = xcd_grid(nitems);
     if (grid > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "%lld points need too many workgroups", (long long)m);
     if (pl.specific)
         hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, true>), dim3(unsigned(grid)), dim3(256), lds, st, pts, m,
-                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems);
+                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems, rounds);
     else
         hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, false>), dim3(unsigned(grid)), dim3(256), lds, st, pts, m,
-                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems);
+                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems, rounds);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
