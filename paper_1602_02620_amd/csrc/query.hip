@@ -126,6 +126,7 @@ __device__ inline void item_coords(const VerifyArgs &a, uint32_t it, int64_t &qi
 
 // Bins of at most this many entries are scanned by one lane.
 constexpr uint32_t kLaneBin = 32;
+static_assert(kLaneBin <= 32, "a lane keeps the matches of its bin in a 32-bit mask");
 // Batches of more queries number their items table-major.
 constexpr int64_t kTableMajorBatch = 2048;
 
@@ -247,9 +248,19 @@ __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, co
             key[k] = j < j1 ? bk[j] : ~qkey;
             id[k] = j < j1 ? ids[j] : 0u;
         }
+        // the lane's matches among its R4 entries, verified one per round
+        // (as in the item pass)
+        uint32_t mm = 0;
 #pragma unroll
-        for (int k = 0; k < R4; ++k)
-            if (key[k] == qkey && near_in_table(a, spc, qi, T, qkey, rq, key[k], id[k])) emit_pair(a, ps, qi, id[k]);
+        for (int k = 0; k < R4; ++k) mm |= uint32_t(key[k] == qkey) << k;
+        while (mm) {
+            const int k = __builtin_ctz(mm);
+            mm &= mm - 1;
+            uint32_t idk = id[0];
+#pragma unroll
+            for (int h = 1; h < R4; ++h) idk = k == h ? id[h] : idk;
+            if (near_in_table(a, spc, qi, T, qkey, rq, qkey, idk)) emit_pair(a, ps, qi, idk);
+        }
     }
 }
 
@@ -355,17 +366,25 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
         const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
         const uint32_t *ids = a.tids + int64_t(T) * a.n;
         const int rq = query_radius(a, qi);
-        // the bin's keys in chunks of 8 independent loads, then the matches
+        // the bin's keys in chunks of 8 independent loads, giving the mask of
+        // matching positions (a bin here holds at most kLaneBin = 32)
+        uint32_t mm = 0;
         for (uint32_t j0 = lo; j0 < hi; j0 += 8) {
             uint32_t kk[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) kk[c] = j0 + c < hi ? bk[j0 + c] : ~qkey;
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (kk[c] == qkey) {
-                    const uint32_t id = ids[j0 + c];
-                    if (near_in_table(a, spc, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
-                }
+            for (int c = 0; c < 8; ++c) mm |= uint32_t(kk[c] == qkey) << (j0 - lo + uint32_t(c));
+        }
+        // then the matches, one per lane at a time: the lanes verify their
+        // k-th matches together, so the wave runs as many rounds of the
+        // dependent loads (id, then point) as its busiest lane has matches,
+        // not one per matching position
+        while (mm) {
+            const uint32_t c = uint32_t(__builtin_ctz(mm));
+            mm &= mm - 1;
+            const uint32_t id = ids[lo + c];
+            if (near_in_table(a, spc, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
         }
     }
     flush_pairs(a, ps, stage_count(ps));
