@@ -48,30 +48,47 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
         uint32_t B[kMaxLogD];
 #pragma unroll
         for (int l = 0; l < kMaxLogD; ++l) B[l] = l < mbits ? (1u << l) : 0u;
-        for (int w = 0; w < W; ++w) {
-            uint64_t diff = x[w] ^ q[w];
-            if (w == W - 1) diff &= last_mask;
-            while (diff) {
-                const int c = w * 64 + __builtin_ctzll(diff);
-                diff &= diff - 1;
-                const uint32_t pcc = pc[c];
-                if (int(pcc >> 16) != p) continue;
-                const uint32_t uc = pcc & 0xFFFFu;
-                // constrain the basis to v with <v, uc> = 0: the odd vector
-                // with the lowest leading bit is dropped and XORed into the
-                // other odd ones (their leading bits are higher, so they stay
-                // distinct)
-                int star = -1;
-                uint32_t bs = 0;
+        for (int w0 = 0; w0 < W; w0 += 4) {
+            // four words per round trip (clamped indexes, as in the Hamming
+            // test), one when the vectors have one word
+            uint64_t dw[4];
+            if (W == 1) {
+                dw[0] = x[0] ^ q[0];
+                dw[1] = dw[2] = dw[3] = 0ull;
+            } else {
 #pragma unroll
-                for (int l = 0; l < kMaxLogD; ++l) {
-                    if (B[l] && (__popc(B[l] & uc) & 1)) {
-                        if (star < 0) {
-                            star = l;
-                            bs = B[l];
-                            B[l] = 0u;
-                        } else {
-                            B[l] ^= bs;
+                for (int j = 0; j < 4; ++j) {
+                    const int w = min(w0 + j, W - 1);
+                    dw[j] = x[w] ^ q[w];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int w = w0 + j;
+                uint64_t diff = w < W ? dw[j] : 0ull;
+                if (w == W - 1) diff &= last_mask;
+                while (diff) {
+                    const int c = w * 64 + __builtin_ctzll(diff);
+                    diff &= diff - 1;
+                    const uint32_t pcc = pc[c];
+                    if (int(pcc >> 16) != p) continue;
+                    const uint32_t uc = pcc & 0xFFFFu;
+                    // constrain the basis to v with <v, uc> = 0: the odd
+                    // vector with the lowest leading bit is dropped and XORed
+                    // into the other odd ones (their leading bits are higher,
+                    // so they stay distinct)
+                    int star = -1;
+                    uint32_t bs = 0;
+#pragma unroll
+                    for (int l = 0; l < kMaxLogD; ++l) {
+                        if (B[l] && (__popc(B[l] & uc) & 1)) {
+                            if (star < 0) {
+                                star = l;
+                                bs = B[l];
+                                B[l] = 0u;
+                            } else {
+                                B[l] ^= bs;
+                            }
                         }
                     }
                 }
@@ -132,13 +149,27 @@ constexpr int64_t kTableMajorBatch = 2048;
 
 __device__ inline int query_radius(const VerifyArgs &a, int64_t qi) { return a.rq_vec ? a.rq_vec[qi] : a.rq; }
 
-// popcount(x XOR q) over the W words (pad bits masked).
+// popcount(x XOR q) over the W words (pad bits masked).  The words are
+// loaded four at a time (indexes clamped to the last word, which is then
+// masked out), so a candidate costs one round trip per four words rather
+// than one per word.
 __device__ inline int hamming(const uint64_t *x, const uint64_t *q, int W, uint64_t last_mask) {
+    if (W == 1) return __popcll((x[0] ^ q[0]) & last_mask);
     int dist = 0;
-    for (int w = 0; w < W; ++w) {
-        uint64_t df = x[w] ^ q[w];
-        if (w == W - 1) df &= last_mask;
-        dist += __popcll(df);
+    for (int w0 = 0; w0 < W; w0 += 4) {
+        uint64_t xw[4], qw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = min(w0 + j, W - 1);
+            xw[j] = x[w];
+            qw[j] = q[w];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint64_t df = xw[j] ^ qw[j];
+            if (w0 + j == W - 1) df &= last_mask;
+            dist += w0 + j < W ? __popcll(df) : 0;
+        }
     }
     return dist;
 }
@@ -245,14 +276,15 @@ __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, co
 #pragma unroll
         for (int k = 0; k < R4; ++k) {
             const uint32_t j = b0 + uint32_t(k) * 64u + uint32_t(lane);
-            key[k] = j < j1 ? bk[j] : ~qkey;
-            id[k] = j < j1 ? ids[j] : 0u;
+            key[k] = bk[min(j, j1 - 1)];  // clamped, so the loads need no branch
+            id[k] = ids[min(j, j1 - 1)];
         }
         // the lane's matches among its R4 entries, verified one per round
         // (as in the item pass)
         uint32_t mm = 0;
 #pragma unroll
-        for (int k = 0; k < R4; ++k) mm |= uint32_t(key[k] == qkey) << k;
+        for (int k = 0; k < R4; ++k)
+            mm |= uint32_t(key[k] == qkey && b0 + uint32_t(k) * 64u + uint32_t(lane) < j1) << k;
         while (mm) {
             const int k = __builtin_ctz(mm);
             mm &= mm - 1;
@@ -370,11 +402,15 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
         // matching positions (a bin here holds at most kLaneBin = 32)
         uint32_t mm = 0;
         for (uint32_t j0 = lo; j0 < hi; j0 += 8) {
+            // unconditional loads (index clamped to the bin's last entry) so
+            // that all 8 are in flight together; positions past the bin are
+            // masked below
             uint32_t kk[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) kk[c] = j0 + c < hi ? bk[j0 + c] : ~qkey;
+            for (int c = 0; c < 8; ++c) kk[c] = bk[min(j0 + uint32_t(c), hi - 1)];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) mm |= uint32_t(kk[c] == qkey) << (j0 - lo + uint32_t(c));
+            for (int c = 0; c < 8; ++c)
+                mm |= uint32_t(kk[c] == qkey && j0 + uint32_t(c) < hi) << (j0 - lo + uint32_t(c));
         }
         // then the matches, one per lane at a time: the lanes verify their
         // k-th matches together, so the wave runs as many rounds of the
