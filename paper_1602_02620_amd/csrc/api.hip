@@ -93,9 +93,6 @@ static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bi
     return b;
 }
 
-// Hash + table build on st, then a synchronisation.  marks (optional,
-// kRebuildPhases + 1 events): before the hash, after the hash, then after
-// each table kernel.
 // The next build's pass-2 form (BuildMode), from pass 2's counters of the
 // last build.  A rebuild hashes the index's own points with its fixed hash
 // functions, so its groups and bins are those of the last build, whose
@@ -122,7 +119,8 @@ static fclsh_status take_build_counts(IndexHandle *h) {
 }
 
 // Enqueues hash + table build on st; sync = wait for it (and take the
-// counters) before returning.
+// counters) before returning.  marks (optional, kRebuildPhases + 1 events):
+// before the hash, after the hash, then after each table kernel.
 static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *marks = nullptr, bool sync = true) {
     Index &ix = h->ix;
     const int64_t L = ix.prm.L();
@@ -133,16 +131,15 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
         FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n, ix.dir_bits),
                             "table histograms"));
     }
-    if (!h->host_cnt) {
-        if (hipHostMalloc(reinterpret_cast<void **>(&h->host_cnt), 2 * sizeof(uint32_t), hipHostMallocDefault) !=
+    if (!h->host_cnt &&
+        hipHostMalloc(reinterpret_cast<void **>(&h->host_cnt), 2 * sizeof(uint32_t), hipHostMallocDefault) !=
             hipSuccess) {
-            h->host_cnt = nullptr;
-            return fail(FCLSH_ENOMEM, "pinned host allocation failed");
-        }
-        if (hipEventCreateWithFlags(&h->cnt_ev, hipEventDisableTiming) != hipSuccess) {
-            h->cnt_ev = nullptr;
-            return fail(FCLSH_EDEVICE, "hipEventCreate failed");
-        }
+        h->host_cnt = nullptr;
+        return fail(FCLSH_ENOMEM, "pinned host allocation failed");
+    }
+    if (!h->cnt_ev && hipEventCreateWithFlags(&h->cnt_ev, hipEventDisableTiming) != hipSuccess) {
+        h->cnt_ev = nullptr;
+        return fail(FCLSH_EDEVICE, "hipEventCreate failed");
     }
     FCLSH_TRY(take_build_counts(h));
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
