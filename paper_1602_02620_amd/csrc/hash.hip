@@ -169,13 +169,14 @@ constexpr size_t stage_words() {
     return size_t(stage_index<LOGD, U>((1 << LOGD) - 2, 4 * U - 1)) + 1;
 }
 
-// One workgroup of 4 waves per (part, 4 consecutive point groups), in
-// XCD-contiguous order; each wave takes one group of U consecutive points and
-// the block writes the keys of its 4U points out together.  Short-lived
-// waves keep every SIMD full: a grid-stride loop over groups measured 1.9x
-// slower on the mid workload.  The part's
-// gather table (per in-lane column k and sub-lane s, the coordinate feeding
-// it and its even representative b'') is staged in LDS once per workgroup.
+// One workgroup of 4 waves per (part, `rounds` x 4 consecutive point
+// groups), in XCD-contiguous order; in each round every wave takes one group
+// of U consecutive points and the block writes the keys of its 4U points out
+// together.  Short-lived waves keep every SIMD full: a grid-stride loop over
+// groups measured 1.9x slower on the mid workload, and the 512-column kernel
+// runs one round (see hash_rounds).  The part's gather table (per in-lane
+// column k and sub-lane s, the coordinate feeding it and its even
+// representative b'') is staged in LDS once per workgroup.
 template <int LOGD, int LOGV, bool SPECIFIC>
 __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restrict__ pts, int64_t m, int W,
                                                        const int32_t *__restrict__ seg,
