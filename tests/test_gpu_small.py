@@ -407,6 +407,37 @@ def test_largest_hadamard_order():
     idx.close()
 
 
+def test_many_matches_per_bin_across_the_lane_limit():
+    """Groups of 1, 8, 31, 32, 33 and 64 equal points: their keys are equal in
+    every table, so a query at one of them finds that many matches in one bin
+    of each table.  Bins of up to 32 entries are verified by one lane (the
+    matches kept in a 32-bit mask, one verified per round), larger ones go
+    to the spill queue; both sides of that limit are hit.  Queries at the
+    points and at distance 1 and 2 equal the linear scan."""
+    rng = np.random.default_rng(47)
+    d, r, seed = 64, 4, 47
+    base = synth.uniform_points(4000, d, rng)
+    sizes = [1, 8, 31, 32, 33, 64]
+    reps = synth.uniform_points(len(sizes), d, rng)
+    pts = np.concatenate([base] + [np.repeat(reps[i:i + 1], k, axis=0) for i, k in enumerate(sizes)])
+    pts = pts[rng.permutation(len(pts))]
+    idx = fc.Index(dev(pts), d, r, seed=seed)
+    qs = np.concatenate([reps] + [np.stack([synth.flip_distinct(x, d, dist, rng) for x in reps]) for dist in (1, 2)])
+    # the queried bins straddle the lane limit
+    db = idx.info["dir_bits"]
+    qk = as_u32(idx.hash(dev(reps)))
+    dr = as_u32(idx.directory())
+    sizes_seen = set()
+    for T in range(qk.shape[0]):
+        b = qk[T] >> np.uint32(31 - db)
+        sizes_seen.update((dr[T, b + 1] - dr[T, b]).tolist())
+    assert min(sizes_seen) <= 32 < max(sizes_seen), sorted(sizes_seen)[:5]
+    want = oracle.brute_force(pts, d, qs, r).ids
+    assert_same_lists(csr_lists(*idx.query(dev(qs), r)), want)
+    assert_same_lists(csr_lists(*idx.query_plain(dev(qs[:6]), r)), want[:6])
+    idx.close()
+
+
 def test_rebuild_is_deterministic():
     w = synth.small(0.1)
     idx = fc.Index(dev(w.points), w.d, w.r, seed=5)
