@@ -104,8 +104,10 @@ FCLSH_API fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed,
  * at most 65535 tables.
  * The build hashes every point into its L keys (Alg. 2), then buckets each
  * table (hash tables of non-empty buckets, Sec. 2.2): every table is stored
- * as its n (key, id) pairs sorted by key then id, with a directory over the
- * top key bits.  The index keeps a copy of the points for the distance
+ * as its n (key, id) pairs grouped by directory bin (the top dir_bits bits of
+ * the 31-bit key), ids ascending within a bin, with the directory of bin
+ * starts.  A bucket (equal keys) lies inside one bin; keys within a bin are
+ * not sorted.  The index keeps a copy of the points for the distance
  * checks of queries.  Index memory is allocated by the library on the current
  * device and released by fclsh_index_free.
  * Errors: FCLSH_EINVAL, FCLSH_EUNSUPPORTED, FCLSH_ENOMEM, FCLSH_EDEVICE.
@@ -187,9 +189,10 @@ FCLSH_API fclsh_status fclsh_hash(fclsh_index idx, const uint64_t *d_pts, int64_
                         uint32_t *d_keys, void *stream);
 
 /* Device pointers of the index's tables: keys and ids [L][n] uint32 (table T
- * at offset T*n, sorted by key then id), directory [L][2^dir_bits + 1] uint32
- * (start of the entries whose key has the given top dir_bits bits of 31) and
- * the point copy [n][W] uint64.  Owned by the index; read only. */
+ * at offset T*n, grouped by directory bin, ids ascending within a bin; see
+ * fclsh_build_index), directory [L][2^dir_bits + 1] uint32 (start of the
+ * entries whose key has the given top dir_bits bits of 31) and the point
+ * copy [n][W] uint64.  Owned by the index; read only. */
 FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys,
                                 const uint32_t **d_tids, const uint32_t **d_dir,
                                 const uint64_t **d_points);
