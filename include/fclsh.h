@@ -61,7 +61,11 @@ typedef struct fclsh_graph_s *fclsh_graph;
 typedef struct {
     int32_t partitions;        /* t; 0 = the experiments' rule: 1 if r < 10 else 2
                                   (Sec. 4.1 parameter settings, Sec. 4.3)          */
-    int32_t reserved;          /* must be 0                                        */
+    int32_t replicate;         /* Alg. 1's first branch: 0 or 1 = none; k > 1 builds
+                                  the family on k copies of every point (the
+                                  replicated point has k*d coordinates, k*d <= 4096,
+                                  and distances grow k-fold, so the radius becomes
+                                  k*r with one part; partitions must be 0 or 1)   */
     uint64_t prime;            /* 0 or 2^31-1 (the only prime the kernels support) */
     uint64_t mem_budget_bytes; /* 0 = no limit; else the build fails with
                                   FCLSH_ENOMEM if the index and its build scratch
@@ -86,8 +90,13 @@ typedef struct {
  * [p*floor(d/t), (p+1)*floor(d/t)) of the permutation, the last part taking
  * the remainder.
  *
- * Outputs (host arrays of d entries): part[c] in [0,t), col[c] in
- * [0, 2^(r'+1)), b[c] in [0, P).  *t_out and *r_part_out receive t and r'.
+ * With opts->replicate = k > 1 (Alg. 1, first branch) the draws are those
+ * of d' = k*d coordinates and radius k*r with t = 1: coordinate c' of the
+ * replicated point is copy c' / d of coordinate c' mod d.
+ *
+ * Outputs (host arrays of d' entries, d' = d without replication): part[c]
+ * in [0,t), col[c] in [0, 2^(r'+1)), b[c] in [0, P).  *t_out and
+ * *r_part_out receive t and r'.
  * Errors: FCLSH_EINVAL (d <= 0, r < 0, null pointer), FCLSH_EUNSUPPORTED
  * (r' > 11, t > 64 or t > d, prime other than 2^31-1).
  * ------------------------------------------------------------------------- */
@@ -177,7 +186,8 @@ FCLSH_API fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r,
                               int32_t *t, int32_t *r_part, int64_t *n,
                               int32_t *L, int32_t *dir_bits, int32_t *group_bits);
 
-/* The parameters an index was built with (host arrays of d entries). */
+/* The parameters an index was built with (host arrays of d' entries: d
+ * times the replication, see fclsh_derive_params). */
 FCLSH_API fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col,
                                 uint64_t *b);
 

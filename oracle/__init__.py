@@ -9,6 +9,7 @@ definition of the paper, each citing its passage); this module only compiles it
 with gcc and marshals numpy arrays through ctypes.
 
     derive_params   Alg. 1 partitioning + Alg. 2 random draws (SplitMix64)
+    replicate       Alg. 1 replication (the copies of a point concatenated)
     masks           basic CoveringLSH masks g_v, Eq. (2) / Eq. (5)
     keys            Eq. (1) universal hash of g_v AND x  (O(d L) per point)
     tables          hash tables of non-empty buckets, sorted by (key, id)
@@ -127,6 +128,22 @@ def derive_params(d: int, r: int, seed: int, override_t: int = 0, P: int = MERSE
     if rc != 0:
         raise ValueError(f"oracle refused parameters d={d} r={r} t={override_t}")
     return Params(d, r, t.value, rp.value, part, col, b, P)
+
+
+def replicate(points: np.ndarray, d: int, times: int) -> np.ndarray:
+    """Alg. 1, first branch: every point repeated `times` times, the copies
+    concatenated (coordinate i*d + c of the result is coordinate c).  A
+    distance of k between two points becomes times * k.  uint64 [n, W] with d
+    coordinates -> uint64 [n, W'] with times * d coordinates."""
+    points = np.ascontiguousarray(points, np.uint64)
+    n = points.shape[0]
+    bits = np.unpackbits(points.view(np.uint8).reshape(n, -1), axis=1, bitorder="little")[:, :d]
+    rep = np.tile(bits, (1, times))
+    dd = times * d
+    W2 = (dd + 63) // 64
+    padded = np.zeros((n, W2 * 64), np.uint8)
+    padded[:, :dd] = rep
+    return np.packbits(padded, axis=1, bitorder="little").view(np.uint64).reshape(n, W2)
 
 
 def explicit_params(d: int, rpart: int, part, col, b, P: int = MERSENNE31, r: int | None = None) -> Params:

@@ -50,7 +50,7 @@ class FclshError(RuntimeError):
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("partitions", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("partitions", ctypes.c_int32), ("replicate", ctypes.c_int32),
                 ("prime", ctypes.c_uint64), ("mem_budget_bytes", ctypes.c_uint64)]
 
 
@@ -115,14 +115,16 @@ def words(d: int) -> int:
     return (d + 63) // 64
 
 
-def derive_params(d: int, r: int, seed: int, partitions: int = 0):
-    """Host-only parameter draw: returns dict(t, r_part, part, col, b)."""
-    part = np.zeros(d, np.int32)
-    col = np.zeros(d, np.int32)
-    b = np.zeros(d, np.uint64)
+def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int = 0):
+    """Host-only parameter draw: returns dict(t, r_part, part, col, b), the
+    arrays over the d * replicate coordinates of the replicated point."""
+    dd = d * max(1, replicate)
+    part = np.zeros(dd, np.int32)
+    col = np.zeros(dd, np.int32)
+    b = np.zeros(dd, np.uint64)
     t = ctypes.c_int32()
     rp = ctypes.c_int32()
-    opts = BuildOpts(partitions, 0, 0, 0)
+    opts = BuildOpts(partitions, replicate, 0, 0)
     _check(lib().fclsh_derive_params(d, r, seed & (2**64 - 1), ctypes.byref(opts), ctypes.byref(t),
                                      ctypes.byref(rp), part.ctypes.data, col.ctypes.data, b.ctypes.data))
     return {"t": t.value, "r_part": rp.value, "part": part, "col": col, "b": b}
@@ -162,14 +164,14 @@ class Index:
     """An exact r-NN index (Def. 2) built on the GPU.  Immutable."""
 
     def __init__(self, points, d: int, r: int, seed: int = 0, partitions: int = 0,
-                 mem_budget_bytes: int = 0, stream=None, *, _params=None):
+                 mem_budget_bytes: int = 0, stream=None, *, replicate: int = 0, _params=None):
         torch = _torch()
         pts = _dev_words(points, d, "points")
         n = pts.shape[0]
         h = ctypes.c_void_p()
         st = _stream_ptr(stream)
         if _params is None:
-            opts = BuildOpts(partitions, 0, 0, mem_budget_bytes)
+            opts = BuildOpts(partitions, replicate, 0, mem_budget_bytes)
             _check(lib().fclsh_build_index(ctypes.c_void_p(pts.data_ptr()), n, d, r, seed & (2**64 - 1),
                                            ctypes.byref(opts), st, ctypes.byref(h)))
         else:
@@ -182,6 +184,7 @@ class Index:
                                                        0, st, ctypes.byref(h)))
         self._h = h
         self.d = d
+        self.replicate = max(1, replicate) if _params is None else 1  # copies per point of the family
         self.device = pts.device
         self._ids_per_query = 64.0  # sizes the id buffer of the next batch
         del torch
@@ -212,7 +215,7 @@ class Index:
                 "dir_bits": db.value, "group_bits": gb.value}
 
     def params(self) -> dict:
-        d = self.d
+        d = self.d * self.replicate  # the family's coordinates
         part = np.zeros(d, np.int32)
         col = np.zeros(d, np.int32)
         b = np.zeros(d, np.uint64)

@@ -200,14 +200,15 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tids), size_t(L * n) * 4, "table ids")) ||
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dir),
                        size_t(L) * ((size_t(1) << ix.dir_bits) + 1) * 4, "directory")) ||
-        (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dpc), size_t(ix.prm.d) * 4, "params")))
+        (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dpc), size_t(ix.prm.dd()) * 4, "params")))
         return bail(s);
     if ((s = build_hash_plan(&ix))) return bail(s);
     {
         // (part, column) of each coordinate in one word for the dedupe test:
         // parts and columns (< 2^kMaxLogD) each fit 16 bits
-        std::vector<uint32_t> pc(size_t(ix.prm.d));
-        for (int c = 0; c < ix.prm.d; ++c) pc[size_t(c)] = uint32_t(ix.prm.part[c]) << 16 | uint32_t(ix.prm.col[c]);
+        std::vector<uint32_t> pc(size_t(ix.prm.dd()));
+        for (int c = 0; c < ix.prm.dd(); ++c)
+            pc[size_t(c)] = uint32_t(ix.prm.part[c]) << 16 | uint32_t(ix.prm.col[c]);
         if (hipMemcpy(ix.dpc, pc.data(), pc.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(FCLSH_EDEVICE, "parameter upload failed"));
     }
@@ -297,7 +298,7 @@ fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed, const fcls
     FCLSH_TRY(derive_params(d, r, seed, opts, &p));
     *t_out = p.t;
     *r_part_out = p.rp;
-    for (int c = 0; c < d; ++c) {
+    for (int c = 0; c < p.dd(); ++c) {
         part[c] = p.part[c];
         col[c] = p.col[c];
         b[c] = p.b[c];
@@ -365,7 +366,7 @@ fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r, int32_t *
 fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col, uint64_t *b) {
     if (!idx) return fail(FCLSH_EINVAL, "null index");
     const Index &ix = handle(idx)->ix;
-    for (int c = 0; c < ix.prm.d; ++c) {
+    for (int c = 0; c < ix.prm.dd(); ++c) {
         if (part) part[c] = ix.prm.part[c];
         if (col) col[c] = ix.prm.col[c];
         if (b) b[c] = ix.prm.b[c];

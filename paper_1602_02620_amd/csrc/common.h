@@ -46,10 +46,15 @@ inline int ilog2_ceil(uint64_t x) {
 }
 
 // Host-side parameters of one index (Alg. 1 + Alg. 2 draws).
+// d: dimensions of the points; rep: copies of every point the family is
+// built on (Alg. 1's replication; 1 = none), so the family's coordinates
+// are the dd() = rep * d bits of the replicated point, coordinate c' reading
+// bit c' mod d.  part, col and b have dd() entries.
 struct Params {
-    int d = 0, r = 0, t = 1, rp = 0;
+    int d = 0, r = 0, t = 1, rp = 0, rep = 1;
     std::vector<int32_t> part, col;
     std::vector<uint64_t> b;
+    int dd() const { return rep * d; }
     int D() const { return 1 << (rp + 1); }
     int Lp() const { return D() - 1; }
     int L() const { return t * Lp(); }

@@ -369,7 +369,9 @@ fclsh_status build_hash_plan(Index *ix) {
 
     // column -> coordinates of each part
     std::vector<std::vector<std::vector<int32_t>>> lists(p.t, std::vector<std::vector<int32_t>>(D));
-    for (int c = 0; c < p.d; ++c) lists[p.part[c]][p.col[c]].push_back(c);
+    // (with replication, coordinate c of the replicated point is bit c mod d
+    // of the point: each bit feeds one column per copy)
+    for (int c = 0; c < p.dd(); ++c) lists[p.part[c]][p.col[c]].push_back(c);
     size_t most = 0;
     for (auto &lp : lists)
         for (auto &l : lp) most = std::max(most, l.size());
@@ -401,7 +403,7 @@ fclsh_status build_hash_plan(Index *ix) {
                     const int c = lst[a];
                     const uint64_t b = p.b[c];
                     tab[at] = uint32_t((b & 1) ? b + kPrime : b);  // even representative, < 2^32
-                    tab[at + 1] = coord_entry(uint32_t(c));
+                    tab[at + 1] = coord_entry(uint32_t(c % p.d));
                 }
             }
     }

@@ -75,17 +75,23 @@ const char *last_error_cstr() { return g_last_error.c_str(); }
 
 fclsh_status check_params(const Params &p) {
     if (p.d <= 0 || p.d > kMaxDims) return fail(FCLSH_EUNSUPPORTED, "d=%d outside [1, %d]", p.d, kMaxDims);
+    if (p.rep < 1 || (p.rep > 1 && p.t != 1))
+        return fail(FCLSH_EINVAL, "replication (%d copies) needs a single part", p.rep);
+    if (p.dd() > kMaxDims)
+        return fail(FCLSH_EUNSUPPORTED, "%d copies of d=%d exceed %d coordinates", p.rep, p.d, kMaxDims);
     if (p.t < 1 || p.t > kMaxParts || p.t > p.d)
         return fail(FCLSH_EUNSUPPORTED, "t=%d parts unsupported for d=%d", p.t, p.d);
     if (p.rp < 0 || p.rp + 1 > kMaxLogD)
         return fail(FCLSH_EUNSUPPORTED, "per-part radius r'=%d: 2^(r'+1) exceeds %d columns", p.rp,
                     1 << kMaxLogD);
-    if (p.r < 0 || p.r / p.t > p.rp)
+    // a replicated point has rep times the distance (Alg. 1)
+    if (p.r < 0 || p.r * p.rep / p.t > p.rp)
         return fail(FCLSH_EINVAL, "radius r=%d not covered by t=%d parts of radius %d", p.r, p.t, p.rp);
-    if ((int)p.part.size() != p.d || (int)p.col.size() != p.d || (int)p.b.size() != p.d)
-        return fail(FCLSH_EINVAL, "parameter arrays must have d entries");
+    const int dd = p.dd();
+    if ((int)p.part.size() != dd || (int)p.col.size() != dd || (int)p.b.size() != dd)
+        return fail(FCLSH_EINVAL, "parameter arrays must have d * replicate entries");
     std::vector<int> seen(p.t, 0);
-    for (int c = 0; c < p.d; ++c) {
+    for (int c = 0; c < dd; ++c) {
         if (p.part[c] < 0 || p.part[c] >= p.t) return fail(FCLSH_EINVAL, "part[%d]=%d out of range", c, p.part[c]);
         if (p.col[c] < 0 || p.col[c] >= p.D()) return fail(FCLSH_EINVAL, "col[%d]=%d out of range", c, p.col[c]);
         if (p.b[c] >= kPrime) return fail(FCLSH_EINVAL, "b[%d] not below the prime", c);
@@ -96,13 +102,22 @@ fclsh_status check_params(const Params &p) {
     return FCLSH_OK;
 }
 
-fclsh_status derive_params(int d, int r, uint64_t seed, const fclsh_build_opts *opts, Params *out) {
-    if (d <= 0 || r < 0) return fail(FCLSH_EINVAL, "need d > 0 and r >= 0 (d=%d r=%d)", d, r);
-    if (opts && opts->reserved != 0) return fail(FCLSH_EINVAL, "fclsh_build_opts.reserved must be 0");
+fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts *opts, Params *out) {
+    if (d0 <= 0 || r < 0) return fail(FCLSH_EINVAL, "need d > 0 and r >= 0 (d=%d r=%d)", d0, r);
+    if (opts && opts->replicate < 0) return fail(FCLSH_EINVAL, "negative replicate");
     if (opts && opts->prime != 0 && opts->prime != kPrime)
         return fail(FCLSH_EUNSUPPORTED, "only the prime 2^31-1 is supported");
+    // Alg. 1, first branch: rep copies of every point, so a radius r becomes
+    // rep * r on rep * d coordinates, with one part
+    const int rep = (opts && opts->replicate > 1) ? opts->replicate : 1;
+    if (rep > 1 && opts->partitions > 1)
+        return fail(FCLSH_EINVAL, "replication and partitioning are exclusive (Alg. 1)");
+    if (int64_t(rep) * d0 > kMaxDims)
+        return fail(FCLSH_EUNSUPPORTED, "%d copies of d=%d exceed %d coordinates", rep, d0, kMaxDims);
+    const int d = rep * d0;  // coordinates the family is drawn for
+    r *= rep;
     // Sec. 4.1 / Sec. 4.3: partition only for large radii (r >= 10, two parts).
-    int t = (opts && opts->partitions > 0) ? opts->partitions : (r >= 10 ? 2 : 1);
+    int t = rep > 1 ? 1 : (opts && opts->partitions > 0) ? opts->partitions : (r >= 10 ? 2 : 1);
     if (t > d || t > kMaxParts) return fail(FCLSH_EUNSUPPORTED, "t=%d parts for d=%d", t, d);
     int rp = r / t;  // pigeonhole: some part keeps at most floor(r/t) differences
     if (rp + 1 > kMaxLogD)
@@ -111,8 +126,9 @@ fclsh_status derive_params(int d, int r, uint64_t seed, const fclsh_build_opts *
     const int D = 1 << (rp + 1);
 
     Params p;
-    p.d = d;
-    p.r = r;
+    p.d = d0;
+    p.r = r / rep;
+    p.rep = rep;
     p.t = t;
     p.rp = rp;
     p.part.assign(d, 0);

@@ -42,8 +42,13 @@ namespace {
 // -1 if there is none (then d(x, q) exceeds what the family covers).
 // pc[c] = part(c) << 16 | column(c) (the verification kernels stage it in
 // LDS).
+// With replication (rep copies of every point, Alg. 1), the family's
+// coordinates are the rep * d0 bits of the replicated point: a differing bit
+// c differs in every copy, and each copy i constrains by its own column
+// pc[i * d0 + c].
 __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t *__restrict__ q, int W,
-                                  const uint32_t *__restrict__ pc, int t, int mbits, int Lp, uint64_t last_mask) {
+                                  const uint32_t *__restrict__ pc, int t, int mbits, int Lp, uint64_t last_mask,
+                                  int d0, int rep) {
     for (int p = 0; p < t; ++p) {
         uint32_t B[kMaxLogD];
 #pragma unroll
@@ -68,26 +73,28 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
                 uint64_t diff = w < W ? dw[j] : 0ull;
                 if (w == W - 1) diff &= last_mask;
                 while (diff) {
-                    const int c = w * 64 + __builtin_ctzll(diff);
+                    const int c0 = w * 64 + __builtin_ctzll(diff);
                     diff &= diff - 1;
-                    const uint32_t pcc = pc[c];
-                    if (int(pcc >> 16) != p) continue;
-                    const uint32_t uc = pcc & 0xFFFFu;
-                    // constrain the basis to v with <v, uc> = 0: the odd
-                    // vector with the lowest leading bit is dropped and XORed
-                    // into the other odd ones (their leading bits are higher,
-                    // so they stay distinct)
-                    int star = -1;
-                    uint32_t bs = 0;
+                    for (int i = 0, c = c0; i < rep; ++i, c += d0) {
+                        const uint32_t pcc = pc[c];
+                        if (int(pcc >> 16) != p) continue;
+                        const uint32_t uc = pcc & 0xFFFFu;
+                        // constrain the basis to v with <v, uc> = 0: the odd
+                        // vector with the lowest leading bit is dropped and
+                        // XORed into the other odd ones (their leading bits
+                        // are higher, so they stay distinct)
+                        int star = -1;
+                        uint32_t bs = 0;
 #pragma unroll
-                    for (int l = 0; l < kMaxLogD; ++l) {
-                        if (B[l] && (__popc(B[l] & uc) & 1)) {
-                            if (star < 0) {
-                                star = l;
-                                bs = B[l];
-                                B[l] = 0u;
-                            } else {
-                                B[l] ^= bs;
+                        for (int l = 0; l < kMaxLogD; ++l) {
+                            if (B[l] && (__popc(B[l] & uc) & 1)) {
+                                if (star < 0) {
+                                    star = l;
+                                    bs = B[l];
+                                    B[l] = 0u;
+                                } else {
+                                    B[l] ^= bs;
+                                }
                             }
                         }
                     }
@@ -104,6 +111,7 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
 struct VerifyArgs {
     const uint64_t *pts;
     int W, d, t, mbits, Lp, L;
+    int d0, rep;  // dimensions of a point and copies per point (d = rep * d0 staged words)
     uint64_t last_mask;
     const uint32_t *pc;  // part << 16 | column per coordinate (global; staged in LDS per workgroup)
     const uint64_t *queries;
@@ -249,7 +257,7 @@ __device__ inline bool near_in_table(const VerifyArgs &a, const uint32_t *spc, i
     const uint64_t *xp = a.pts + int64_t(id) * a.W;
     const uint64_t *qp = a.queries + qi * a.W;
     if (hamming(xp, qp, a.W, a.last_mask) > rq) return false;
-    return first_shared_table(xp, qp, a.W, spc, a.t, a.mbits, a.Lp, a.last_mask) == T;
+    return first_shared_table(xp, qp, a.W, spc, a.t, a.mbits, a.Lp, a.last_mask, a.d0, a.rep) == T;
 }
 
 // Stages the per-coordinate (part, column) words in the workgroup's LDS.
@@ -713,7 +721,9 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.L = L;
     a.last_mask = last_word_mask(ix.prm.d);
     a.pc = ix.dpc;
-    a.d = ix.prm.d;
+    a.d = ix.prm.dd();
+    a.d0 = ix.prm.d;
+    a.rep = ix.prm.rep;
     a.queries = queries;
     a.nq = nq;
     a.rq_vec = rq_vec;
@@ -737,7 +747,7 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     if (nq > 0) {
         // the item pass needs no more waves than rounds of 64 items
         const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 64 * kVerifyWaves));
-        const size_t pc_lds = size_t(ix.prm.d) * 4;  // staged (part, column) words, d <= 4096
+        const size_t pc_lds = size_t(ix.prm.dd()) * 4;  // staged (part, column) words, at most 4096
         hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
         FCLSH_HIP(hipGetLastError());
         hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);

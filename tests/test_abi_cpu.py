@@ -58,6 +58,28 @@ def test_params_match_oracle(d, r, seed, t):
     assert np.array_equal(p["b"], o.b)
 
 
+@pytest.mark.parametrize("d,r,seed,times", [(128, 2, 3011, 4), (128, 3, 3012, 3), (64, 5, 3013, 2),
+                                            (100, 2, 3014, 3), (7, 1, 3015, 2)])
+def test_replicated_params_match_oracle(d, r, seed, times):
+    # Alg. 1's replication: the draws of times*d coordinates at radius times*r, one part
+    p = fc.derive_params(d, r, seed, replicate=times)
+    o = oracle.derive_params(times * d, times * r, seed, override_t=1)
+    assert p["t"] == 1 and p["r_part"] == o.rpart == times * r
+    assert np.array_equal(p["part"], o.part)
+    assert np.array_equal(p["col"], o.col)
+    assert np.array_equal(p["b"], o.b)
+
+
+@pytest.mark.parametrize("d,r,t,times,status", [(64, 2, 2, 3, fc.FCLSH_EINVAL),        # with partitions
+                                                (2048, 1, 0, 3, fc.FCLSH_EUNSUPPORTED),  # 6144 coordinates
+                                                (64, 4, 0, 3, fc.FCLSH_EUNSUPPORTED),    # radius 12: 2^13 columns
+                                                (64, 2, 0, -1, fc.FCLSH_EINVAL)])
+def test_replication_errors(d, r, t, times, status):
+    with pytest.raises(fc.FclshError) as e:
+        fc.derive_params(d, r, 1, partitions=t, replicate=times)
+    assert e.value.status == status
+
+
 @pytest.mark.parametrize("d,r,t,status", [(0, 3, 0, fc.FCLSH_EINVAL), (10, -1, 0, fc.FCLSH_EINVAL),
                                           (64, 24, 0, fc.FCLSH_EUNSUPPORTED),  # r' = 12: 2^13 columns
                                           (4, 2, 5, fc.FCLSH_EUNSUPPORTED),    # more parts than coordinates

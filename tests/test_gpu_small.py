@@ -438,6 +438,38 @@ def test_many_matches_per_bin_across_the_lane_limit():
     idx.close()
 
 
+@pytest.mark.parametrize("d,r,times", [(128, 2, 4), (128, 3, 3), (100, 2, 3), (64, 5, 2)],
+                         ids=["r2x4", "r3x3", "general", "r5x2"])
+def test_replication(d, r, times):
+    """Alg. 1's replication: the family is drawn for times copies of every
+    point (times * d coordinates, radius times * r, one part; Fig. 3's
+    settings give L = 511, 1023, 2047).  The GPU hashes the points
+    themselves, each copy of a bit being one more gather entry; its keys and
+    tables equal the oracle's on the replicated points, and the answers
+    (dedupe over all copies of a differing bit) equal the linear scan on the
+    points."""
+    seed = 3100 + 10 * r + times
+    w = synth.uniform_with_planted(3000, d, r, 30, 6, seed, f"rep{times}")
+    _say(f"[replication] d={d} r={r} x{times}")
+    idx = fc.Index(dev(w.points), d, r, seed=seed, replicate=times)
+    pr = oracle.derive_params(times * d, times * r, seed, override_t=1)
+    assert idx.info["L"] == pr.L and idx.info["t"] == 1
+    p = idx.params()
+    assert np.array_equal(p["col"], pr.col) and np.array_equal(p["b"], pr.b)
+    orc = OracleIndex(oracle.replicate(w.points, d, times), pr, with_tables=False)
+    assert np.array_equal(as_u32(idx.hash(dev(w.points))), orc.keys)
+    assert np.array_equal(as_u32(idx.hash(dev(w.queries))), oracle.keys(oracle.replicate(w.queries, d, times), pr))
+    tk, ti = idx.tables()
+    wk, wi = orc.binned_tables(idx.info["dir_bits"])
+    assert np.array_equal(as_u32(tk), wk) and np.array_equal(as_u32(ti), wi)
+    for rq in sorted({0, max(0, r - 1), r}):
+        want = oracle.brute_force(w.points, d, w.queries, rq).ids
+        assert_same_lists(csr_lists(*idx.query(dev(w.queries), rq)), want)
+    want = oracle.brute_force(w.points, d, w.queries[:4], r).ids
+    assert_same_lists(csr_lists(*idx.query_plain(dev(w.queries[:4]), r)), want)
+    idx.close()
+
+
 def test_rebuild_is_deterministic():
     w = synth.small(0.1)
     idx = fc.Index(dev(w.points), w.d, w.r, seed=5)

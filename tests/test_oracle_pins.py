@@ -106,6 +106,53 @@ def test_printed_table_counts(golden):
         assert pr.t == t and pr.L == L
 
 
+def _bits_to_words(bits: str) -> np.ndarray:
+    # coordinates 1..d left to right -> bit c-1 of the packed point
+    w = np.zeros((1, (len(bits) + 63) // 64), np.uint64)
+    for c, ch in enumerate(bits):
+        if ch == "1":
+            w[0, c // 64] |= np.uint64(1) << np.uint64(c % 64)
+    return w
+
+
+def test_replication_example(golden):
+    for ln in golden("replication.txt"):
+        f = ln.split()
+        if f[0] != "example":
+            continue
+        bits, times, want = f[1], int(f[2]), f[3]
+        got = oracle.replicate(_bits_to_words(bits), len(bits), times)
+        assert np.array_equal(got, _bits_to_words(want))
+
+
+def test_replication_table_counts(golden):
+    # Fig. 3's replication: the family of radius times * r on the replicated
+    # points, one part
+    for ln in golden("replication.txt"):
+        f = ln.split()
+        if f[0] != "tables":
+            continue
+        r, times, L = int(f[1]), int(f[2]), int(f[3])
+        pr = oracle.derive_params(times * 128, times * r, seed=7, override_t=1)
+        assert pr.t == 1 and pr.L == L
+
+
+@pytest.mark.parametrize("d,r,times,seed", [(6, 1, 3, 1), (8, 1, 2, 2), (5, 2, 2, 3)])
+def test_replication_covering_exhaustive(d, r, times, seed):
+    # Theorem 1 on the replicated points: a difference of at most r becomes
+    # one of at most times * r, which the family of that radius covers
+    pr = oracle.derive_params(times * d, times * r, seed, override_t=1)
+    m = oracle.masks(pr).astype(bool)
+    for pos in _all_z(d, r):
+        z = np.zeros((1, 1), np.uint64)
+        for c in pos:
+            z[0, 0] |= np.uint64(1) << np.uint64(c)
+        zz = oracle.replicate(z, d, times)
+        zb = np.array([(int(zz[0, c // 64]) >> (c % 64)) & 1 for c in range(times * d)], bool)
+        assert zb.sum() == times * len(pos)
+        assert np.any(~np.any(m & zb, axis=1)), f"difference {pos} not covered"
+
+
 def test_splitmix64_reference_outputs(golden):
     for ln in golden("splitmix64.txt"):
         seed, k, v = ln.split()
