@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mid", choices=["mid", "small", "learned_code", "batched"])
+    ap.add_argument("--workload", default="mid", choices=["mid", "small", "learned_code", "batched", "fig3_replication"])
     ap.add_argument("--seed", type=int, default=3002)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="rough CPU budget of the oracle leg")
@@ -80,8 +80,9 @@ def main():
     qs = fc.to_device_words(w.queries, dev)
     stream = torch.cuda.current_stream()
 
-    stage(f"build index: {w.name} n={n} d={d} r={r}")
-    idx = fc.Index(pts, d, r, seed=args.seed)
+    rep = int(w.meta.get("replicate", 1))  # Alg. 1's replication (1 = none)
+    stage(f"build index: {w.name} n={n} d={d} r={r} copies={rep}")
+    idx = fc.Index(pts, d, r, seed=args.seed, replicate=rep)
     info = idx.info
     L = info["L"]
     if args.kernel_only:
@@ -211,8 +212,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: n={n} d={d} r={r} L={L} t={info['t']} nq={nq}",
-                   "n": n, "d": d, "r": r, "L": L, "queries": nq, "seed": args.seed},
+        "config": {"workload": f"{w.name}: n={n} d={d} r={r}" + (f" copies={rep}" if rep > 1 else "")
+                               + f" L={L} t={info['t']} nq={nq}",
+                   "n": n, "d": d, "r": r, "L": L, "queries": nq, "seed": args.seed, "copies": rep},
         "breakdown": {
             "hash_ms": ms_hash, "hash_points_per_s": n / (ms_hash * 1e-3),
             "hash_keys_per_s": n * L / (ms_hash * 1e-3),
@@ -422,7 +424,13 @@ def cpu_baseline(w, idx, qs, keys, args, fc):
     import oracle
 
     budget = args.cpu_seconds
-    pr = oracle.derive_params(w.d, w.r, args.seed)
+    rep = int(w.meta.get("replicate", 1))
+    if rep > 1:  # the family of the replicated points (Alg. 1): k*d coordinates, radius k*r, one part
+        pr = oracle.derive_params(rep * w.d, rep * w.r, args.seed, override_t=1)
+        kpts = oracle.replicate(w.points, w.d, rep)
+    else:
+        pr = oracle.derive_params(w.d, w.r, args.seed)
+        kpts = w.points
     mask = oracle.masks(pr)
     cores = oracle.num_threads()
     # keys: calibrate on a sample that keeps every thread busy (the oracle
@@ -430,13 +438,13 @@ def cpu_baseline(w, idx, qs, keys, args, fc):
     # half the budget
     probe = np.arange(min(w.n, 64 * 4 * cores))
     a = time.perf_counter()
-    oracle.keys(w.points, pr, which=probe, mask=mask)
+    oracle.keys(kpts, pr, which=probe, mask=mask)
     per_pt = (time.perf_counter() - a) / len(probe)
     npick = int(max(64, min(w.n, 0.5 * budget / max(per_pt, 1e-9))))
     rng = np.random.default_rng(7)
     which = np.sort(rng.choice(w.n, size=npick, replace=False))
     a = time.perf_counter()
-    ok = oracle.keys(w.points, pr, which=which, mask=mask)
+    ok = oracle.keys(kpts, pr, which=which, mask=mask)
     t_keys = time.perf_counter() - a
     gk = keys[:, which].cpu().numpy().view(np.uint32)
     keys_equal = bool(np.array_equal(gk, ok))

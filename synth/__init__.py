@@ -197,5 +197,16 @@ def served_b(scale: float = 1.0, nq: int = 4096) -> Workload:
     return uniform_with_planted(n, 1024, 20, nq, 5, seed=1006, name="served_b", query_radius=rq)
 
 
+def fig3_replication(scale: float = 1.0) -> Workload:
+    """The shape of the paper's pre-processing experiment (Fig. 3): n = 65,536
+    uniform 128-bit points, r = 3, the index built on 3 copies of every point
+    (L = 1023); 1,000 queries x 10 planted."""
+    n = max(2000, int(65_536 * scale))
+    nq = max(4, int(1000 * scale))
+    w = uniform_with_planted(n, 128, 3, nq, 10, seed=1007, name="fig3_replication")
+    w.meta["replicate"] = 3
+    return w
+
+
 WORKLOADS = {"small": small, "mid": mid, "learned_code": learned_code, "batched": batched,
-             "served_a": served_a, "served_b": served_b}
+             "served_a": served_a, "served_b": served_b, "fig3_replication": fig3_replication}
