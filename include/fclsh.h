@@ -180,8 +180,9 @@ FCLSH_API const char *fclsh_last_error(void);
 
 /* Shape of a built index. Any output pointer may be NULL.  dir_bits: the
  * directory's bin width B (bins = top B key bits); group_bits: the key bits
- * that form the groups of the table build's last pass (8, or more for large
- * n, where a middle pass splits the 256 super-bins further). */
+ * that form the groups of the table build's last pass (8; more for large n,
+ * where a middle pass splits the 256 super-bins further; fewer for small n,
+ * where the last pass merges neighbouring super-bins). */
 FCLSH_API fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r,
                               int32_t *t, int32_t *r_part, int64_t *n,
                               int32_t *L, int32_t *dir_bits, int32_t *group_bits);

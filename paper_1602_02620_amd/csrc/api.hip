@@ -108,7 +108,8 @@ static fclsh_status take_build_counts(IndexHandle *h) {
     h->cnt_pending = false;
     Index &ix = h->ix;
     if (h->cnt_mode == BuildMode::kSlotAll) return FCLSH_OK;
-    const int64_t groups = int64_t(ix.prm.L()) << (8 + table_split_bits(ix.n, ix.dir_bits));
+    const int64_t groups =
+        int64_t(ix.prm.L()) << (8 + table_split_bits(ix.n, ix.dir_bits) - table_merge_bits(ix.n, ix.dir_bits));
     // groups listed for the second kernel + groups that took the ballot
     // branch (none in a slot-only build)
     const int64_t off_slot = int64_t(h->host_cnt[0]) + int64_t(h->host_cnt[1]);
@@ -359,7 +360,7 @@ fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r, int32_t *
     if (n) *n = ix.n;
     if (L) *L = ix.prm.L();
     if (dir_bits) *dir_bits = ix.dir_bits;
-    if (group_bits) *group_bits = 8 + table_split_bits(ix.n, ix.dir_bits);
+    if (group_bits) *group_bits = 8 + table_split_bits(ix.n, ix.dir_bits) - table_merge_bits(ix.n, ix.dir_bits);
     return FCLSH_OK;
 }
 

@@ -175,6 +175,7 @@ inline int64_t xcd_grid(int64_t nitems) { return (nitems + kXcds - 1) / kXcds * 
 // pass-2 group kernel, pass-2 kernel for large groups.
 int table_dir_bits(int64_t n);
 int table_split_bits(int64_t n, int dir_bits);
+int table_merge_bits(int64_t n, int dir_bits);
 size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits);
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
                                 uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,

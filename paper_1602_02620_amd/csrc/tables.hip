@@ -625,17 +625,21 @@ __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) 
     }
 }
 
+// Pass-2 group g is groups [g << gk, (g + 1) << gk) of the earlier passes:
+// gk > 0 merges small neighbouring groups (their keys already in order), and
+// gbits + lo_bits = dir_bits either way.
 __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *gstart,
-                                 int gbits, int lo_bits, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, int T, int g) {
+                                 int gbits, int lo_bits, int gk, uint32_t *tkeys, uint32_t *tids, uint32_t *dir,
+                                 int T, int g) {
     const int64_t toff = int64_t(T) * n;
-    // group starts per table: 2^gbits + 1 (<= 4097), so the index fits 32
-    // bits and stays in scalar registers (a 64-bit product lands in vector
-    // registers, and the block-uniform loop exits of the group kernel then
-    // become exec-masked)
-    const uint32_t gs = (1u << gbits) + 1u;
-    const uint32_t gi = uint32_t(T) * gs + uint32_t(g);
+    // group starts per table: 2^(gbits + gk) + 1 (<= 4097), so the index
+    // fits 32 bits and stays in scalar registers (a 64-bit product lands in
+    // vector registers, and the block-uniform loop exits of the group kernel
+    // then become exec-masked)
+    const uint32_t gs = (1u << (gbits + gk)) + 1u;
+    const uint32_t gi = uint32_t(T) * gs + (uint32_t(g) << gk);
     const uint32_t bs = gstart[gi];
-    const uint32_t be = gstart[gi + 1];
+    const uint32_t be = gstart[gi + (1u << gk)];
     P2Args a;
     a.kin = ikeys + toff + bs;
     a.vin = iids + toff + bs;
@@ -662,7 +666,7 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
 template <bool SLOT_ONLY, bool ANY_BIN = false>
 __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const uint32_t *__restrict__ ikeys, const uint32_t *iids, int64_t n, const uint32_t *__restrict__ gstart,
-    int gbits, int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
+    int gbits, int lo_bits, int gk, uint32_t *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
     uint32_t *__restrict__ rest, uint32_t *__restrict__ counts, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
@@ -671,7 +675,7 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
-    const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
+    const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
     const int how = a.count <= uint32_t(kFastTile) ? p2_group<SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
     if (threadIdx.x == 0) {
         if (how == kGroupLeft) rest[atomicAdd(counts, 1u)] = uint32_t(w);
@@ -685,7 +689,8 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
 // path first copies its ids to spare, which that path then reads.
 __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
                                                          int64_t n, const uint32_t *__restrict__ gstart, int gbits,
-                                                         int lo_bits, uint32_t *__restrict__ tkeys, uint32_t *tids,
+                                                         int lo_bits, int gk, uint32_t *__restrict__ tkeys,
+                                                         uint32_t *tids,
                                                          uint32_t *__restrict__ dir, const uint32_t *__restrict__ rest,
                                                          const uint32_t *__restrict__ rest_count,
                                                          uint32_t *__restrict__ spare) {
@@ -695,7 +700,7 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
     for (uint32_t i = blockIdx.x; i < nrest; i += gridDim.x) {
         const int64_t w = rest[i];
         const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
-        P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, tkeys, tids, dir, T, g);
+        P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
         if (a.count > uint32_t(kTile)) {
             if (iids == tids) {
                 uint32_t *copy = spare + int64_t(T) * n + a.bs;
@@ -855,6 +860,17 @@ int table_split_bits(int64_t n, int dir_bits) {
     return std::min(sb, dir_bits - kHiBits);
 }
 
+// Groups that pass 2 merges into one (as a shift), for small tables: the
+// merged groups average at most 2048 entries, their bin count stays within
+// 2^9 (so the group kernel's LDS is what it is unmerged) and at least 8
+// groups remain per table.
+int table_merge_bits(int64_t n, int dir_bits) {
+    const int gbits = kHiBits + table_split_bits(n, dir_bits);
+    int gk = 0;
+    while ((n >> (gbits - gk - 1)) <= 2048 && dir_bits - gbits + gk + 1 <= 9 && gbits - gk - 1 >= 3) ++gk;
+    return gk;
+}
+
 // tile histograms [L][tiles][256], super-bin starts [L][257], group starts
 // [L][(256 << S) + 1] (S > 0 only), the count of groups left to the stable
 // pass-2 kernel, and the list of those groups [L][256 << S]
@@ -881,7 +897,9 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
     const int nblk = int((n + kP1Tile - 1) / kP1Tile);
     const int S = table_split_bits(n, dir_bits);
-    const int gbits = kHiBits + S, lo_bits = dir_bits - gbits;
+    const int gk = table_merge_bits(n, dir_bits);
+    const int gbits = kHiBits + S, lo_bits = dir_bits - gbits;  // groups of passes 1 and 1b
+    const int gbits2 = gbits - gk, lo_bits2 = lo_bits + gk;     // pass 2's groups
     uint32_t *hist = scratch;
     uint32_t *bstart = hist + size_t(L) * nblk * kHiBins;
     uint32_t *gstart = S ? bstart + size_t(L) * (kHiBins + 1) : bstart;
@@ -917,22 +935,22 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
         p2v = tids;
     }
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
-    const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits)) * 4;
-    const size_t lds_fast = (size_t(p2_region_a(lo_bits)) + (size_t(1) << lo_bits) + 1) * 4;
-    const int64_t nitems2 = int64_t(L) << gbits;  // (table, group) items, a multiple of kXcds
+    const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits2)) * 4;
+    const size_t lds_fast = (size_t(p2_region_a(lo_bits2)) + (size_t(1) << lo_bits2) + 1) * 4;
+    const int64_t nitems2 = int64_t(L) << gbits2;  // (table, group) items, a multiple of kXcds
     if (mode == BuildMode::kSlotAll)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<true, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
-                           st, p2k, p2v, n, gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
+                           st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
     else if (mode == BuildMode::kSlotOnly)
         hipLaunchKernelGGL(p2_fast_kernel<true>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
-                           gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
+                           gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
     else
         hipLaunchKernelGGL(p2_fast_kernel<false>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
-                           gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, nitems2);
+                           gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
     hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2, st,
-                       p2k, p2v, n, gstart, gbits, lo_bits, tkeys, tids, dir, rest, rest_count, tmpv);
+                       p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, tmpv);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[5], st));
     return FCLSH_OK;

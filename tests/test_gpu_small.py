@@ -263,22 +263,26 @@ def test_radius_and_capacity_errors():
     idx.close()
 
 
-def test_rebuild_slot_only_with_large_bins():
+@pytest.mark.parametrize("n,group_bits,mode", [(300000, 8, "slot_only"), (20000, 4, "full")])
+def test_rebuild_slot_only_with_large_bins(n, group_bits, mode):
     """A first build takes pass 2's full group kernel; when it sent at most
     1 % of the groups off the slot branch, a rebuild takes the slot-only form,
     which leaves the groups with a large bin to the second kernel.  Here 60
-    copies of one point put one large bin in every table (1 of 256 groups),
-    so the rebuild exercises that fallback.  Both builds equal the oracle."""
+    copies of one point put one large bin in every table: at 300000 points
+    that is 1 of 256 groups, so the rebuilds exercise that fallback; at 20000
+    points pass 2 merges 16 super-bins per group, one group in 16 holds the
+    bin, and the rebuilds keep the full form (its ballot branch then takes
+    that group).  Every build equals the oracle."""
     rng = np.random.default_rng(41)
-    n, d, r = 20000, 64, 4
+    d, r = 64, 4
     pts = synth.uniform_points(n, d, rng)
     pts[1:61] = pts[0]  # 61 equal points: equal keys in every table
     idx = fc.Index(dev(pts), d, r, seed=41)
     orc = OracleIndex(pts, oracle.derive_params(d, r, 41), with_tables=False)
     db = idx.info["dir_bits"]
-    assert idx.info["group_bits"] == 8
+    assert idx.info["group_bits"] == group_bits
     wk, wi = orc.binned_tables(db)
-    assert idx.build_mode == "slot_only"
+    assert idx.build_mode == mode
     for build in ("first build", "rebuild", "second rebuild", "async rebuilds"):
         if build == "async rebuilds":
             # enqueued without host waits; the table reads follow on the stream
@@ -286,11 +290,11 @@ def test_rebuild_slot_only_with_large_bins():
             idx.rebuild_async()
         elif build != "first build":
             idx.rebuild()
-        _say(f"[slot-only] {build}")
+        _say(f"[slot-only n={n}] {build}")
         tk, ti = idx.tables()
         assert np.array_equal(as_u32(tk), wk), build
         assert np.array_equal(as_u32(ti), wi), build
-        assert idx.build_mode == "slot_only", build
+        assert idx.build_mode == mode, build
     # a query enqueued right after an asynchronous rebuild sees the new tables
     qs = pts[[0, 100, 5000]]
     idx.rebuild_async()
