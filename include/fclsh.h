@@ -70,6 +70,11 @@ typedef struct {
     uint64_t mem_budget_bytes; /* 0 = no limit; else the build fails with
                                   FCLSH_ENOMEM if the index and its build scratch
                                   would exceed it                                  */
+    int32_t exclude_column0;   /* nonzero: the coordinate map never targets column 0
+                                  (the all-zero column), the variant of Sec. 3.2
+                                  with the sharper bound on expected collisions;
+                                  a part is then specific when it has at most
+                                  D - 1 coordinates                               */
 } fclsh_build_opts;
 
 /* ---------------------------------------------------------------------------

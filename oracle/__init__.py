@@ -57,7 +57,7 @@ def lib():
         L.orc_parts_for_radius.restype = i32
         L.orc_parts_for_radius.argtypes = [i32, i32]
         L.orc_derive_params.restype = i32
-        L.orc_derive_params.argtypes = [i32, i32, u64, i32, u64, vp, vp, vp, vp, vp]
+        L.orc_derive_params.argtypes = [i32, i32, u64, i32, u64, i32, vp, vp, vp, vp, vp]
         L.orc_masks.restype = None
         L.orc_masks.argtypes = [i32, i32, i32, vp, vp, vp]
         L.orc_keys.restype = None
@@ -117,13 +117,14 @@ def parts_for_radius(r: int, override_t: int = 0) -> int:
     return int(lib().orc_parts_for_radius(r, override_t))
 
 
-def derive_params(d: int, r: int, seed: int, override_t: int = 0, P: int = MERSENNE31) -> Params:
+def derive_params(d: int, r: int, seed: int, override_t: int = 0, P: int = MERSENNE31,
+                  exclude_column0: bool = False) -> Params:
     part = np.zeros(d, np.int32)
     col = np.zeros(d, np.int32)
     b = np.zeros(d, np.uint64)
     t = ctypes.c_int32()
     rp = ctypes.c_int32()
-    rc = lib().orc_derive_params(d, r, seed & (2**64 - 1), override_t, P, ctypes.byref(t),
+    rc = lib().orc_derive_params(d, r, seed & (2**64 - 1), override_t, P, int(bool(exclude_column0)), ctypes.byref(t),
                                  ctypes.byref(rp), _p(part), _p(col), _p(b))
     if rc != 0:
         raise ValueError(f"oracle refused parameters d={d} r={r} t={override_t}")

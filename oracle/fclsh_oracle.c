@@ -123,7 +123,7 @@ int orc_parts_for_radius(int r, int override_t)
  * Draw order: pi, then the columns part by part, then b.
  * Returns 0, or -1 on bad arguments (r' + 1 > 20 is refused). */
 int orc_derive_params(int d, int r, uint64_t seed, int override_t, uint64_t P,
-                      int32_t *t_out, int32_t *rpart_out,
+                      int skip_col0, int32_t *t_out, int32_t *rpart_out,
                       int32_t *part, int32_t *col, uint64_t *b)
 {
     if (d <= 0 || r < 0 || P < 2)
@@ -135,6 +135,10 @@ int orc_derive_params(int d, int r, uint64_t seed, int override_t, uint64_t P,
     if (rp + 1 > 20)
         return -1;
     int32_t D = 1 << (rp + 1);
+    /* Sec. 3.2 variant: the map m takes values in the columns other than
+     * column 0, so there are D - 1 of them, numbered from 1 */
+    int32_t ncol = skip_col0 ? D - 1 : D;
+    int32_t first = skip_col0 ? 1 : 0;
     orc_rng g = {seed, 0};
 
     int32_t *pi = (int32_t *)malloc(sizeof(int32_t) * (size_t)d);
@@ -150,16 +154,16 @@ int orc_derive_params(int d, int r, uint64_t seed, int override_t, uint64_t P,
         int32_t lo = p * block;
         int32_t hi = (p == t - 1) ? d : (p + 1) * block;
         int32_t dp = hi - lo;
-        if (dp <= D) {
-            orc_shuffle(&g, perm, D);
+        if (dp <= ncol) {
+            orc_shuffle(&g, perm, ncol);
             for (int32_t k = 0; k < dp; k++) {
                 part[pi[lo + k]] = p;
-                col[pi[lo + k]] = perm[k];
+                col[pi[lo + k]] = first + perm[k];
             }
         } else {
             for (int32_t k = 0; k < dp; k++) {
                 part[pi[lo + k]] = p;
-                col[pi[lo + k]] = (int32_t)orc_bounded(&g, (uint64_t)D);
+                col[pi[lo + k]] = first + (int32_t)orc_bounded(&g, (uint64_t)ncol);
             }
         }
     }

@@ -51,7 +51,8 @@ class FclshError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("partitions", ctypes.c_int32), ("replicate", ctypes.c_int32),
-                ("prime", ctypes.c_uint64), ("mem_budget_bytes", ctypes.c_uint64)]
+                ("prime", ctypes.c_uint64), ("mem_budget_bytes", ctypes.c_uint64),
+                ("exclude_column0", ctypes.c_int32)]
 
 
 _lib = None
@@ -115,7 +116,8 @@ def words(d: int) -> int:
     return (d + 63) // 64
 
 
-def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int = 0):
+def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int = 0,
+                  exclude_column0: bool = False):
     """Host-only parameter draw: returns dict(t, r_part, part, col, b), the
     arrays over the d * replicate coordinates of the replicated point."""
     dd = d * max(1, replicate)
@@ -124,7 +126,7 @@ def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int
     b = np.zeros(dd, np.uint64)
     t = ctypes.c_int32()
     rp = ctypes.c_int32()
-    opts = BuildOpts(partitions, replicate, 0, 0)
+    opts = BuildOpts(partitions, replicate, 0, 0, int(bool(exclude_column0)))
     _check(lib().fclsh_derive_params(d, r, seed & (2**64 - 1), ctypes.byref(opts), ctypes.byref(t),
                                      ctypes.byref(rp), part.ctypes.data, col.ctypes.data, b.ctypes.data))
     return {"t": t.value, "r_part": rp.value, "part": part, "col": col, "b": b}
@@ -164,14 +166,15 @@ class Index:
     """An exact r-NN index (Def. 2) built on the GPU.  Immutable."""
 
     def __init__(self, points, d: int, r: int, seed: int = 0, partitions: int = 0,
-                 mem_budget_bytes: int = 0, stream=None, *, replicate: int = 0, _params=None):
+                 mem_budget_bytes: int = 0, stream=None, *, replicate: int = 0,
+                 exclude_column0: bool = False, _params=None):
         torch = _torch()
         pts = _dev_words(points, d, "points")
         n = pts.shape[0]
         h = ctypes.c_void_p()
         st = _stream_ptr(stream)
         if _params is None:
-            opts = BuildOpts(partitions, replicate, 0, mem_budget_bytes)
+            opts = BuildOpts(partitions, replicate, 0, mem_budget_bytes, int(bool(exclude_column0)))
             _check(lib().fclsh_build_index(ctypes.c_void_p(pts.data_ptr()), n, d, r, seed & (2**64 - 1),
                                            ctypes.byref(opts), st, ctypes.byref(h)))
         else:

@@ -124,6 +124,10 @@ fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts 
         return fail(FCLSH_EUNSUPPORTED, "per-part radius %d needs 2^%d columns (max %d)", rp, rp + 1,
                     1 << kMaxLogD);
     const int D = 1 << (rp + 1);
+    // Sec. 3.2 variant: column 0 (the all-zero column of every codeword) is
+    // never a target, so the columns drawn from are 1..D-1
+    const bool skip0 = opts && opts->exclude_column0;
+    const int ncols = skip0 ? D - 1 : D, col0 = skip0 ? 1 : 0;
 
     Params p;
     p.d = d0;
@@ -141,25 +145,25 @@ fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts 
     if (t > 1) rng.shuffle(order);  // Alg. 1: permute before partitioning
 
     const int block = d / t;
-    std::vector<int32_t> cols(D);
+    std::vector<int32_t> cols(ncols);
     for (int q = 0; q < t; ++q) {
         const int begin = q * block;
         const int end = (q + 1 == t) ? d : begin + block;
         const int dq = end - begin;
-        if (dq <= D) {
-            // specific construction: random permutation of the D columns,
-            // the part's coordinates take its first dq entries
-            for (int j = 0; j < D; ++j) cols[j] = j;
+        if (dq <= ncols) {
+            // specific construction: random permutation of the allowed
+            // columns, the part's coordinates take its first dq entries
+            for (int j = 0; j < ncols; ++j) cols[j] = col0 + j;
             rng.shuffle(cols);
             for (int k = 0; k < dq; ++k) {
                 p.part[order[begin + k]] = q;
                 p.col[order[begin + k]] = cols[k];
             }
         } else {
-            // general construction: i.i.d. uniform column per coordinate
+            // general construction: i.i.d. uniform allowed column per coordinate
             for (int k = 0; k < dq; ++k) {
                 p.part[order[begin + k]] = q;
-                p.col[order[begin + k]] = int32_t(rng.below(uint64_t(D)));
+                p.col[order[begin + k]] = col0 + int32_t(rng.below(uint64_t(ncols)));
             }
         }
     }

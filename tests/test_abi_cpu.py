@@ -70,6 +70,22 @@ def test_replicated_params_match_oracle(d, r, seed, times):
     assert np.array_equal(p["b"], o.b)
 
 
+@pytest.mark.parametrize("d,r,t,times", [(64, 4, 0, 0), (31, 4, 0, 0), (32, 4, 0, 0), (100, 6, 0, 0),
+                                         (128, 10, 0, 0), (96, 12, 3, 0), (40, 2, 0, 2)])
+def test_exclude_column0_params_match_oracle(d, r, t, times):
+    # the Sec. 3.2 variant: library and oracle draw the same columns from 1..D-1
+    p = fc.derive_params(d, r, 77, partitions=t, replicate=times, exclude_column0=True)
+    k = max(1, times)
+    o = oracle.derive_params(k * d, k * r, 77, override_t=t if times == 0 else 1, exclude_column0=True)
+    assert p["t"] == o.t and p["r_part"] == o.rpart
+    assert np.array_equal(p["part"], o.part)
+    assert np.array_equal(p["col"], o.col) and p["col"].min() >= 1
+    assert np.array_equal(p["b"], o.b)
+    # without the option the draws differ (column 0 is a legal target there)
+    q = fc.derive_params(d, r, 77, partitions=t, replicate=times)
+    assert not np.array_equal(q["col"], p["col"])
+
+
 @pytest.mark.parametrize("d,r,t,times,status", [(64, 2, 2, 3, fc.FCLSH_EINVAL),        # with partitions
                                                 (2048, 1, 0, 3, fc.FCLSH_EUNSUPPORTED),  # 6144 coordinates
                                                 (64, 4, 0, 3, fc.FCLSH_EUNSUPPORTED),    # radius 12: 2^13 columns

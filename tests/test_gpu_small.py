@@ -474,6 +474,30 @@ def test_replication(d, r, times):
     idx.close()
 
 
+@pytest.mark.parametrize("d,r,t", [(31, 4, 0), (64, 4, 0), (100, 6, 0), (128, 10, 0)],
+                         ids=["specific-boundary", "general", "specific", "two-parts"])
+def test_exclude_column0(d, r, t):
+    """The Sec. 3.2 variant whose map avoids column 0: the parameters, keys
+    and tables equal the oracle's for the same draw, and the answers equal
+    the linear scan."""
+    seed = 3300 + d + r
+    w = synth.uniform_with_planted(3000, d, r, 30, 6, seed, f"x0-{d}")
+    _say(f"[exclude column 0] d={d} r={r}")
+    idx = fc.Index(dev(w.points), d, r, seed=seed, partitions=t, exclude_column0=True)
+    pr = oracle.derive_params(d, r, seed, override_t=t, exclude_column0=True)
+    p = idx.params()
+    assert np.array_equal(p["col"], pr.col) and np.array_equal(p["b"], pr.b) and p["col"].min() >= 1
+    orc = OracleIndex(w.points, pr, with_tables=False)
+    assert np.array_equal(as_u32(idx.hash(dev(w.points))), orc.keys)
+    tk, ti = idx.tables()
+    wk, wi = orc.binned_tables(idx.info["dir_bits"])
+    assert np.array_equal(as_u32(tk), wk) and np.array_equal(as_u32(ti), wi)
+    for rq in sorted({0, r}):
+        want = oracle.brute_force(w.points, d, w.queries, rq).ids
+        assert_same_lists(csr_lists(*idx.query(dev(w.queries), rq)), want)
+    idx.close()
+
+
 def test_rebuild_is_deterministic():
     w = synth.small(0.1)
     idx = fc.Index(dev(w.points), w.d, w.r, seed=5)

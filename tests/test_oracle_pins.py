@@ -309,6 +309,53 @@ def test_theorem2_property2_statistical():
 
 
 # --------------------------------------------------------------------------
+# Sec. 3.2 variant: the coordinate map never targets column 0
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,r,t,seed", [(6, 2, 0, 1), (7, 2, 0, 2), (8, 2, 0, 3), (12, 2, 0, 4),
+                                        (16, 4, 0, 5), (14, 5, 2, 6)])
+def test_exclude_column0_covering_exhaustive(d, r, t, seed):
+    # the variant is still r-covering (every difference pattern of weight <= r
+    # avoids the mask of some row); its columns are 1..D-1, injective in a
+    # part of at most D - 1 coordinates (d = 7 at D = 8 is that boundary,
+    # d = 8 already takes the i.i.d. map)
+    pr = oracle.derive_params(d, r, seed, override_t=t, exclude_column0=True)
+    assert np.all((pr.col >= 1) & (pr.col < pr.D))
+    for q in range(pr.t):
+        cq = pr.col[pr.part == q]
+        if len(cq) <= pr.D - 1:
+            assert len(set(cq.tolist())) == len(cq)
+    m = oracle.masks(pr).astype(bool)
+    for pos in _all_z(d, r):
+        z = np.zeros(d, bool)
+        z[list(pos)] = True
+        assert np.any(~np.any(m & z, axis=1)), f"difference {pos} not covered"
+
+
+def test_exclude_column0_expected_collisions():
+    # General construction (i.i.d. columns): row v != 0 collides on a
+    # difference of k coordinates iff all k columns are orthogonal to v.  Of
+    # the D - 1 columns other than 0, D/2 - 1 are, so the expected number of
+    # colliding rows is (D-1) ((D/2-1)/(D-1))^k, below the bound 2^(r+1-k) of
+    # Sec. 3.2 and below (D-1)/2^k, the value when column 0 may be drawn.
+    rng = np.random.default_rng(23)
+    d, r = 24, 2
+    D = 2 ** (r + 1)
+    for k in range(1, 5):
+        trials = 3000
+        vals = np.empty(trials)
+        for s in range(trials):
+            pr = oracle.derive_params(d, r, 50000 * k + s, exclude_column0=True)
+            z = rng.choice(d, size=k, replace=False)
+            vals[s] = 2 ** (r + 1 - gf2_rank([int(pr.col[c]) for c in z])) - 1
+        exact = (D - 1) * ((D / 2 - 1) / (D - 1)) ** k
+        assert abs(vals.mean() - exact) < 0.08, (k, vals.mean(), exact)
+        assert exact < 2 ** (r + 1 - k) and exact < (D - 1) / 2 ** k
+        if k == 1:
+            assert np.all(vals == D / 2 - 1)  # no column is orthogonal to every row
+
+
+# --------------------------------------------------------------------------
 # Parameter draws: structural invariants of Alg. 1 / Alg. 2
 # --------------------------------------------------------------------------
 
