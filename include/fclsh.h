@@ -105,6 +105,17 @@ typedef struct {
  * Errors: FCLSH_EINVAL (d <= 0, r < 0, null pointer), FCLSH_EUNSUPPORTED
  * (r' > 11, t > 64 or t > d, prime other than 2^31-1).
  * ------------------------------------------------------------------------- */
+/* Alg. 1's choice of pre-processing for n points, radius r and
+ * approximation ratio c, with log taken base 2 (the keys' bits): when
+ * c*r < log n the points are replicated k = floor(log n / (c*r)) times
+ * (*replicate = k, *partitions = 1); when c*r > log n they are split into
+ * t = ceil(c*r / log n) parts (*replicate = 1, *partitions = t); when c*r
+ * equals log n neither (1, 1).  The results go into fclsh_build_opts.
+ * Errors: FCLSH_EINVAL (n < 2, r <= 0, c <= 1 or not a number, null
+ * pointer). */
+FCLSH_API fclsh_status fclsh_preprocessing(int64_t n, int32_t r, double c,
+                                           int32_t *replicate, int32_t *partitions);
+
 FCLSH_API fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed,
                                  const fclsh_build_opts *opts, int32_t *t_out,
                                  int32_t *r_part_out, int32_t *part, int32_t *col,

@@ -19,6 +19,7 @@ with gcc and marshals numpy arrays through ctypes.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -129,6 +130,19 @@ def derive_params(d: int, r: int, seed: int, override_t: int = 0, P: int = MERSE
     if rc != 0:
         raise ValueError(f"oracle refused parameters d={d} r={r} t={override_t}")
     return Params(d, r, t.value, rp.value, part, col, b, P)
+
+
+def preprocessing(n: int, r: int, c: float) -> tuple[int, int]:
+    """Alg. 1's branch for n points, radius r and approximation ratio c, log
+    base 2: (copies, parts) = (floor(log n / cr), 1) when cr < log n,
+    (1, ceil(cr / log n)) when cr > log n, else (1, 1)."""
+    logn = math.log2(n)
+    cr = c * r
+    if cr < logn:
+        return math.floor(logn / cr), 1
+    if cr > logn:
+        return 1, math.ceil(cr / logn)
+    return 1, 1
 
 
 def replicate(points: np.ndarray, d: int, times: int) -> np.ndarray:

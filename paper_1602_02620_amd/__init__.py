@@ -35,6 +35,7 @@ EXPORTS = [
     "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
     "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
+    "fclsh_preprocessing",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -82,6 +83,7 @@ def lib():
             "fclsh_index_rebuild_async": [vp, vp],
             "fclsh_index_rebuild_timed": [vp, vp, P(ctypes.c_float), i32],
             "fclsh_index_build_mode": [vp, P(i32)],
+            "fclsh_preprocessing": [i64, i32, ctypes.c_double, P(i32), P(i32)],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_batch_finish": [vp, vp, vp, vp, i64, P(i64)],
@@ -114,6 +116,13 @@ def _check(status: int):
 
 def words(d: int) -> int:
     return (d + 63) // 64
+
+
+def preprocessing(n: int, r: int, c: float) -> dict:
+    """Alg. 1's choice for n points, radius r, ratio c: dict(replicate, partitions)."""
+    rep, t = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().fclsh_preprocessing(n, r, c, ctypes.byref(rep), ctypes.byref(t)))
+    return {"replicate": rep.value, "partitions": t.value}
 
 
 def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int = 0,

@@ -1,5 +1,7 @@
 // C ABI of the library (declared in include/fclsh.h): argument checking, the
 // index object and its device memory, per-stream query workspaces.
+#include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -290,6 +292,17 @@ using namespace fclsh;
 extern "C" {
 
 const char *fclsh_last_error(void) { return last_error_cstr(); }
+
+fclsh_status fclsh_preprocessing(int64_t n, int32_t r, double c, int32_t *replicate, int32_t *partitions) {
+    if (!replicate || !partitions) return fail(FCLSH_EINVAL, "null output pointer");
+    if (n < 2 || r <= 0 || !(c > 1.0)) return fail(FCLSH_EINVAL, "need n >= 2, r > 0 and c > 1");
+    const double logn = std::log2(double(n)), cr = c * double(r);
+    *replicate = 1;
+    *partitions = 1;
+    if (cr < logn) *replicate = int32_t(std::floor(logn / cr));
+    else if (cr > logn) *partitions = int32_t(std::min(std::ceil(cr / logn), double(1 << 30)));
+    return FCLSH_OK;
+}
 
 fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed, const fclsh_build_opts *opts,
                                  int32_t *t_out, int32_t *r_part_out, int32_t *part, int32_t *col, uint64_t *b) {

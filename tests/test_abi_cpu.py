@@ -70,6 +70,21 @@ def test_replicated_params_match_oracle(d, r, seed, times):
     assert np.array_equal(p["b"], o.b)
 
 
+def test_preprocessing_matches_oracle():
+    for n in [2, 3, 1000, 10000, 65536, 1 << 20, 10 ** 7, 1 << 40]:
+        for c in [1.01, 1.1, 1.5, 2.0, 2.5, 3.0, 7.0]:
+            for r in range(1, 65):
+                got = fc.preprocessing(n, r, c)
+                assert (got["replicate"], got["partitions"]) == oracle.preprocessing(n, r, c), (n, r, c)
+
+
+@pytest.mark.parametrize("n,r,c", [(1, 3, 2.0), (1000, 0, 2.0), (1000, 3, 1.0), (1000, 3, float("nan"))])
+def test_preprocessing_errors(n, r, c):
+    with pytest.raises(fc.FclshError) as e:
+        fc.preprocessing(n, r, c)
+    assert e.value.status == fc.FCLSH_EINVAL
+
+
 @pytest.mark.parametrize("d,r,t,times", [(64, 4, 0, 0), (31, 4, 0, 0), (32, 4, 0, 0), (100, 6, 0, 0),
                                          (128, 10, 0, 0), (96, 12, 3, 0), (40, 2, 0, 2)])
 def test_exclude_column0_params_match_oracle(d, r, t, times):

@@ -8,6 +8,7 @@ colliding functions, a statistical check of Theorem 2 property 2, and brute
 force on tiny inputs.  None of them needs a GPU.
 """
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -306,6 +307,41 @@ def test_theorem2_property2_statistical():
                 tot += 2 ** (r + 1 - gf2_rank(cols)) - 1
             mean = tot / trials
             assert mean < 2 ** (r + 1 - dist) * 1.05 + 0.05, (d, r, dist, mean)
+
+
+# --------------------------------------------------------------------------
+# Alg. 1: which pre-processing branch, and how many copies or parts
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 1000, 65536, 1 << 20, 10 ** 7, 1 << 40])
+@pytest.mark.parametrize("c", [1.1, 1.5, 2.0, 3.0])
+def test_preprocessing_keeps_tables_near_n_to_1_over_c(n, c):
+    # The pre-processing exists to keep the radius the family is drawn for
+    # at about log(n)/c, so that a part has about n^(1/c) tables: the chosen
+    # copies (or parts) leave that radius at most log(n)/c, and one copy
+    # more (or one part fewer) would push it over.
+    logn = math.log2(n)
+    for r in range(1, 41):
+        k, t = oracle.preprocessing(n, r, c)
+        assert k >= 1 and t >= 1 and (k == 1 or t == 1)
+        if c * r < logn:
+            assert t == 1 and c * k * r <= logn < c * (k + 1) * r
+            assert 2 ** (k * r + 1) - 1 < 2 * n ** (1 / c)
+        elif c * r > logn:
+            assert k == 1 and c * r / t <= logn
+            assert t == 1 or c * r / (t - 1) > logn
+            assert 2 ** (r // t + 1) - 1 < 2 * n ** (1 / c)
+        else:
+            assert (k, t) == (1, 1)
+
+
+def test_preprocessing_special_cases():
+    # c r = log n takes neither branch; small radii replicate, large ones split
+    assert oracle.preprocessing(65536, 8, 2.0) == (1, 1)
+    assert oracle.preprocessing(65536, 2, 2.0) == (4, 1)
+    assert oracle.preprocessing(65536, 1, 1.5) == (10, 1)
+    assert oracle.preprocessing(1 << 20, 20, 2.0) == (1, 2)
+    assert oracle.preprocessing(1 << 20, 21, 2.0) == (1, 3)
 
 
 # --------------------------------------------------------------------------
