@@ -194,6 +194,8 @@ def main():
         idx.query(qs, r)
         lat_batch.append((time.perf_counter() - a) * 1e3)
 
+    # Sec. 4.1's cost measure: summed bucket sizes over the L tables, per query
+    coll_per_query = float(idx.collisions(qs).to(torch.float64).mean().item())
     stage("keys of all points for the oracle comparison")
     keys = torch.empty((L, n), dtype=torch.int32, device=dev)
     idx.hash(pts, out=keys)
@@ -225,7 +227,7 @@ def main():
             "pass2_ballot_share": ballot_entries / entries, "pass2_rest_share": rest_entries / entries,
             "pass2_form": idx.build_mode,
             "query_batch_ms": ms_query, "queries_per_s": nq / (ms_query * 1e-3),
-            "reported_ids": total_ids,
+            "reported_ids": total_ids, "collisions_per_query": coll_per_query,
             "plain_query_ms_p50": pct(lat_plain, 50), "plain_query_ms_p99": pct(lat_plain, 99),
             "plain_queries_per_s": 1e3 / float(np.mean(lat_plain)) if lat_plain else None,
             "batch_latency_ms_p50": pct(lat_batch, 50), "batch_latency_ms_p99": pct(lat_batch, 99),
