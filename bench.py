@@ -6,9 +6,13 @@ neighbours each): hash every point into its L keys (Alg. 2), bucket the keys
 into the L tables, and answer the query batch exactly (Strategy 2).  Inputs
 are resident in HBM before the timed region starts.
 
-Prints one JSON line.  `value` is points per second through the whole step;
-the breakdown (hash-only rate, keys/s, bucketing, queries/s, batched vs plain
-per-query latency) and the roofline of the dominant kernel ride along.
+Prints one JSON line.  `value` is points per second through the whole step.
+Alongside: the breakdown (hash-only rate, keys/s, bucketing, queries/s,
+Sec. 4.1's #Collisions and #Candidates per query), the roofline of the
+dominant kernel and the hash / build / query rooflines at their algorithmic
+bytes, the batched block (an autotuned 100,000-query batch against the plain
+one-launch-sequence-per-query path) and the served block (continuous batching
+of Poisson-arriving requests over the resident index, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -45,6 +49,8 @@ def parse():
                     help="also run the served section (off by default)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rps", type=float, default=100.0, help="Poisson request rate of the served run")
+    ap.add_argument("--serve-max", type=int, default=4096, help="largest request (queries) of the served block")
+    ap.add_argument("--big-batch", type=int, default=100_000, help="queries in the batched block's batch")
     ap.add_argument("--kernel-only", choices=["hash", "build"], default=None,
                     help="profiling aid: launch only this part (plus a plain copy of known size "
                          "for counter calibration) --kernel-reps times")
@@ -82,7 +88,7 @@ def main():
 
     rep = int(w.meta.get("replicate", 1))  # Alg. 1's replication (1 = none)
     stage(f"build index: {w.name} n={n} d={d} r={r} copies={rep}")
-    idx = fc.Index(pts, d, r, seed=args.seed, replicate=rep)
+    idx = fc.Index(pts, d, r, seed=args.seed, replicate=rep, keep_build_scratch=True)
     info = idx.info
     L = info["L"]
     if args.kernel_only:
@@ -146,7 +152,9 @@ def main():
     rest_entries = int(sb_count[rest].sum().item())
     ballot_entries = int(sb_count[~rest & (sb_max > 48)].sum().item())
     dir_bytes = 4 * L * ((1 << dir_bits) + 1)
-    kernel_bytes = {  # algorithmic bytes per launch
+    # bytes each kernel moves itself (its reads and writes, for the counter
+    # comparison) ...
+    moved_bytes = {
         "fht_hash_kernel": n * (W * 8 + 4 * L),                    # read the point, write its L keys
         "p1_hist_kernel": 4 * entries + 4 * L * nblk * 256,          # read keys, write tile histograms
         "p1_scan_kernel": 8 * L * nblk * 256,                        # read + write the histograms
@@ -158,9 +166,19 @@ def main():
         "p2_fast_kernel": 16 * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries),
         "p2_rest_kernel": 16 * rest_entries + dir_bytes * (rest_entries / entries) + 4,
     }
+    # ... and the algorithmic bytes the roofline is priced at: the hash step
+    # reads a point and writes its L keys (d/8 + 4L per point); the table
+    # build's minimum is 12 B per table entry (read a key, write key + id),
+    # which each build kernel is charged for the entries it handles
+    alg_bytes = {k: 12 * entries for k in moved_bytes}
+    alg_bytes["fht_hash_kernel"] = moved_bytes["fht_hash_kernel"]
+    alg_bytes["p1b_split_kernel"] = 12 * entries if group_bits > 8 else 0
+    alg_bytes["p2_fast_kernel"] = 12 * (entries - rest_entries)
+    alg_bytes["p2_rest_kernel"] = 12 * rest_entries
     dominant = max(phase_ms, key=phase_ms.get)
-    achieved = kernel_bytes[dominant] / (phase_ms[dominant] * 1e-3) / 1e9
+    achieved = alg_bytes[dominant] / (phase_ms[dominant] * 1e-3) / 1e9
     ms_hash = phase_ms["fht_hash_kernel"]
+    build_bytes = 12 * entries  # the table build as a whole: read key, write key + id
     ms_build = sum(v for k, v in phase_ms.items() if k != "fht_hash_kernel")
 
     def ev_time(fn, reps):
@@ -194,13 +212,26 @@ def main():
         idx.query(qs, r)
         lat_batch.append((time.perf_counter() - a) * 1e3)
 
-    # Sec. 4.1's cost measure: summed bucket sizes over the L tables, per query
-    coll_per_query = float(idx.collisions(qs).to(torch.float64).mean().item())
+    # Sec. 4.1's cost measures per query: #Collisions (summed bucket sizes
+    # over the L tables) and #Candidates (distinct points among them)
+    coll_t, cand_t = idx.cost(qs)
+    coll_per_query = float(coll_t.to(torch.float64).mean().item())
+    cand_per_query = float(cand_t.to(torch.float64).mean().item())
+    # the query side's algorithmic bytes: per query its d/8 bits, a directory
+    # pair per table, a key and an id per bucket entry (bins mix keys), a
+    # point per distinct candidate (at least one 64-byte sector) and 4 bytes
+    # per reported id
+    q_bytes = (nq * (W * 8 + 8 * L) + 8 * float(coll_t.sum().item())
+               + float(cand_t.sum().item()) * max(W * 8, 64) + 4 * total_ids)
+    extra = {}
+    stage("batched block: autotuned large batch vs plain")
+    extra["batched"] = batched_block(args, w, idx, qs, r, total0, lat_plain, torch, fc)
+    stage("served block: request loop over the resident index")
+    extra["served"] = served_block(args, w, idx, r, lat_plain, torch, fc)
     stage("keys of all points for the oracle comparison")
     keys = torch.empty((L, n), dtype=torch.int32, device=dev)
     idx.hash(pts, out=keys)
     torch.cuda.synchronize()
-    build_bytes = 12 * entries  # the table build as a whole: read key, write key + id
     out = {
         "metric": METRIC,
         "value": n / (ms_step * 1e-3),
@@ -220,7 +251,7 @@ def main():
         "breakdown": {
             "hash_ms": ms_hash, "hash_points_per_s": n / (ms_hash * 1e-3),
             "hash_keys_per_s": n * L / (ms_hash * 1e-3),
-            "hash_GBps": kernel_bytes["fht_hash_kernel"] / (ms_hash * 1e-3) / 1e9,
+            "hash_GBps": alg_bytes["fht_hash_kernel"] / (ms_hash * 1e-3) / 1e9,
             "build_ms": ms_build, "build_entries_per_s": entries / (ms_build * 1e-3),
             "build_GBps_at_12B_per_entry": build_bytes / (ms_build * 1e-3) / 1e9,
             "kernel_ms": phase_ms,
@@ -228,6 +259,7 @@ def main():
             "pass2_form": idx.build_mode,
             "query_batch_ms": ms_query, "queries_per_s": nq / (ms_query * 1e-3),
             "reported_ids": total_ids, "collisions_per_query": coll_per_query,
+            "candidates_per_query": cand_per_query,
             "plain_query_ms_p50": pct(lat_plain, 50), "plain_query_ms_p99": pct(lat_plain, 99),
             "plain_queries_per_s": 1e3 / float(np.mean(lat_plain)) if lat_plain else None,
             "batch_latency_ms_p50": pct(lat_batch, 50), "batch_latency_ms_p99": pct(lat_batch, 99),
@@ -235,8 +267,17 @@ def main():
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dominant, n, d, r),
-                     "bytes_per_launch": kernel_bytes[dominant], "ms_per_launch": phase_ms[dominant]},
+                     "bytes_per_launch": alg_bytes[dominant], "ms_per_launch": phase_ms[dominant],
+                     "moved_bytes_per_launch": moved_bytes[dominant]},
+        "rooflines": {
+            "hash": roof(alg_bytes["fht_hash_kernel"], ms_hash, "fht_hash_kernel", n, d, r,
+                         "d/8 + 4L bytes per point"),
+            "build": roof(build_bytes, ms_build, None, n, d, r, "12 bytes per table entry, all build kernels"),
+            "query": roof(q_bytes, ms_query, None, n, d, r,
+                          "per query d/8 + 8L + 8 per collision + max(d/8, 64) per candidate + 4 per id"),
+        },
     }
+    out.update(extra)
     checks = []
     if not args.no_cpu_baseline:
         stage(f"oracle on the host, about {args.cpu_seconds:.0f} s")
@@ -246,15 +287,93 @@ def main():
     torch.cuda.empty_cache()
     if args.batched:
         stage("batched section")
-        out["batched"], chk = batched_section(args, fc, torch)
+        out["batched_4M_skewed"], chk = batched_section(args, fc, torch)
         checks.append(chk)
     if args.served:
         stage("served section")
-        out["served"], chk = served_section(args, fc, torch)
+        out["served_two_indexes"], chk = served_section(args, fc, torch)
         checks.append(chk)
     if checks and not args.no_cpu_baseline:
         out["cpu_baseline"]["answers_checked"] = verify_samples(checks)
     print(json.dumps(out), flush=True)
+
+
+def roof(nbytes, ms, kernel, n, d, r, basis):
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBS,
+            "bytes": nbytes, "ms": ms, "basis": basis,
+            "traffic": measured_traffic(kernel, n, d, r) if kernel else None}
+
+
+def batched_block(args, w, idx, qs, r, total0, lat_plain, torch, fc):
+    """The batched path at scale on the default index: the autotuner picks
+    the verification launch shape on a sample, then one synchronous batch of
+    the workload's queries repeated to --big-batch queries, against the plain
+    path (one launch sequence and synchronisation per query)."""
+    tune = idx.autotune(qs, r)
+    reps = -(-args.big_batch // qs.shape[0])
+    big = qs.repeat(reps, 1)[:args.big_batch].contiguous()
+    offs, ids = idx.query(big, r)  # sizes the workspace
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(3):
+        a = time.perf_counter()
+        offs, ids = idx.query(big, r)
+        lat.append((time.perf_counter() - a) * 1e3)
+    # every repeat of the base batch answers as the base batch did
+    cnt = (offs[1:] - offs[:-1]).view(-1)
+    base = cnt[:qs.shape[0]]
+    same = bool(torch.equal(cnt, base.repeat(reps)[:cnt.numel()]))
+    ms = float(np.median(lat))
+    qps = big.shape[0] / (ms * 1e-3)
+    plain_qps = 1e3 / float(np.mean(lat_plain))
+    return {"queries": int(big.shape[0]), "tuning": tune, "batch_ms": ms, "queries_per_s": qps,
+            "batch_latency_ms_p50": pct(lat, 50), "batch_latency_ms_p99": pct(lat, 99),
+            "plain_queries_per_s": plain_qps, "plain_query_ms_p50": pct(lat_plain, 50),
+            "plain_query_ms_p99": pct(lat_plain, 99), "speedup_vs_plain": qps / plain_qps,
+            "answers_equal_across_repeats": same, "reported_ids": int(offs[-1].item())}
+
+
+def served_block(args, w, idx, r, lat_plain, torch, fc):
+    """Continuous batching over the resident default index: Poisson request
+    arrivals, request sizes U[1, --serve-max] queries drawn from the
+    workload's queries, radius U{0..r} per request.  Latency is arrival to
+    completion; the plain path's service time for the same request (its
+    queries one launch sequence each) is reported beside it.  Sampled answers
+    are compared with the same queries answered alone."""
+    from paper_1602_02620_amd.serve import Server, poisson_trace
+
+    srv = Server({"mid": idx}, max_batch=args.serve_max, streams=3)
+    rng = np.random.default_rng(31)
+    arrivals = poisson_trace(args.serve_rps, args.serve_seconds, rng)
+    reqs = []
+    t0 = time.perf_counter()
+    for ta in arrivals:
+        while time.perf_counter() - t0 < ta:
+            time.sleep(50e-6)
+        m = int(rng.integers(1, args.serve_max + 1))
+        rows = rng.integers(0, w.nq, size=m)
+        rad = int(rng.integers(0, r + 1))
+        reqs.append((rows, rad, srv.submit("mid", w.queries[rows], rad)))
+    results = [f.result(timeout=300) for *_, f in reqs]
+    t_end = time.perf_counter()
+    srv.close()
+    st = srv.stats()
+    per_q = float(np.mean(lat_plain))
+    plain_req = [per_q * len(rows) for rows, _, _ in reqs]
+    # alone vs in the mix, for a few sampled requests
+    same = True
+    for k in rng.choice(len(reqs), size=min(4, len(reqs)), replace=False):
+        rows, rad, _ = reqs[k]
+        alone = fc.split_csr(*idx.query_radii(fc.to_device_words(w.queries[rows]),
+                                              torch.full((len(rows),), rad, dtype=torch.int32)))
+        same &= all(np.array_equal(a, b) for a, b in zip(alone, results[k]))
+    return {"requests": st["requests"], "queries": st["queries"], "batches": st["batches"],
+            "offered_requests_per_s": args.serve_rps, "seconds": t_end - t0,
+            "queries_per_s": st["queries"] / (t_end - t0),
+            "latency_ms_p50": st["p50_ms"], "latency_ms_p99": st["p99_ms"],
+            "plain_service_ms_p50": pct(plain_req, 50), "plain_service_ms_p99": pct(plain_req, 99),
+            "alone_equals_mix": bool(same)}
 
 
 def batched_section(args, fc, torch):

@@ -57,8 +57,14 @@ typedef struct fclsh_index_s *fclsh_index;
 /* An instantiated HIP graph of one batched query (fclsh_query_graph_create). */
 typedef struct fclsh_graph_s *fclsh_graph;
 
-/* Build options (all-zero = the paper's defaults). */
+/* Build options.  struct_size must be sizeof(fclsh_build_opts) as the caller
+ * was compiled with it (FCLSH_BUILD_OPTS_INIT sets it): the library reads
+ * only the fields that lie inside struct_size and gives the others their
+ * defaults, so a caller built against an older, shorter struct keeps working.
+ * struct_size 0, or larger than the library's struct, is FCLSH_EINVAL.  With
+ * every other field zero the options are the paper's defaults. */
 typedef struct {
+    uint32_t struct_size;      /* sizeof(fclsh_build_opts)                         */
     int32_t partitions;        /* t; 0 = the experiments' rule: 1 if r < 10 else 2
                                   (Sec. 4.1 parameter settings, Sec. 4.3)          */
     int32_t replicate;         /* Alg. 1's first branch: 0 or 1 = none; k > 1 builds
@@ -66,16 +72,24 @@ typedef struct {
                                   replicated point has k*d coordinates, k*d <= 4096,
                                   and distances grow k-fold, so the radius becomes
                                   k*r with one part; partitions must be 0 or 1)   */
+    int32_t exclude_column0;   /* nonzero: the coordinate map never targets column 0
+                                  (the all-zero column), the variant of Sec. 3.3
+                                  with the sharper bound on expected collisions;
+                                  a part is then specific when it has at most
+                                  D - 1 coordinates                               */
     uint64_t prime;            /* 0 or 2^31-1 (the only prime the kernels support) */
     uint64_t mem_budget_bytes; /* 0 = no limit; else the build fails with
                                   FCLSH_ENOMEM if the index and its build scratch
                                   would exceed it                                  */
-    int32_t exclude_column0;   /* nonzero: the coordinate map never targets column 0
-                                  (the all-zero column), the variant of Sec. 3.2
-                                  with the sharper bound on expected collisions;
-                                  a part is then specific when it has at most
-                                  D - 1 coordinates                               */
+    int32_t keep_build_scratch;/* nonzero: keep the build's scratch (3 uint32 per
+                                  table entry plus histograms) resident after the
+                                  build, for rebuilds; 0 = release it when the
+                                  build ends (a later rebuild allocates it again
+                                  and keeps it)                                    */
+    int32_t reserved;          /* must be 0                                        */
 } fclsh_build_opts;
+
+#define FCLSH_BUILD_OPTS_INIT {(uint32_t)sizeof(fclsh_build_opts), 0, 0, 0, 0, 0, 0, 0}
 
 /* ---------------------------------------------------------------------------
  * Index parameters (host only, no device work).
@@ -184,7 +198,10 @@ FCLSH_API fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_quer
                                int64_t ids_capacity, int64_t *total_out);
 
 /* Release an index (NULL is ignored).  The caller must make sure no work using
- * it is still queued. */
+ * it is still queued.  A graph captured on the index (fclsh_query_graph_create)
+ * keeps the index's memory alive: with graphs still alive the index only
+ * becomes unusable (every later call on it fails with FCLSH_EINVAL) and its
+ * memory is released when the last of its graphs is freed. */
 FCLSH_API void fclsh_index_free(fclsh_index idx);
 
 /* Thread-local description of the last failure ("" if none). */
@@ -202,6 +219,15 @@ FCLSH_API const char *fclsh_last_error(void);
 FCLSH_API fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r,
                               int32_t *t, int32_t *r_part, int64_t *n,
                               int32_t *L, int32_t *dir_bits, int32_t *group_bits);
+
+/* Device memory held by an index, in bytes (any output pointer may be NULL):
+ * *index_bytes = what answering queries needs (the point copy, the tables,
+ * the directory and the hash parameters); *build_scratch_bytes = the table
+ * build's scratch, held only when the index keeps it (keep_build_scratch, or
+ * after a rebuild); *workspace_bytes = the query workspaces of every stream
+ * that has queried the index, and of its live graphs.  Host only. */
+FCLSH_API fclsh_status fclsh_index_memory(fclsh_index idx, uint64_t *index_bytes,
+                                          uint64_t *build_scratch_bytes, uint64_t *workspace_bytes);
 
 /* The parameters an index was built with (host arrays of d' entries: d
  * times the replication, see fclsh_derive_params). */
@@ -273,6 +299,18 @@ FCLSH_API fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d
                                     int64_t nq, void *stream,
                                     uint64_t *d_collisions);
 
+/* Both cost measures of Sec. 4.1 per query (device uint64 outputs of nq
+ * entries): d_collisions[i] = #Collisions, the summed sizes of query i's L
+ * buckets (what C_lookup is proportional to); d_candidates[i] = #Candidates,
+ * the number of distinct points among them (what C_check is proportional
+ * to).  Duplicates are removed as the paper does, with an n-bit bitmap per
+ * query (queries are processed in chunks whose bitmaps fit 256 MB).  A
+ * diagnostic pass next to fclsh_query_batch, which needs neither counter.
+ * Allocates the bitmaps; synchronises `stream`.  Errors: FCLSH_EINVAL,
+ * FCLSH_ENOMEM, FCLSH_EDEVICE. */
+FCLSH_API fclsh_status fclsh_query_cost(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                        void *stream, uint64_t *d_collisions, uint64_t *d_candidates);
+
 /* The plain path: one query at a time, each answered by its own launch
  * sequence (hash, lookup and verify, compaction) and a synchronisation; the
  * baseline the batched path is measured against.  Same outputs and errors as
@@ -333,8 +371,11 @@ FCLSH_API fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *
 /* Captures fclsh_query_batch_async with these fixed buffers into a HIP graph
  * on `stream` (which must not be the null stream) and instantiates it.
  * Replaying it (fclsh_graph_launch) answers whatever queries d_queries holds
- * at that time.  The stream's workspace must be reserved first and must not
- * be re-reserved while the graph is alive. */
+ * at that time.  The stream's workspace must be reserved first (for at least
+ * nq queries); the graph gets a private copy of that workspace of the same
+ * capacities, so later calls on the stream (which may grow its workspace)
+ * never touch the graph's buffers.  The graph keeps the index alive (see
+ * fclsh_index_free).  Allocates; synchronises `stream`. */
 FCLSH_API fclsh_status fclsh_query_graph_create(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
                                                 int32_t r_query, const int32_t *d_radii, uint64_t *d_offsets,
                                                 uint32_t *d_ids, int64_t ids_capacity, uint64_t *d_result,

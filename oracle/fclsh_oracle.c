@@ -135,7 +135,7 @@ int orc_derive_params(int d, int r, uint64_t seed, int override_t, uint64_t P,
     if (rp + 1 > 20)
         return -1;
     int32_t D = 1 << (rp + 1);
-    /* Sec. 3.2 variant: the map m takes values in the columns other than
+    /* Sec. 3.3 variant: the map m takes values in the columns other than
      * column 0, so there are D - 1 of them, numbered from 1 */
     int32_t ncol = skip_col0 ? D - 1 : D;
     int32_t first = skip_col0 ? 1 : 0;

@@ -35,7 +35,7 @@ EXPORTS = [
     "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async", "fclsh_query_graph_create",
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
     "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
-    "fclsh_preprocessing",
+    "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -51,9 +51,17 @@ class FclshError(RuntimeError):
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("partitions", ctypes.c_int32), ("replicate", ctypes.c_int32),
+    """fclsh_build_opts; struct_size is filled in by make()."""
+    _fields_ = [("struct_size", ctypes.c_uint32), ("partitions", ctypes.c_int32),
+                ("replicate", ctypes.c_int32), ("exclude_column0", ctypes.c_int32),
                 ("prime", ctypes.c_uint64), ("mem_budget_bytes", ctypes.c_uint64),
-                ("exclude_column0", ctypes.c_int32)]
+                ("keep_build_scratch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, partitions=0, replicate=0, exclude_column0=False, mem_budget_bytes=0,
+             keep_build_scratch=False):
+        return cls(ctypes.sizeof(cls), partitions, replicate, int(bool(exclude_column0)), 0,
+                   mem_budget_bytes, int(bool(keep_build_scratch)), 0)
 
 
 _lib = None
@@ -76,6 +84,7 @@ def lib():
             "fclsh_query_batch": [vp, vp, i64, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_plain": [vp, vp, i64, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_index_info": [vp, P(i32), P(i32), P(i32), P(i32), P(i64), P(i32), P(i32), P(i32)],
+            "fclsh_index_memory": [vp, P(u64), P(u64), P(u64)],
             "fclsh_index_params": [vp, vp, vp, vp],
             "fclsh_hash": [vp, vp, i64, vp, vp],
             "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
@@ -85,6 +94,7 @@ def lib():
             "fclsh_index_build_mode": [vp, P(i32)],
             "fclsh_preprocessing": [i64, i32, ctypes.c_double, P(i32), P(i32)],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
+            "fclsh_query_cost": [vp, vp, i64, vp, vp, vp],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_batch_finish": [vp, vp, vp, vp, i64, P(i64)],
             "fclsh_query_reserve": [vp, i64, i64, i64, vp],
@@ -135,7 +145,7 @@ def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int
     b = np.zeros(dd, np.uint64)
     t = ctypes.c_int32()
     rp = ctypes.c_int32()
-    opts = BuildOpts(partitions, replicate, 0, 0, int(bool(exclude_column0)))
+    opts = BuildOpts.make(partitions, replicate, exclude_column0)
     _check(lib().fclsh_derive_params(d, r, seed & (2**64 - 1), ctypes.byref(opts), ctypes.byref(t),
                                      ctypes.byref(rp), part.ctypes.data, col.ctypes.data, b.ctypes.data))
     return {"t": t.value, "r_part": rp.value, "part": part, "col": col, "b": b}
@@ -176,14 +186,14 @@ class Index:
 
     def __init__(self, points, d: int, r: int, seed: int = 0, partitions: int = 0,
                  mem_budget_bytes: int = 0, stream=None, *, replicate: int = 0,
-                 exclude_column0: bool = False, _params=None):
+                 exclude_column0: bool = False, keep_build_scratch: bool = False, _params=None):
         torch = _torch()
         pts = _dev_words(points, d, "points")
         n = pts.shape[0]
         h = ctypes.c_void_p()
         st = _stream_ptr(stream)
         if _params is None:
-            opts = BuildOpts(partitions, replicate, 0, mem_budget_bytes, int(bool(exclude_column0)))
+            opts = BuildOpts.make(partitions, replicate, exclude_column0, mem_budget_bytes, keep_build_scratch)
             _check(lib().fclsh_build_index(ctypes.c_void_p(pts.data_ptr()), n, d, r, seed & (2**64 - 1),
                                            ctypes.byref(opts), st, ctypes.byref(h)))
         else:
@@ -225,6 +235,13 @@ class Index:
                                       ctypes.byref(gb)))
         return {"d": d.value, "r": r.value, "t": t.value, "r_part": rp.value, "n": n.value, "L": L.value,
                 "dir_bits": db.value, "group_bits": gb.value}
+
+    def memory(self) -> dict:
+        """fclsh_index_memory: device bytes of the index, its kept build
+        scratch and its query workspaces."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().fclsh_index_memory(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"index_bytes": a.value, "build_scratch_bytes": b.value, "workspace_bytes": c.value}
 
     def params(self) -> dict:
         d = self.d * self.replicate  # the family's coordinates
@@ -423,6 +440,17 @@ class Index:
         _check(lib().fclsh_query_collisions(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0],
                                             _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())))
         return out
+
+
+    def cost(self, queries, stream=None):
+        """Sec. 4.1's #Collisions and #Candidates per query: (int64 [nq], int64 [nq])."""
+        torch = _torch()
+        q = _dev_words(queries, self.d, "queries")
+        coll = torch.empty(q.shape[0], dtype=torch.int64, device=q.device)
+        cand = torch.empty_like(coll)
+        _check(lib().fclsh_query_cost(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0], _stream_ptr(stream),
+                                      ctypes.c_void_p(coll.data_ptr()), ctypes.c_void_p(cand.data_ptr())))
+        return coll, cand
 
 
 class QueryGraph:

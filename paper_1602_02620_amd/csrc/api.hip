@@ -2,6 +2,7 @@
 // index object and its device memory, per-stream query workspaces.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -10,17 +11,6 @@
 
 namespace fclsh {
 
-
-fclsh_status Scratch::get(void **p, size_t bytes, const char *what) {
-    void *q = nullptr;
-    if (hipMalloc(&q, bytes ? bytes : 1) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(FCLSH_ENOMEM, "scratch allocation of %zu bytes for %s failed", bytes, what);
-    }
-    ptrs.push_back(q);
-    *p = q;
-    return FCLSH_OK;
-}
 
 fclsh_status dev_alloc(Index *ix, void **p, size_t bytes, const char *what) {
     void *q = nullptr;
@@ -63,16 +53,26 @@ struct IndexHandle {
     Index ix;
     std::mutex mu;
     std::map<hipStream_t, QueryWorkspace *> ws;
-    uint32_t *keys = nullptr;  // build scratch, kept for rebuilds
+    // build scratch (hash keys, two partition buffers, histograms), held
+    // between builds only when the index keeps it (keep_build_scratch, or once
+    // it has been rebuilt)
+    uint32_t *keys = nullptr;
     uint32_t *tk = nullptr;
     uint32_t *tv = nullptr;
     uint32_t *aux = nullptr;
+    uint64_t scratch_bytes = 0;
+    bool keep_scratch = false;
     // pass 2's counters of the last build, copied to pinned host memory
     // behind an event (read before the next build chooses its pass-2 form)
     uint32_t *host_cnt = nullptr;
     hipEvent_t cnt_ev = nullptr;
     bool cnt_pending = false;
     BuildMode cnt_mode = BuildMode::kFull;  // form of the build the counters come from
+    // graphs captured on the index hold its buffers: fclsh_index_free only
+    // marks a handle with live graphs as released, and the last graph's free
+    // destroys it
+    int live_graphs = 0;
+    bool released = false;
     QueryWorkspace *workspace(hipStream_t st) {
         std::lock_guard<std::mutex> g(mu);
         auto it = ws.find(st);
@@ -82,6 +82,50 @@ struct IndexHandle {
         return w;
     }
 };
+
+static void free_build_scratch(IndexHandle *h) {
+    for (uint32_t **p : {&h->keys, &h->tk, &h->tv, &h->aux}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    h->scratch_bytes = 0;
+}
+
+// All four scratch buffers or none.
+static fclsh_status alloc_build_scratch(IndexHandle *h) {
+    if (h->keys) return FCLSH_OK;
+    const Index &ix = h->ix;
+    const size_t entries = size_t(ix.prm.L()) * size_t(ix.n);
+    const size_t aux = table_build_scratch_bytes(ix.prm.L(), ix.n, ix.dir_bits);
+    struct {
+        uint32_t **p;
+        size_t bytes;
+    } want[] = {{&h->keys, entries * 4}, {&h->tk, entries * 4}, {&h->tv, entries * 4}, {&h->aux, aux}};
+    for (auto &w : want) {
+        if (hipMalloc(reinterpret_cast<void **>(w.p), std::max<size_t>(w.bytes, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            *w.p = nullptr;
+            free_build_scratch(h);
+            return fail(FCLSH_ENOMEM, "device allocation of %zu bytes of build scratch failed", w.bytes);
+        }
+        h->scratch_bytes += w.bytes;
+    }
+    return FCLSH_OK;
+}
+
+static void destroy_handle(IndexHandle *h) {
+    for (auto &kv : h->ws) {
+        ws_release(*kv.second);
+        delete kv.second;
+    }
+    h->ws.clear();
+    if (h->cnt_ev) (void)hipEventSynchronize(h->cnt_ev);
+    if (h->cnt_ev) (void)hipEventDestroy(h->cnt_ev);
+    if (h->host_cnt) (void)hipHostFree(h->host_cnt);
+    free_build_scratch(h);
+    dev_free_all(&h->ix);
+    delete h;
+}
 
 static void lookup_tuning(Index &ix);
 
@@ -127,13 +171,6 @@ static fclsh_status take_build_counts(IndexHandle *h) {
 static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *marks = nullptr, bool sync = true) {
     Index &ix = h->ix;
     const int64_t L = ix.prm.L();
-    if (!h->keys) {
-        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->keys), size_t(L * ix.n) * 4, "build keys"));
-        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->tk), size_t(L * ix.n) * 4, "sort buffer"));
-        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->tv), size_t(L * ix.n) * 4, "sort buffer"));
-        FCLSH_TRY(dev_alloc(&ix, reinterpret_cast<void **>(&h->aux), table_build_scratch_bytes(L, ix.n, ix.dir_bits),
-                            "table histograms"));
-    }
     if (!h->host_cnt &&
         hipHostMalloc(reinterpret_cast<void **>(&h->host_cnt), 2 * sizeof(uint32_t), hipHostMallocDefault) !=
             hipSuccess) {
@@ -145,6 +182,7 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
         return fail(FCLSH_EDEVICE, "hipEventCreate failed");
     }
     FCLSH_TRY(take_build_counts(h));
+    FCLSH_TRY(alloc_build_scratch(h));
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
     FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
@@ -158,12 +196,13 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
     if (sync) {
         FCLSH_HIP(hipStreamSynchronize(st));
         FCLSH_TRY(take_build_counts(h));
+        if (!h->keep_scratch) free_build_scratch(h);
     }
     return FCLSH_OK;
 }
 
 static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&prm, uint64_t budget,
-                                 hipStream_t st, fclsh_index *out) {
+                                 bool keep_scratch, hipStream_t st, fclsh_index *out) {
     if (!out) return fail(FCLSH_EINVAL, "out is null");
     *out = nullptr;
     if (!d_points) return fail(FCLSH_EINVAL, "d_points is null");
@@ -185,9 +224,9 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
         (void)hipGetLastError();
     }
     lookup_tuning(ix);
+    h->keep_scratch = keep_scratch;
     auto bail = [&](fclsh_status s) {
-        dev_free_all(&ix);
-        delete h;
+        destroy_handle(h);
         return s;
     };
     if (budget) {
@@ -283,7 +322,29 @@ struct DeviceBuffers {
 struct GraphHandle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    IndexHandle *owner = nullptr;
+    QueryWorkspace ws;  // private: no later call on a stream can regrow it
 };
+
+// The caller's options, read up to its struct_size; fields past it keep
+// their defaults (zero).
+static fclsh_status read_opts(const fclsh_build_opts *in, fclsh_build_opts *out) {
+    *out = fclsh_build_opts{};
+    out->struct_size = sizeof(fclsh_build_opts);
+    if (!in) return FCLSH_OK;
+    if (in->struct_size < sizeof(uint32_t) || in->struct_size > sizeof(fclsh_build_opts))
+        return fail(FCLSH_EINVAL, "opts->struct_size %u outside [4, %zu]", in->struct_size, sizeof(fclsh_build_opts));
+    std::memcpy(reinterpret_cast<char *>(out) + sizeof(uint32_t), reinterpret_cast<const char *>(in) + sizeof(uint32_t),
+                in->struct_size - sizeof(uint32_t));
+    out->struct_size = sizeof(fclsh_build_opts);
+    if (out->reserved != 0) return fail(FCLSH_EINVAL, "opts->reserved must be 0");
+    return FCLSH_OK;
+}
+
+// A handle a call may use: not null and not released.
+static bool usable(fclsh_index idx) {
+    return idx && !reinterpret_cast<IndexHandle *>(idx)->released;
+}
 
 }  // namespace fclsh
 
@@ -308,8 +369,10 @@ fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed, const fcls
                                  int32_t *t_out, int32_t *r_part_out, int32_t *part, int32_t *col, uint64_t *b) {
     if (!t_out || !r_part_out || !part || !col || !b) return fail(FCLSH_EINVAL, "null output pointer");
     if (d > kMaxDims) return fail(FCLSH_EUNSUPPORTED, "d=%d exceeds %d", d, kMaxDims);
+    fclsh_build_opts o;
+    FCLSH_TRY(read_opts(opts, &o));
     Params p;
-    FCLSH_TRY(derive_params(d, r, seed, opts, &p));
+    FCLSH_TRY(derive_params(d, r, seed, &o, &p));
     *t_out = p.t;
     *r_part_out = p.rp;
     for (int c = 0; c < p.dd(); ++c) {
@@ -324,9 +387,11 @@ fclsh_status fclsh_build_index(const uint64_t *d_points, int64_t n, int32_t d, i
                                const fclsh_build_opts *opts, void *stream, fclsh_index *out) {
     if (out) *out = nullptr;
     if (d > kMaxDims) return fail(FCLSH_EUNSUPPORTED, "d=%d exceeds %d", d, kMaxDims);
+    fclsh_build_opts o;
+    FCLSH_TRY(read_opts(opts, &o));
     Params p;
-    FCLSH_TRY(derive_params(d, r, seed, opts, &p));
-    return build_common(d_points, n, std::move(p), opts ? opts->mem_budget_bytes : 0,
+    FCLSH_TRY(derive_params(d, r, seed, &o, &p));
+    return build_common(d_points, n, std::move(p), o.mem_budget_bytes, o.keep_build_scratch != 0,
                         reinterpret_cast<hipStream_t>(stream), out);
 }
 
@@ -345,26 +410,47 @@ fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, int64_t n, 
     p.part.assign(part, part + d);
     p.col.assign(col, col + d);
     p.b.assign(b, b + d);
-    return build_common(d_points, n, std::move(p), 0, reinterpret_cast<hipStream_t>(stream), out);
+    return build_common(d_points, n, std::move(p), 0, false, reinterpret_cast<hipStream_t>(stream), out);
 }
 
 void fclsh_index_free(fclsh_index idx) {
     if (!idx) return;
     IndexHandle *h = handle(idx);
-    for (auto &kv : h->ws) {
-        ws_release(*kv.second);
-        delete kv.second;
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        if (h->released) return;
+        h->released = true;
+        if (h->live_graphs > 0) {
+            // the graphs keep the tables, points and parameters; what only
+            // later calls would have used goes now
+            for (auto &kv : h->ws) {
+                ws_release(*kv.second);
+                delete kv.second;
+            }
+            h->ws.clear();
+            free_build_scratch(h);
+            return;
+        }
     }
-    if (h->cnt_ev) (void)hipEventSynchronize(h->cnt_ev);
-    if (h->cnt_ev) (void)hipEventDestroy(h->cnt_ev);
-    if (h->host_cnt) (void)hipHostFree(h->host_cnt);
-    dev_free_all(&h->ix);
-    delete h;
+    destroy_handle(h);
+}
+
+fclsh_status fclsh_index_memory(fclsh_index idx, uint64_t *index_bytes, uint64_t *build_scratch_bytes,
+                                uint64_t *workspace_bytes) {
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    IndexHandle *h = handle(idx);
+    std::lock_guard<std::mutex> g(h->mu);
+    uint64_t w = 0;
+    for (auto &kv : h->ws) w += ws_bytes(*kv.second);
+    if (index_bytes) *index_bytes = h->ix.bytes_owned;
+    if (build_scratch_bytes) *build_scratch_bytes = h->scratch_bytes;
+    if (workspace_bytes) *workspace_bytes = w;
+    return FCLSH_OK;
 }
 
 fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r, int32_t *t, int32_t *r_part, int64_t *n,
                               int32_t *L, int32_t *dir_bits, int32_t *group_bits) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     const Index &ix = handle(idx)->ix;
     if (d) *d = ix.prm.d;
     if (r) *r = ix.prm.r;
@@ -378,7 +464,7 @@ fclsh_status fclsh_index_info(fclsh_index idx, int32_t *d, int32_t *r, int32_t *
 }
 
 fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col, uint64_t *b) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     const Index &ix = handle(idx)->ix;
     for (int c = 0; c < ix.prm.dd(); ++c) {
         if (part) part[c] = ix.prm.part[c];
@@ -389,7 +475,7 @@ fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col, ui
 }
 
 fclsh_status fclsh_hash(fclsh_index idx, const uint64_t *d_pts, int64_t m, uint32_t *d_keys, void *stream) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (m < 0 || m > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "m=%lld out of range", (long long)m);
     if (m && (!d_pts || !d_keys)) return fail(FCLSH_EINVAL, "null buffer");
     return launch_hash(handle(idx)->ix, d_pts, m, d_keys, m, reinterpret_cast<hipStream_t>(stream));
@@ -397,7 +483,7 @@ fclsh_status fclsh_hash(fclsh_index idx, const uint64_t *d_pts, int64_t m, uint3
 
 fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const uint32_t **d_tids,
                                 const uint32_t **d_dir, const uint64_t **d_points) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     const Index &ix = handle(idx)->ix;
     if (d_tkeys) *d_tkeys = ix.tkeys;
     if (d_tids) *d_tids = ix.tids;
@@ -407,12 +493,13 @@ fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const
 }
 
 fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    handle(idx)->keep_scratch = true;  // rebuilds keep their scratch
     return hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream));
 }
 
 fclsh_status fclsh_index_build_mode(fclsh_index idx, int32_t *mode) {
-    if (!idx || !mode) return fail(FCLSH_EINVAL, "null argument");
+    if (!usable(idx) || !mode) return fail(FCLSH_EINVAL, "null argument or released index");
     IndexHandle *h = handle(idx);
     FCLSH_TRY(take_build_counts(h));
     *mode = int32_t(h->ix.build_mode);
@@ -420,12 +507,13 @@ fclsh_status fclsh_index_build_mode(fclsh_index idx, int32_t *mode) {
 }
 
 fclsh_status fclsh_index_rebuild_async(fclsh_index idx, void *stream) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    handle(idx)->keep_scratch = true;
     return hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream), nullptr, false);
 }
 
 fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *phase_ms, int32_t nphase) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!phase_ms || nphase < kRebuildPhases) return fail(FCLSH_EINVAL, "phase_ms needs %d entries", kRebuildPhases);
     hipEvent_t ev[kRebuildPhases + 1] = {};
     fclsh_status s = FCLSH_OK;
@@ -434,6 +522,7 @@ fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *pha
             s = fail(FCLSH_EDEVICE, "hipEventCreate failed");
             break;
         }
+    handle(idx)->keep_scratch = true;
     if (s == FCLSH_OK) s = hash_and_bucket(handle(idx), reinterpret_cast<hipStream_t>(stream), ev);
     for (int k = 0; s == FCLSH_OK && k < kRebuildPhases; ++k)
         if (hipEventElapsedTime(&phase_ms[k], ev[k], ev[k + 1]) != hipSuccess)
@@ -446,7 +535,7 @@ fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *pha
 fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                void *stream, uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                int64_t *total_out) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || nq > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "nq=%lld out of range", (long long)nq);
     if (nq && !d_queries) return fail(FCLSH_EINVAL, "null queries");
@@ -462,7 +551,7 @@ fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries, int64
 
 fclsh_status fclsh_query_batch_finish(fclsh_index idx, void *stream, const uint64_t *d_offsets, uint32_t *d_ids,
                                       int64_t ids_capacity, int64_t *total_out) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
     IndexHandle *h = handle(idx);
@@ -472,7 +561,7 @@ fclsh_status fclsh_query_batch_finish(fclsh_index idx, void *stream, const uint6
 
 fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries, int64_t nq, void *stream,
                                     uint64_t *d_collisions) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (nq < 0 || (nq && (!d_queries || !d_collisions))) return fail(FCLSH_EINVAL, "bad arguments");
     if (nq == 0) return FCLSH_OK;
     IndexHandle *h = handle(idx);
@@ -480,10 +569,21 @@ fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries, 
     return query_collisions(h->ix, *h->workspace(st), d_queries, nq, d_collisions, st);
 }
 
+fclsh_status fclsh_query_cost(fclsh_index idx, const uint64_t *d_queries, int64_t nq, void *stream,
+                              uint64_t *d_collisions, uint64_t *d_candidates) {
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    if (nq < 0 || nq > 0x7FFFFFFFll || (nq && (!d_queries || !d_collisions || !d_candidates)))
+        return fail(FCLSH_EINVAL, "bad arguments");
+    if (nq == 0) return FCLSH_OK;
+    IndexHandle *h = handle(idx);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return query_cost(h->ix, *h->workspace(st), d_queries, nq, d_collisions, d_candidates, st);
+}
+
 fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                void *stream, uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                int64_t *total_out) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
     IndexHandle *h = handle(idx);
@@ -499,7 +599,7 @@ fclsh_status fclsh_query_batch_radii(fclsh_index idx, const uint64_t *d_queries,
                                      const int32_t *d_radii, int32_t max_radius, void *stream,
                                      uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                      int64_t *total_out) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || nq > 0x7FFFFFFFll || (nq && (!d_queries || !d_radii))) return fail(FCLSH_EINVAL, "bad queries");
     if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
@@ -514,7 +614,7 @@ fclsh_status fclsh_query_batch_radii(fclsh_index idx, const uint64_t *d_queries,
 
 fclsh_status fclsh_query_reserve(fclsh_index idx, int64_t max_nq, int64_t pair_capacity,
                                  int64_t spill_capacity, void *stream) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (max_nq < 0 || pair_capacity < 1 || spill_capacity < 1) return fail(FCLSH_EINVAL, "bad capacities");
     IndexHandle *h = handle(idx);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -525,7 +625,7 @@ fclsh_status fclsh_query_reserve(fclsh_index idx, int64_t max_nq, int64_t pair_c
 fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                      const int32_t *d_radii, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
                                      int64_t ids_capacity, uint64_t *d_result) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
     if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
@@ -545,28 +645,47 @@ fclsh_status fclsh_query_graph_create(fclsh_index idx, const uint64_t *d_queries
                                       fclsh_graph *out) {
     if (!out) return fail(FCLSH_EINVAL, "null output pointer");
     *out = nullptr;
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (!stream) return fail(FCLSH_EINVAL, "graph capture needs a non-null stream");
-    auto *g = new GraphHandle();
+    if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
+    if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    IndexHandle *h = handle(idx);
+    if (r_query < 0) return fail(FCLSH_EINVAL, "negative query radius");
+    if (r_query > h->ix.prm.r)
+        return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", r_query, h->ix.prm.r);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    const QueryWorkspace &sws = *h->workspace(st);
+    if (nq * h->ix.prm.L() > sws.cap_items || nq + 1 > sws.cap_q || !sws.ctrl || !sws.pq || !sws.spill)
+        return fail(FCLSH_EINVAL, "query workspace of the stream not reserved for %lld queries", (long long)nq);
+    auto *g = new GraphHandle();
+    auto drop = [&](fclsh_status s) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        ws_release(g->ws);
         delete g;
-        return fail(FCLSH_EDEVICE, "hipStreamBeginCapture failed");
+        return s;
+    };
+    FCLSH_HIP(hipStreamSynchronize(st));
+    fclsh_status s = ws_reserve(g->ws, std::max<int64_t>(nq, sws.cap_q - 1), h->ix.prm.L(), sws.cap_pairs,
+                                sws.cap_spill);
+    if (s != FCLSH_OK) return drop(s);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return drop(fail(FCLSH_EDEVICE, "hipStreamBeginCapture failed"));
+    s = query_batch_async(h->ix, g->ws, d_queries, nq, r_query, d_radii, st, d_offsets, d_ids, ids_capacity);
+    if (s == FCLSH_OK) s = publish_result(g->ws, d_result, st);
+    const hipError_t e = hipStreamEndCapture(st, &g->graph);
+    if (s != FCLSH_OK) return drop(s);
+    if (e != hipSuccess) return drop(fail(FCLSH_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e)));
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        g->exec = nullptr;
+        return drop(fail(FCLSH_EDEVICE, "hipGraphInstantiate failed"));
     }
-    fclsh_status s = fclsh_query_batch_async(idx, d_queries, nq, r_query, d_radii, stream, d_offsets, d_ids,
-                                             ids_capacity, d_result);
-    hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(st, &graph);
-    if (s != FCLSH_OK || e != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        delete g;
-        return s != FCLSH_OK ? s : fail(FCLSH_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        ++h->live_graphs;
     }
-    g->graph = graph;
-    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        delete g;
-        return fail(FCLSH_EDEVICE, "hipGraphInstantiate failed");
-    }
+    g->owner = h;
     *out = reinterpret_cast<fclsh_graph>(g);
     return FCLSH_OK;
 }
@@ -582,11 +701,20 @@ void fclsh_graph_free(fclsh_graph graph) {
     auto *g = reinterpret_cast<GraphHandle *>(graph);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
+    ws_release(g->ws);  // hipFree waits for the device, so no replay is still running
+    IndexHandle *h = g->owner;
     delete g;
+    if (!h) return;
+    bool last = false;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        last = --h->live_graphs == 0 && h->released;
+    }
+    if (last) destroy_handle(h);
 }
 
 fclsh_status fclsh_index_set_tuning(fclsh_index idx, int32_t tile, int32_t blocks_per_cu) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (tile < 64 || tile > (1 << 20) || blocks_per_cu < 1 || blocks_per_cu > 64)
         return fail(FCLSH_EINVAL, "tile in [64, 2^20], blocks per CU in [1, 64]");
     handle(idx)->ix.tuning = QueryTuning{tile, blocks_per_cu};
@@ -594,7 +722,7 @@ fclsh_status fclsh_index_set_tuning(fclsh_index idx, int32_t tile, int32_t block
 }
 
 fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, int32_t *blocks_per_cu) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (tile) *tile = handle(idx)->ix.tuning.tile;
     if (blocks_per_cu) *blocks_per_cu = handle(idx)->ix.tuning.blocks_per_cu;
     return FCLSH_OK;
@@ -602,7 +730,7 @@ fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, int32_t *blo
 
 fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                             void *stream, int32_t *tile_out, int32_t *blocks_out, float *best_ms_out) {
-    if (!idx) return fail(FCLSH_EINVAL, "null index");
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (nq < 1 || !d_queries) return fail(FCLSH_EINVAL, "autotuning needs a sample batch");
     IndexHandle *h = handle(idx);
     if (r_query < 0 || r_query > h->ix.prm.r) return fail(FCLSH_ERADIUS, "bad query radius");

@@ -118,39 +118,12 @@ struct Index {
 fclsh_status dev_alloc(Index *ix, void **p, size_t bytes, const char *what);
 void dev_free_all(Index *ix);
 
-// Scratch memory that lives for one call.
-struct Scratch {
-    std::vector<void *> ptrs;
-    ~Scratch() {
-        for (void *p : ptrs) (void)hipFree(p);
-    }
-    fclsh_status get(void **p, size_t bytes, const char *what);
-    template <class T>
-    fclsh_status get(T **p, size_t count, const char *what) {
-        return get(reinterpret_cast<void **>(p), count * sizeof(T), what);
-    }
-};
-
 // ----------------------------------------------------------------------------
 // Kernels (launchers)
 // ----------------------------------------------------------------------------
 fclsh_status build_hash_plan(Index *ix);
 fclsh_status launch_hash(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys,
                          int64_t key_stride, hipStream_t st);
-
-// Stable LSD radix sort of nseg equal-length segments of (key, value) pairs by
-// key bits [begin_bit, end_bit).  vals_in may be null: values are then the
-// element's index within its segment.  The result lands in keys_out/vals_out;
-// the two tmp buffers must hold nseg*len entries each.
-fclsh_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in,
-                              uint32_t *keys_out, uint32_t *vals_out, uint32_t *tmp_keys,
-                              uint32_t *tmp_vals, int64_t nseg, int64_t len, int begin_bit,
-                              int end_bit, Scratch &scr, hipStream_t st);
-
-// Exclusive scan of n uint64 values (in place allowed); *total (device,
-// optional) receives the sum.
-fclsh_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *total,
-                                Scratch &scr, hipStream_t st);
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) in turn.  The
 // streaming kernels map workgroup b of a 1-D grid (a multiple of kXcds) to
@@ -213,6 +186,8 @@ struct QueryWorkspace {
 
 fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills);
 void ws_release(QueryWorkspace &ws);
+// Device bytes the workspace holds.
+uint64_t ws_bytes(const QueryWorkspace &ws);
 fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                                const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids,
                                int64_t ids_cap);
@@ -225,6 +200,8 @@ fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
                          hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
 fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq,
                               uint64_t *coll, hipStream_t st);
+fclsh_status query_cost(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, uint64_t *coll,
+                        uint64_t *cand, hipStream_t st);
 // Exclusive scan of n uint64 (in place allowed) using caller-provided
 // partials (scan_partials_needed(n) entries): no allocation, graph-safe.
 int64_t scan_partials_needed(int64_t n);

@@ -124,7 +124,7 @@ fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts 
         return fail(FCLSH_EUNSUPPORTED, "per-part radius %d needs 2^%d columns (max %d)", rp, rp + 1,
                     1 << kMaxLogD);
     const int D = 1 << (rp + 1);
-    // Sec. 3.2 variant: column 0 (the all-zero column of every codeword) is
+    // Sec. 3.3 variant: column 0 (the all-zero column of every codeword) is
     // never a target, so the columns drawn from are 1..D-1
     const bool skip0 = opts && opts->exclude_column0;
     const int ncols = skip0 ? D - 1 : D, col0 = skip0 ? 1 : 0;

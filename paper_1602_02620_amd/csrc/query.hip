@@ -591,51 +591,77 @@ unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
     return unsigned(g);
 }
 
-template <class T>
-fclsh_status regrow(T **p, int64_t want, const char *what) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-    if (hipMalloc(reinterpret_cast<void **>(p), size_t(std::max<int64_t>(want, 1)) * sizeof(T)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(FCLSH_ENOMEM, "device allocation for %s failed", what);
-    }
-    return FCLSH_OK;
-}
-
 uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 1) : ~uint64_t(0); }
 
 }  // namespace
 
+// Grows the workspace to hold nq queries of L tables, `pairs` reported pairs
+// and `spills` spill chunks.  All-or-nothing: every buffer that must grow is
+// allocated first, and only when all of them succeed are the old ones
+// released and the new ones and their capacities installed.  A failed
+// allocation leaves the workspace exactly as it was (old buffers, old
+// capacities), so a later call never runs on a half-grown workspace.
 fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills) {
     ws.pending_nq = -1;  // buffers may be replaced: nothing pending survives
     const int64_t items = nq * L;
-    if (items > ws.cap_items || !ws.qkeys) {
-        FCLSH_TRY(regrow(&ws.qkeys, items, "query keys"));
-        FCLSH_TRY(regrow(&ws.rstart, items, "query ranges"));
-        FCLSH_TRY(regrow(&ws.rlen, items, "query ranges"));
-        FCLSH_TRY(regrow(&ws.rmatch, items, "query ranges"));
-        ws.cap_items = items;
+    struct Grow {
+        void **slot;
+        size_t bytes;
+        const char *what;
+    };
+    std::vector<Grow> grow;
+    auto want = [&](auto **slot, int64_t count, const char *what) {
+        grow.push_back({reinterpret_cast<void **>(slot),
+                        size_t(std::max<int64_t>(count, 1)) * sizeof(**slot), what});
+    };
+    const bool g_items = items > ws.cap_items || !ws.qkeys;
+    const bool g_q = nq + 1 > ws.cap_q || !ws.qcount;
+    const bool g_pairs = pairs > ws.cap_pairs || !ws.pq;
+    const bool g_spill = spills > ws.cap_spill || !ws.spill;
+    if (g_items) {
+        want(&ws.qkeys, items, "query keys");
+        want(&ws.rstart, items, "query ranges");
+        want(&ws.rlen, items, "query ranges");
+        want(&ws.rmatch, items, "query ranges");
     }
-    if (nq + 1 > ws.cap_q || !ws.qcount) {
-        FCLSH_TRY(regrow(&ws.qcount, nq + 1, "query counts"));
-        FCLSH_TRY(regrow(&ws.qfill, nq + 1, "query counts"));
-        FCLSH_TRY(regrow(&ws.qcount64, nq + 1, "query counts"));
-        FCLSH_TRY(regrow(&ws.scan_part, scan_partials_needed(nq + 1), "scan partials"));
-        ws.cap_q = nq + 1;
+    if (g_q) {
+        want(&ws.qcount, nq + 1, "query counts");
+        want(&ws.qfill, nq + 1, "query counts");
+        want(&ws.qcount64, nq + 1, "query counts");
+        want(&ws.scan_part, scan_partials_needed(nq + 1), "scan partials");
     }
-    if (!ws.ctrl) FCLSH_TRY(regrow(&ws.ctrl, 1, "query control"));
-    if (!ws.offs1) FCLSH_TRY(regrow(&ws.offs1, 2, "plain offsets"));
-    if (pairs > ws.cap_pairs || !ws.pq) {
-        FCLSH_TRY(regrow(&ws.pq, pairs, "result pairs"));
-        FCLSH_TRY(regrow(&ws.pid, pairs, "result pairs"));
-        FCLSH_TRY(regrow(&ws.sorttmp, pairs, "result sort"));
-        ws.cap_pairs = pairs;
+    if (!ws.ctrl) want(&ws.ctrl, 1, "query control");
+    if (!ws.offs1) want(&ws.offs1, 2, "plain offsets");
+    if (g_pairs) {
+        want(&ws.pq, pairs, "result pairs");
+        want(&ws.pid, pairs, "result pairs");
+        want(&ws.sorttmp, pairs, "result sort");
     }
-    if (spills > ws.cap_spill || !ws.spill) {
-        FCLSH_TRY(regrow(&ws.spill, spills, "spill queue"));
-        ws.cap_spill = spills;
+    if (g_spill) want(&ws.spill, spills, "spill queue");
+    std::vector<void *> fresh(grow.size(), nullptr);
+    for (size_t i = 0; i < grow.size(); ++i) {
+        if (hipMalloc(&fresh[i], grow[i].bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            for (size_t j = 0; j < i; ++j) (void)hipFree(fresh[j]);
+            return fail(FCLSH_ENOMEM, "device allocation of %zu bytes for %s failed", grow[i].bytes, grow[i].what);
+        }
     }
+    for (size_t i = 0; i < grow.size(); ++i) {
+        if (*grow[i].slot) (void)hipFree(*grow[i].slot);
+        *grow[i].slot = fresh[i];
+    }
+    if (g_items) ws.cap_items = items;
+    if (g_q) ws.cap_q = nq + 1;
+    if (g_pairs) ws.cap_pairs = pairs;
+    if (g_spill) ws.cap_spill = spills;
     return FCLSH_OK;
+}
+
+uint64_t ws_bytes(const QueryWorkspace &ws) {
+    if (!ws.ctrl) return 0;
+    return uint64_t(ws.cap_items) * 16 + uint64_t(ws.cap_q) * 16 +
+           uint64_t(scan_partials_needed(ws.cap_q)) * 8 + sizeof(QueryCtrl) + 16 + uint64_t(ws.cap_pairs) * 12 +
+           uint64_t(ws.cap_spill) * 16;
 }
 
 void ws_release(QueryWorkspace &ws) {
@@ -664,6 +690,103 @@ fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *que
                        coll);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
+}
+
+namespace {
+
+// Sec. 4.1's two cost measures per query, with the paper's own duplicate
+// elimination: an n-bit bitmap per query.  Every entry of the query's L
+// buckets is a collision; its id's bit is set with one atomic OR, and a bit
+// found clear is a new distinct candidate.  One wave per (query, table) item
+// (query-major, so a query's tables share its bitmap in cache); the lanes
+// stride over the item's directory bin and keep the entries whose key equals
+// the query's.  Wave totals go to the per-query counters with one atomic each.
+__global__ __launch_bounds__(256) void cost_kernel(const uint32_t *__restrict__ qkeys, int64_t qn, int L,
+                                                   const uint32_t *__restrict__ tkeys,
+                                                   const uint32_t *__restrict__ tids,
+                                                   const uint32_t *__restrict__ dir, int64_t n, int dir_bits,
+                                                   uint32_t *__restrict__ bitmap, int64_t bm_words,
+                                                   unsigned long long *__restrict__ coll,
+                                                   unsigned long long *__restrict__ cand) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nb = int64_t(1) << dir_bits;
+    const int64_t items = qn * L;
+    const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / 64);
+    for (int64_t it = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6); it < items; it += nwaves) {
+        const int64_t ql = it / L;
+        const int T = int(it - ql * L);
+        const uint32_t key = qkeys[int64_t(T) * qn + ql];
+        const uint32_t *dr = dir + int64_t(T) * (nb + 1);
+        const uint32_t bin = key >> (31 - dir_bits);
+        const uint32_t lo = dr[bin], hi = dr[bin + 1];
+        const uint32_t *tk = tkeys + int64_t(T) * n;
+        const uint32_t *ti = tids + int64_t(T) * n;
+        uint32_t *bm = bitmap + ql * bm_words;
+        uint32_t nc = 0, nd = 0;
+        for (uint32_t j = lo + uint32_t(lane); j < hi; j += 64) {
+            if (tk[j] != key) continue;
+            const uint32_t id = ti[j];
+            const uint32_t bit = 1u << (id & 31u);
+            ++nc;
+            nd += (atomicOr(&bm[id >> 5], bit) & bit) ? 0u : 1u;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            nc += uint32_t(__shfl_xor(int(nc), o, 64));
+            nd += uint32_t(__shfl_xor(int(nd), o, 64));
+        }
+        if (lane == 0 && nc) {
+            atomicAdd(&coll[ql], (unsigned long long)nc);
+            atomicAdd(&cand[ql], (unsigned long long)nd);
+        }
+    }
+}
+
+// Clears a chunk's bitmaps and counters (a kernel, not a memset).
+__global__ void cost_clear_kernel(uint32_t *__restrict__ bitmap, int64_t words, unsigned long long *__restrict__ coll,
+                                  unsigned long long *__restrict__ cand, int64_t qn) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < words; i += stride) bitmap[i] = 0u;
+    for (int64_t i = i0; i < qn; i += stride) {
+        coll[i] = 0ull;
+        cand[i] = 0ull;
+    }
+}
+
+}  // namespace
+
+// #Collisions and #Candidates of Sec. 4.1 for a batch, in chunks of queries
+// whose bitmaps fit a fixed budget.
+fclsh_status query_cost(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, uint64_t *coll,
+                        uint64_t *cand, hipStream_t st) {
+    const int L = ix.prm.L();
+    const int64_t bm_words = (ix.n + 31) / 32;
+    constexpr int64_t kBitmapBudget = int64_t(256) << 20;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kBitmapBudget / (bm_words * 4)));
+    FCLSH_TRY(ws_reserve(ws, chunk, L, std::max<int64_t>(ws.cap_pairs, 1), std::max<int64_t>(ws.cap_spill, 1)));
+    uint32_t *bitmap = nullptr;
+    if (hipMalloc(&bitmap, size_t(chunk * bm_words) * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FCLSH_ENOMEM, "device allocation of the candidate bitmaps failed");
+    }
+    fclsh_status s = FCLSH_OK;
+    for (int64_t q0 = 0; q0 < nq && s == FCLSH_OK; q0 += chunk) {
+        const int64_t qn = std::min(chunk, nq - q0);
+        auto *c0 = reinterpret_cast<unsigned long long *>(coll + q0);
+        auto *d0 = reinterpret_cast<unsigned long long *>(cand + q0);
+        hipLaunchKernelGGL(cost_clear_kernel, dim3(grid_for(qn * bm_words, 256, 4096)), dim3(256), 0, st, bitmap,
+                           qn * bm_words, c0, d0, qn);
+        s = launch_hash(ix, queries + q0 * ix.W, qn, ws.qkeys, qn, st);
+        if (s != FCLSH_OK) break;
+        hipLaunchKernelGGL(cost_kernel, dim3(grid_for(qn * L, 4, 1u << 16)), dim3(256), 0, st, ws.qkeys, qn, L,
+                           ix.tkeys, ix.tids, ix.dir, ix.n, ix.dir_bits, bitmap, bm_words, c0, d0);
+        if (hipGetLastError() != hipSuccess) s = fail(FCLSH_EDEVICE, "cost kernel launch failed");
+    }
+    const hipError_t e = hipStreamSynchronize(st);
+    (void)hipFree(bitmap);
+    if (s == FCLSH_OK && e != hipSuccess)
+        s = fail(FCLSH_EDEVICE, "query cost counters failed: %s", hipGetErrorString(e));
+    return s;
 }
 
 // The batched pipeline, entirely on the stream: no allocation, no host

@@ -7,10 +7,6 @@ import numpy as np
 import oracle
 
 
-def oracle_params_for(idx_params: dict, d: int, r: int, t: int, rp: int) -> oracle.Params:
-    return oracle.explicit_params(d, rp, idx_params["part"], idx_params["col"], idx_params["b"], r=r)
-
-
 def oracle_derive(d, r, seed, t=0):
     return oracle.derive_params(d, r, seed, override_t=t)
 

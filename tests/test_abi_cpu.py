@@ -88,7 +88,7 @@ def test_preprocessing_errors(n, r, c):
 @pytest.mark.parametrize("d,r,t,times", [(64, 4, 0, 0), (31, 4, 0, 0), (32, 4, 0, 0), (100, 6, 0, 0),
                                          (128, 10, 0, 0), (96, 12, 3, 0), (40, 2, 0, 2)])
 def test_exclude_column0_params_match_oracle(d, r, t, times):
-    # the Sec. 3.2 variant: library and oracle draw the same columns from 1..D-1
+    # the Sec. 3.3 variant: library and oracle draw the same columns from 1..D-1
     p = fc.derive_params(d, r, 77, partitions=t, replicate=times, exclude_column0=True)
     k = max(1, times)
     o = oracle.derive_params(k * d, k * r, 77, override_t=t if times == 0 else 1, exclude_column0=True)
@@ -125,3 +125,52 @@ def test_param_errors(d, r, t, status):
 def test_largest_supported_family():
     p = fc.derive_params(64, 11, 1, partitions=1)  # r' = 11: D = 4096 columns
     assert p["r_part"] == 11 and int(p["col"].max()) < 4096
+
+
+def _derive_with(opts):
+    d = 300
+    part = np.zeros(d, np.int32)
+    col = np.zeros(d, np.int32)
+    b = np.zeros(d, np.uint64)
+    t, rp = fc.ctypes.c_int32(), fc.ctypes.c_int32()
+    st = fc.lib().fclsh_derive_params(d, 9, 8, fc.ctypes.byref(opts), fc.ctypes.byref(t), fc.ctypes.byref(rp),
+                                      part.ctypes.data, col.ctypes.data, b.ctypes.data)
+    return st, t.value
+
+
+def test_build_opts_struct_size():
+    # a full struct reads every field: partitions = 3 takes effect
+    st, t = _derive_with(fc.BuildOpts.make(partitions=3))
+    assert st == fc.FCLSH_OK and t == 3
+    # a caller built against a struct that ends before `partitions` gets the
+    # default for it (t = 1 at r = 9), whatever lies past its size
+    o = fc.BuildOpts.make(partitions=3)
+    o.struct_size = 4
+    st, t = _derive_with(o)
+    assert st == fc.FCLSH_OK and t == 1
+    # size 0 or larger than the library's struct is refused
+    for bad in (0, fc.ctypes.sizeof(fc.BuildOpts) + 8):
+        o = fc.BuildOpts.make()
+        o.struct_size = bad
+        st, _ = _derive_with(o)
+        assert st == fc.FCLSH_EINVAL
+    o = fc.BuildOpts.make()
+    o.reserved = 1
+    assert _derive_with(o)[0] == fc.FCLSH_EINVAL
+
+
+def test_header_struct_layout_matches_binding():
+    # the C compiler's layout of fclsh_build_opts equals the binding's
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"fclsh.h\"\n"
+           "int main(void){printf(\"%zu\", sizeof(fclsh_build_opts));"
+           + "".join(f"printf(\" %zu\", offsetof(fclsh_build_opts, {f}));" for f, _ in fc.BuildOpts._fields_)
+           + "return 0;}\n")
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        c = os.path.join(tmp, "layout.c")
+        exe = os.path.join(tmp, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    want = [fc.ctypes.sizeof(fc.BuildOpts)] + [getattr(fc.BuildOpts, f).offset for f, _ in fc.BuildOpts._fields_]
+    assert [int(x) for x in out] == want

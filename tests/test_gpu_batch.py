@@ -226,3 +226,77 @@ def test_autotune_with_heavy_buckets():
     assert res["ms"] > 0 and idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"]}
     assert_same_lists(csr_lists(*idx.query(dev(qs), 4)), want)
     idx.close()
+
+
+def test_graph_owns_its_workspace_and_keeps_the_index():
+    """A captured graph keeps its own workspace: a larger batch on the same
+    stream (which grows the stream's workspace) does not disturb its replays.
+    Releasing the index while the graph lives leaves the graph working and
+    makes later calls on the index fail; the graph's free releases it."""
+    w = synth.small(0.3)
+    r = w.r
+    _say(f"[graph] n={w.n} d={w.d} r={r}")
+    idx = fc.Index(dev(w.points), w.d, r, seed=5)
+    nq = 8
+    stream = torch.cuda.Stream()
+    qbuf = torch.empty((nq, fc.words(w.d)), dtype=torch.int64, device="cuda")
+    offsets = torch.zeros(nq + 1, dtype=torch.int64, device="cuda")
+    ids = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    result = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with torch.cuda.stream(stream):
+        idx.reserve(nq, pair_capacity=1 << 12, spill_capacity=1 << 10, stream=stream)
+        qbuf.copy_(dev(w.queries[:nq]))
+        g = idx.query_graph(qbuf, r, offsets, ids, result, stream=stream)
+    stream.synchronize()
+    before = idx.memory()["workspace_bytes"]
+    # a much larger batch on the same stream grows the stream's workspace
+    big = np.concatenate([w.queries] * 8)
+    with torch.cuda.stream(stream):
+        idx.query(dev(big), r, stream=stream)
+    stream.synchronize()
+    assert idx.memory()["workspace_bytes"] > before
+    want = oracle.brute_force(w.points, w.d, w.queries[:nq], r).ids
+    for rep in range(2):
+        with torch.cuda.stream(stream):
+            ids.fill_(-1)
+            g.launch(stream=stream)
+        stream.synchronize()
+        assert int(result[1]) == 0
+        assert_same_lists(csr_lists(offsets, ids[:int(result[0])]), want)
+    raw = fc.ctypes.c_void_p(idx._h.value)
+    idx.close()  # the graph still holds the tables
+    # the released handle refuses calls (it stays allocated while the graph lives)
+    L = fc.ctypes.c_int32()
+    st = fc.lib().fclsh_index_info(raw, None, None, None, None, None, fc.ctypes.byref(L), None, None)
+    assert st == fc.FCLSH_EINVAL
+    with torch.cuda.stream(stream):
+        qbuf.copy_(dev(w.queries[nq:2 * nq]))
+        ids.fill_(-1)
+        g.launch(stream=stream)
+    stream.synchronize()
+    want = oracle.brute_force(w.points, w.d, w.queries[nq:2 * nq], r).ids
+    assert_same_lists(csr_lists(offsets, ids[:int(result[0])]), want)
+    g.close()
+
+
+def test_index_memory_report():
+    """Resident bytes of a served index: the point copy, the tables and the
+    directory (plus a few KB of hash parameters); the build scratch is gone
+    after the build unless it was asked to stay, and a rebuild keeps it."""
+    w = synth.small(0.5)
+    _say(f"[memory] n={w.n} d={w.d} r={w.r}")
+    idx = fc.Index(dev(w.points), w.d, w.r, seed=6)
+    inf = idx.info
+    L, n = inf["L"], inf["n"]
+    tables = 2 * 4 * L * n
+    points = 8 * fc.words(w.d) * n
+    directory = 4 * L * ((1 << inf["dir_bits"]) + 1)
+    m = idx.memory()
+    assert m["build_scratch_bytes"] == 0
+    assert tables + points + directory <= m["index_bytes"] <= tables + points + directory + (1 << 20)
+    idx.rebuild()
+    assert idx.memory()["build_scratch_bytes"] >= 3 * 4 * L * n
+    idx.close()
+    kept = fc.Index(dev(w.points), w.d, w.r, seed=6, keep_build_scratch=True)
+    assert kept.memory()["build_scratch_bytes"] >= 3 * 4 * L * n
+    kept.close()

@@ -116,6 +116,17 @@ def test_collisions_counter(case):
     assert np.array_equal(got, s2.collisions)
 
 
+def test_cost_counters(case):
+    # Sec. 4.1's #Collisions and #Candidates (bitmap dedupe on the GPU) equal
+    # the oracle's Strategy-2 counters
+    name, w, idx, orc = case
+    s2 = orc.strategy2(w.queries, w.r)
+    coll, cand = (x.cpu().numpy() for x in idx.cost(dev(w.queries)))
+    assert np.array_equal(coll, s2.collisions)
+    assert np.array_equal(cand, s2.candidates)
+    assert np.all(cand <= coll) and np.all(cand >= np.array([len(x) for x in s2.ids]))
+
+
 def test_smaller_radii(case):
     name, w, idx, orc = case
     for rq in sorted({0, 1, w.r // 2, w.r - 1}):
@@ -477,7 +488,7 @@ def test_replication(d, r, times):
 @pytest.mark.parametrize("d,r,t", [(31, 4, 0), (64, 4, 0), (100, 6, 0), (128, 10, 0)],
                          ids=["specific-boundary", "general", "specific", "two-parts"])
 def test_exclude_column0(d, r, t):
-    """The Sec. 3.2 variant whose map avoids column 0: the parameters, keys
+    """The Sec. 3.3 variant whose map avoids column 0: the parameters, keys
     and tables equal the oracle's for the same draw, and the answers equal
     the linear scan."""
     seed = 3300 + d + r

@@ -345,7 +345,7 @@ def test_preprocessing_special_cases():
 
 
 # --------------------------------------------------------------------------
-# Sec. 3.2 variant: the coordinate map never targets column 0
+# Sec. 3.3 variant: the coordinate map never targets column 0
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("d,r,t,seed", [(6, 2, 0, 1), (7, 2, 0, 2), (8, 2, 0, 3), (12, 2, 0, 4),
@@ -373,7 +373,7 @@ def test_exclude_column0_expected_collisions():
     # difference of k coordinates iff all k columns are orthogonal to v.  Of
     # the D - 1 columns other than 0, D/2 - 1 are, so the expected number of
     # colliding rows is (D-1) ((D/2-1)/(D-1))^k, below the bound 2^(r+1-k) of
-    # Sec. 3.2 and below (D-1)/2^k, the value when column 0 may be drawn.
+    # Sec. 3.3 and below (D-1)/2^k, the value when column 0 may be drawn.
     rng = np.random.default_rng(23)
     d, r = 24, 2
     D = 2 ** (r + 1)
