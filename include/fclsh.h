@@ -368,6 +368,28 @@ FCLSH_API fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *
                                                uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                                uint64_t *d_result);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fclsh_query_batch_async with the same arguments, outputs and status bits,
+ * but its workspace (query keys, per-query counters, scan partials, control
+ * block, spill queue, result pairs) is laid out in one fixed array of 64 MiB
+ * that the library holds in static device memory on each GPU it runs on,
+ * until the process ends.  The call allocates and frees nothing.  The query
+ * keys and per-query counters take 4*L + 16 bytes per query (plus alignment);
+ * a quarter of the rest holds spill chunks (16 B each) and the remainder
+ * result pairs (12 B each).  A batch whose fixed part does not fit is
+ * rejected with FCLSH_ENOMEM before anything is enqueued; one whose pairs or
+ * spill chunks overflow what is left reports it in d_result's status bits
+ * (1 pairs, 2 spill), as fclsh_query_batch_async does.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents (the
+ * counters are cleared by the call's own kernels): calls whose work overlaps
+ * on one GPU, on any streams, race and must be serialised by the caller.
+ * The first call on a device looks up the array's address there. */
+FCLSH_API fclsh_status fclsh_query_batch_noalloc(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
+                                                 int32_t r_query, const int32_t *d_radii, void *stream,
+                                                 uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
+                                                 uint64_t *d_result);
+
 /* Captures fclsh_query_batch_async with these fixed buffers into a HIP graph
  * on `stream` (which must not be the null stream) and instantiates it.
  * Replaying it (fclsh_graph_launch) answers whatever queries d_queries holds

@@ -36,6 +36,7 @@ EXPORTS = [
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
     "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
     "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
+    "fclsh_query_batch_noalloc",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -99,6 +100,7 @@ def lib():
             "fclsh_query_batch_finish": [vp, vp, vp, vp, i64, P(i64)],
             "fclsh_query_reserve": [vp, i64, i64, i64, vp],
             "fclsh_query_batch_async": [vp, vp, i64, i32, vp, vp, vp, vp, i64, vp],
+            "fclsh_query_batch_noalloc": [vp, vp, i64, i32, vp, vp, vp, vp, i64, vp],
             "fclsh_query_graph_create": [vp, vp, i64, i32, vp, vp, vp, i64, vp, vp, P(vp)],
             "fclsh_graph_launch": [vp, vp],
             "fclsh_index_set_tuning": [vp, i32, i32],

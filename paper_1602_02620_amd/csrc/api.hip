@@ -319,6 +319,37 @@ struct DeviceBuffers {
     }
 };
 
+// Workspace of fclsh_query_batch_noalloc: one array per GPU, in the code
+// object's static device memory, so that the call itself allocates nothing.
+// In host code `scratch` only names the symbol; its address on a device comes
+// from hipGetSymbolAddress with that device current, looked up once per device
+// and kept in g_scratch_addr.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_addr;
+
+static fclsh_status scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return FCLSH_OK;
+    }
+    int cur = -1;
+    FCLSH_HIP(hipGetDevice(&cur));
+    if (cur != device) FCLSH_HIP(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+        return fail(FCLSH_EDEVICE, "hipGetSymbolAddress of the no-allocation scratch failed: %s",
+                    hipGetErrorString(e));
+    g_scratch_addr[device] = p;
+    *out = p;
+    return FCLSH_OK;
+}
+
 struct GraphHandle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -635,6 +666,26 @@ fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *d_queries,
         return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", r_query, h->ix.prm.r);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     QueryWorkspace &ws = *h->workspace(st);
+    FCLSH_TRY(query_batch_async(h->ix, ws, d_queries, nq, r_query, d_radii, st, d_offsets, d_ids, ids_capacity));
+    return publish_result(ws, d_result, st);
+}
+
+fclsh_status fclsh_query_batch_noalloc(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
+                                       const int32_t *d_radii, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
+                                       int64_t ids_capacity, uint64_t *d_result) {
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
+    if (nq < 0 || nq > 0x7FFFFFFFll || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    IndexHandle *h = handle(idx);
+    if (r_query < 0) return fail(FCLSH_EINVAL, "negative query radius");
+    if (r_query > h->ix.prm.r)
+        return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", r_query, h->ix.prm.r);
+    void *base = nullptr;
+    FCLSH_TRY(scratch_address(h->ix.device, &base));
+    QueryWorkspace ws;
+    FCLSH_TRY(ws_carve(ws, base, kNoAllocScratchBytes, nq, h->ix.prm.L()));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     FCLSH_TRY(query_batch_async(h->ix, ws, d_queries, nq, r_query, d_radii, st, d_offsets, d_ids, ids_capacity));
     return publish_result(ws, d_result, st);
 }

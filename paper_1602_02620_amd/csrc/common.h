@@ -186,6 +186,8 @@ struct QueryWorkspace {
 
 fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills);
 void ws_release(QueryWorkspace &ws);
+// A workspace laid out in one caller-owned device buffer (no allocation).
+fclsh_status ws_carve(QueryWorkspace &ws, void *base, size_t bytes, int64_t nq, int L);
 // Device bytes the workspace holds.
 uint64_t ws_bytes(const QueryWorkspace &ws);
 fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,

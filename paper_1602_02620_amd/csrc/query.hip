@@ -657,6 +657,58 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
     return FCLSH_OK;
 }
 
+// Lays a workspace for nq queries of L tables out in one caller-owned device
+// buffer of `bytes` bytes (256-byte aligned pieces): query keys, per-query
+// counters, scan partials and the control block first, then the spill queue
+// and the pair buffers share what is left, a quarter of it for spill chunks
+// (16 B each) and the rest for pairs (12 B each: query, id and the sort's
+// second buffer).  The lookup ranges of the collision count are not laid out.
+// Nothing is allocated.  Returns FCLSH_ENOMEM when the fixed part, at least
+// one pair and one spill chunk do not fit.
+fclsh_status ws_carve(QueryWorkspace &ws, void *base, size_t bytes, int64_t nq, int L) {
+    ws = QueryWorkspace{};
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const int64_t items = nq * L;
+    // offsets of the fixed pieces, computed before any pointer is formed
+    const size_t sz_fixed[] = {size_t(std::max<int64_t>(items, 1)) * 4, size_t(nq + 1) * 4, size_t(nq + 1) * 4,
+                               size_t(nq + 1) * 8, size_t(scan_partials_needed(nq + 1)) * 8, sizeof(QueryCtrl)};
+    size_t off_fixed[6], at = 0;
+    for (int i = 0; i < 6; ++i) {
+        off_fixed[i] = up(at);
+        at = off_fixed[i] + sz_fixed[i];
+    }
+    at = up(at);
+    if (at + 3 * 256 + 16 + 12 > bytes)
+        return fail(FCLSH_ENOMEM, "%lld queries x %d tables need more than the %zu scratch bytes", (long long)nq, L,
+                    bytes);
+    const size_t rest = bytes - at - 3 * 256;  // room for the alignment of the last pieces
+    const int64_t spills = std::max<int64_t>(1, int64_t(rest / 4 / 16));
+    const int64_t pairs = int64_t((rest - size_t(spills) * 16) / 12);
+    const size_t off_spill = at;
+    const size_t off_pq = up(off_spill + size_t(spills) * 16);
+    const size_t off_pid = up(off_pq + size_t(pairs) * 4);
+    const size_t off_tmp = up(off_pid + size_t(pairs) * 4);
+    if (pairs < 1 || off_tmp + size_t(pairs) * 4 > bytes)
+        return fail(FCLSH_ENOMEM, "%lld queries x %d tables leave no room for results in %zu scratch bytes",
+                    (long long)nq, L, bytes);
+    char *const b0 = static_cast<char *>(base);
+    ws.qkeys = reinterpret_cast<uint32_t *>(b0 + off_fixed[0]);
+    ws.qcount = reinterpret_cast<uint32_t *>(b0 + off_fixed[1]);
+    ws.qfill = reinterpret_cast<uint32_t *>(b0 + off_fixed[2]);
+    ws.qcount64 = reinterpret_cast<uint64_t *>(b0 + off_fixed[3]);
+    ws.scan_part = reinterpret_cast<uint64_t *>(b0 + off_fixed[4]);
+    ws.ctrl = reinterpret_cast<QueryCtrl *>(b0 + off_fixed[5]);
+    ws.spill = reinterpret_cast<uint4 *>(b0 + off_spill);
+    ws.pq = reinterpret_cast<uint32_t *>(b0 + off_pq);
+    ws.pid = reinterpret_cast<uint32_t *>(b0 + off_pid);
+    ws.sorttmp = reinterpret_cast<uint32_t *>(b0 + off_tmp);
+    ws.cap_items = items;
+    ws.cap_q = nq + 1;
+    ws.cap_pairs = pairs;
+    ws.cap_spill = spills;
+    return FCLSH_OK;
+}
+
 uint64_t ws_bytes(const QueryWorkspace &ws) {
     if (!ws.ctrl) return 0;
     return uint64_t(ws.cap_items) * 16 + uint64_t(ws.cap_q) * 16 +
