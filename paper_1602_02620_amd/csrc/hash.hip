@@ -150,57 +150,77 @@ __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
     }
 }
 
-// LDS staging of a block's keys: D-1 rows (row v-1 for v = 1..D-1) of
-// PB = 4U points.  Rows are PB + 1 words apart with PAD more words every 32
-// values of v, so that the 64 lanes of one staging store (rows that differ in
-// high index bits) fall into distinct bank pairs; PAD per Hadamard order from
-// a bank model of those stores.  Since v >> 5 is additive over the disjoint
-// bits v = vlane | vreg, a lane's 32 stores are one base plus constants.
+// Waves per workgroup by Hadamard order, so that a workgroup's stage rows
+// (NW*U points of one table) are at least 64 bytes, and 128 where LDS allows:
+// measured on this GPU, writing 2 GB of such rows at a row stride of n keys
+// runs at 1.3 TB/s with 16-byte rows, 3.8 TB/s with 64-byte rows and
+// 5.5 TB/s with 128-byte or wider rows (a contiguous stream: 4.8 TB/s).
 template <int LOGD>
-constexpr int stage_pad() { return LOGD == 9 ? 2 : 1; }
+constexpr int hash_waves() { return LOGD == 9 || LOGD == 10 ? 8 : LOGD == 11 ? 16 : 4; }
 
-template <int LOGD, int U>
-__device__ __host__ constexpr int stage_index(int row, int col) {
-    return row * (4 * U + 1) + ((row + 1) >> 5) * stage_pad<LOGD>() + col;
+// LDS staging of a block's keys: rows indexed by the Hadamard row v in
+// [0, D) (row 0, the dropped all-zero codeword, is never written), each of
+// PB = NW*U points, row v at v*PB + (v >> SH)*PAD.  (PAD, SH) per order from
+// a model of the 64 LDS banks under which both access patterns are
+// conflict-free: a wave's staging store (its G sub-lanes' rows, which differ
+// in high index bits, times its U points) and a wave's write-out read (PB
+// consecutive words of 64/PB consecutive rows).  Since SH <= log2(G), the
+// padding term is additive over the disjoint index bits a lane and a
+// register contribute (a lane's staging stores are one base plus
+// constants), and over v = v0 + G*k with v0 < G (a thread's write-out reads
+// are one base plus constants).
+template <int LOGD>
+constexpr int stage_pad() {
+    return LOGD <= 5 ? 0 : LOGD == 6 ? 4 : LOGD <= 8 ? 8 : LOGD == 9 ? 4 : LOGD == 10 ? 2 : 1;
+}
+template <int LOGD>
+constexpr int stage_shift() { return LOGD <= 5 ? 0 : LOGD == 6 ? 1 : LOGD == 7 ? 2 : LOGD <= 11 ? 3 : 4; }
+
+template <int LOGD, int PB>
+__device__ __host__ constexpr int stage_index(int v, int col) {
+    return v * PB + (v >> stage_shift<LOGD>()) * stage_pad<LOGD>() + col;
 }
 
-template <int LOGD, int U>
+template <int LOGD, int PB>
 constexpr size_t stage_words() {
-    return size_t(stage_index<LOGD, U>((1 << LOGD) - 2, 4 * U - 1)) + 1;
+    return size_t(stage_index<LOGD, PB>((1 << LOGD) - 1, PB - 1)) + 1;
 }
 
-// One workgroup of 4 waves per (part, `rounds` x 4 consecutive point
+// One workgroup of NW waves per (part, `rounds` x NW consecutive point
 // groups), in XCD-contiguous order; in each round every wave takes one group
-// of U consecutive points and the block writes the keys of its 4U points out
-// together.  Short-lived waves keep every SIMD full: a grid-stride loop over
+// of U consecutive points and the block writes the keys of its NW*U points
+// out together.  Short-lived waves keep every SIMD full: a grid-stride loop over
 // groups measured 1.9x slower on the mid workload, and the 512-column kernel
 // runs one round (see hash_rounds).  The part's gather table (per in-lane
 // column k and sub-lane s, the coordinate feeding it and its even
 // representative b'') is staged in LDS once per workgroup.
-template <int LOGD, int LOGV, bool SPECIFIC>
-__global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restrict__ pts, int64_t m, int W,
+template <int LOGD, int LOGV, bool SPECIFIC, int NW>
+__global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__restrict__ pts, int64_t m, int W,
                                                        const int32_t *__restrict__ seg,
                                                        const uint2 *__restrict__ gtab, int E,
                                                        uint32_t *__restrict__ keys, int64_t key_stride,
                                                        int64_t nblk, int64_t nitems, int rounds) {
     using S = Shape<LOGD, LOGV>;
     constexpr int V = S::V, G = S::G, U = S::U, D = S::D;
+    constexpr int PB = NW * U;  // points per stage row
+    constexpr int PAD = stage_pad<LOGD>(), SH = stage_shift<LOGD>();
+    static_assert(SH <= S::LOGG, "the stage padding must split over lane and register index bits");
     extern __shared__ __align__(16) uint32_t lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int s = lane >> S::LOGU;
     const int u = lane & (U - 1);
-    // work item: (part p, `rounds` consecutive blocks of 4 point groups),
+    // work item: (part p, `rounds` consecutive blocks of NW point groups),
     // XCD-contiguous
     const int64_t witem = xcd_contiguous_item(blockIdx.x, gridDim.x);
     if (witem >= nitems) return;  // grid padding
     const int p = int(witem / nblk);
-    const int64_t c0 = (witem % nblk) * 4 * rounds;  // the item's first point group
+    const int64_t c0 = (witem % nblk) * NW * rounds;  // the item's first point group
     const int stride = 2 * W + 1;
     uint2 *tab = reinterpret_cast<uint2 *>(lds);
     uint32_t *wx = lds + 2 * E * G + wave * U * stride;
 
-    for (int i = threadIdx.x; i < E * G; i += 256) tab[i] = gtab[int64_t(p) * E * G + i];
+    for (int i = threadIdx.x; i < E * G; i += 64 * NW) tab[i] = gtab[int64_t(p) * E * G + i];
     __syncthreads();
 
     // index bits of the output held by this lane (see Shape)
@@ -209,12 +229,12 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     for (int b = 0; b < S::LOGG; ++b)
         if ((lane >> (S::LOGU + b)) & 1) vlane |= 1 << (S::swap_stage(b) ? S::swap_reg(b) : LOGV + b);
 
-    // The block's keys are staged in LDS as (D-1) rows of 4U points, then
-    // written out row by row: 4U consecutive points of a table per row
-    // segment instead of the U of one wave.
-    uint32_t *stage = lds + 2 * E * G + 4 * U * stride;
+    // The block's keys are staged in LDS as rows of PB points, then written
+    // out row by row: PB consecutive points of a table per row segment
+    // instead of the U of one wave.
+    uint32_t *stage = lds + 2 * E * G + NW * U * stride;
     const int64_t ngroups = (m + U - 1) / U;
-    for (int64_t g0 = c0; g0 < c0 + 4 * rounds && g0 < ngroups; g0 += 4) {  // workgroup-uniform
+    for (int64_t g0 = c0; g0 < c0 + NW * rounds && g0 < ngroups; g0 += NW) {  // workgroup-uniform
         const int64_t grp = g0 + wave;
         const int64_t base = grp * U;
         if (grp < ngroups) {  // wave-uniform
@@ -275,10 +295,9 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
 
             // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
             const double Sm = __shfl(t[0], u, 64) + kTwo52;
-            // stage_index(vlane + vr - 1, wave * U + u), split into a lane base and
+            // stage_index(vlane | vr, wave * U + u), split into a lane base and
             // a per-register constant
-            constexpr int RS = 4 * U + 1, PAD = stage_pad<LOGD>();
-            const int sbase = (vlane - 1) * RS + (vlane >> 5) * PAD + wave * U + u;
+            const int sbase = vlane * PB + (vlane >> SH) * PAD + wave * U + u;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
                 const int vr = S::vreg(k);
@@ -290,24 +309,41 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
                 const uint64_t zb = __double_as_longlong(z);
                 const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
                 const uint32_t y = min(half + hi - kHiWord52, half + hi - (kHiWord52 + kPrime));
-                stage[sbase + vr * RS + (vr >> 5) * PAD] = y;
+                stage[sbase + vr * PB + (vr >> SH) * PAD] = y;
             }
         }
         __syncthreads();
         {
-            // thread t writes column t % PB of rows t / PB, t / PB + 256 / PB, ...
-            // (PB = 256 / G divides the block)
-            constexpr int PB = 4 * U;
-            constexpr int RSTEP = 256 / PB;
+            // thread t writes column t % PB of rows v = t / PB + G k (the
+            // 64 NW threads cover G rows at a time), stage row v going to
+            // table p (D-1) + v - 1.  Rows of at least 64 bytes are written
+            // with non-temporal stores (this kernel never reads them back);
+            // shorter rows keep the normal path, whose L2 merges the
+            // neighbouring workgroups' pieces of a line.
+            const int v0 = threadIdx.x / PB;
             const int col = threadIdx.x % PB;
             const int64_t i = g0 * U + col;
-            int row = threadIdx.x / PB;
-            if (i < m && row < D - 1) {
-                uint32_t *dst = keys + (int64_t(p) * (D - 1) + row) * key_stride + i;
-                const int64_t dstep = int64_t(RSTEP) * key_stride;
-                for (; row < D - 1; row += RSTEP) {
-                    *dst = stage[stage_index<LOGD, U>(row, col)];
-                    dst += dstep;
+            if (i < m) {
+                const uint32_t *src = stage + stage_index<LOGD, PB>(v0, col);
+                uint32_t *row1 = keys + (int64_t(p) * (D - 1) + v0) * key_stride + i;  // table of v = v0 + 1
+                constexpr int NK = D / G;
+                constexpr int CH = NK < 16 ? NK : 16;
+                constexpr int KSTEP = G * PB + (G >> SH) * PAD;  // stage_index(v + G, c) - stage_index(v, c)
+#pragma unroll
+                for (int k0 = 0; k0 < NK; k0 += CH) {
+                    uint32_t val[CH];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) val[c] = src[(k0 + c) * KSTEP];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const int k = k0 + c;
+                        if (k == 0 && v0 == 0) continue;  // v = 0: the dropped row
+                        uint32_t *dst = row1 + (int64_t(k) * G - 1) * key_stride;
+                        if constexpr (PB * 4 >= 64)
+                            __builtin_nontemporal_store(val[c], dst);
+                        else
+                            *dst = val[c];
+                    }
                 }
             }
         }
@@ -315,7 +351,7 @@ __global__ __launch_bounds__(256) void fht_hash_kernel(const uint64_t *__restric
     }
 }
 
-// Rounds of 4 point groups per workgroup (the gather table is staged once
+// Rounds of NW point groups per workgroup (the gather table is staged once
 // for all of them), by measurement: short-lived workgroups (D' below 512)
 // gain from several rounds, the 512-column kernel loses (hash times in ms
 // for 1 / 2 / 4 / 8 rounds: D' = 512, 1M points: 0.68 / 0.79 / 0.75 / 0.76;
@@ -327,22 +363,23 @@ template <int LOGD, int LOGV>
 fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys, int64_t key_stride,
                       hipStream_t st) {
     using S = Shape<LOGD, LOGV>;
+    constexpr int NW = hash_waves<LOGD>();
     const HashPlan &pl = ix.plan;
-    const size_t lds = size_t(pl.E) * S::G * 8 + size_t(4) * S::U * (2 * pl.W + 1) * 4 +
-                       stage_words<LOGD, S::U>() * 4;
+    const size_t lds = size_t(pl.E) * S::G * 8 + size_t(NW) * S::U * (2 * pl.W + 1) * 4 +
+                       stage_words<LOGD, NW * S::U>() * 4;
     if (lds > 160 * 1024) return fail(FCLSH_EUNSUPPORTED, "hash kernel LDS need %zu bytes", lds);
     const int64_t ngroups = (m + S::U - 1) / S::U;
     const int rounds = hash_rounds(LOGD, pl.specific);
-    const int64_t nblk = (ngroups + 4 * rounds - 1) / (4 * rounds);  // work items per part
+    const int64_t nblk = (ngroups + NW * rounds - 1) / (NW * rounds);  // work items per part
     const int64_t nitems = nblk * pl.t;
     const int64_t grid = xcd_grid(nitems);
     if (grid > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "%lld points need too many workgroups", (long long)m);
     if (pl.specific)
-        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, true>), dim3(unsigned(grid)), dim3(256), lds, st, pts, m,
-                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems, rounds);
+        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, true, NW>), dim3(unsigned(grid)), dim3(64 * NW), lds, st,
+                           pts, m, pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems, rounds);
     else
-        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, false>), dim3(unsigned(grid)), dim3(256), lds, st, pts, m,
-                           pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems, rounds);
+        hipLaunchKernelGGL((fht_hash_kernel<LOGD, LOGV, false, NW>), dim3(unsigned(grid)), dim3(64 * NW), lds, st,
+                           pts, m, pl.W, pl.seg, pl.gtab, pl.E, keys, key_stride, nblk, nitems, rounds);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
