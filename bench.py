@@ -373,7 +373,7 @@ def served_block(args, w, idx, r, lat_plain, torch, fc):
             "queries_per_s": st["queries"] / (t_end - t0),
             "latency_ms_p50": st["p50_ms"], "latency_ms_p99": st["p99_ms"],
             "plain_service_ms_p50": pct(plain_req, 50), "plain_service_ms_p99": pct(plain_req, 99),
-            "alone_equals_mix": bool(same)}
+            "alone_equals_mix": bool(same), "reruns": st["reruns"], "resident_bytes": st["resident_bytes"]}
 
 
 def batched_section(args, fc, torch):
@@ -440,7 +440,7 @@ def served_section(args, fc, torch):
             ix.query_plain(qd[i:i + 1], w.r)
             lat.append(time.perf_counter() - t0)
         plain[name] = float(np.mean(lat))
-    srv = Server({"A": ia, "B": ib}, max_batch=4096, streams=3, mem_budget=8 << 30, ids_per_query=16)
+    srv = Server({"A": ia, "B": ib}, max_batch=4096, streams=3, mem_budget=128 << 30, ids_per_query=16)
     rng = np.random.default_rng(31)
     arrivals = poisson_trace(args.serve_rps, args.serve_seconds, rng)
     reqs = []

@@ -78,6 +78,7 @@ def check_index(w, seed, n_pts=48, n_tables=6, n_queries=24, radii=None):
         bf = oracle.brute_force(w.points, w.d, w.queries[i:i + 1], rq).ids[0]
         assert np.array_equal(got_q[i], bf), f"{w.name}: query {i} differs"
     _say(f"[full] {w.name}: ok, {int(offs[-1])} neighbours in the batch")
+    idx._full_answers = got_q
     return idx
 
 
@@ -106,9 +107,25 @@ def test_full_batched():
     w = synth.batched()
     idx = check_index(w, 3004, n_queries=12)
     # skew: the per-query bucket sizes of the batch span orders of magnitude
-    coll = idx.collisions(fc.to_device_words(w.queries[:2000])).cpu().numpy()
+    qd = fc.to_device_words(w.queries[:2000])
+    coll = idx.collisions(qd).cpu().numpy()
     _say(f"[full] batched #Collisions min {coll.min()} median {np.median(coll)} max {coll.max()}")
     assert coll.max() >= 100 * max(1, int(np.median(coll)))
+    # the heaviest queries (their buckets go through the spill queue) and 200
+    # random ones of the 100,000-query batch, against the linear scan
+    rng = np.random.default_rng(44)
+    heavy = np.argsort(coll)[-50:]
+    sample = np.unique(np.concatenate([heavy, rng.choice(w.nq, size=200, replace=False)]))
+    _say(f"[full] batched: {len(sample)} sampled answers incl. the 50 heaviest (#Collisions >= {coll[heavy].min()})")
+    bf = oracle.brute_force(w.points, w.d, w.queries[sample], w.r).ids
+    for i, want in zip(sample, bf):
+        assert np.array_equal(idx._full_answers[i], want), f"batched: query {i} differs"
+    # Sec. 4.1 counters at full size: #Collisions as counted by the lookup
+    # pass, distinct candidates between the answers and the collisions
+    c2, cand = (x.cpu().numpy() for x in idx.cost(qd))
+    assert np.array_equal(c2, coll)
+    nans = np.array([len(idx._full_answers[i]) for i in range(2000)])
+    assert np.all(cand <= coll) and np.all(cand >= nans)
     idx.close()
 
 
@@ -117,5 +134,5 @@ def test_full_served_indexes():
     idx = check_index(a, 3005, radii=a.query_radius)
     idx.close()
     b = synth.served_b(nq=256)
-    idx = check_index(b, 3006, n_pts=16, n_tables=3, n_queries=12, radii=b.query_radius)
+    idx = check_index(b, 3006, n_pts=16, n_tables=3, n_queries=64, radii=b.query_radius)
     idx.close()

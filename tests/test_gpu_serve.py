@@ -25,7 +25,11 @@ def test_served_requests_exact_alone_and_in_mix():
     b = synth.uniform_with_planted(1500, 1024, 20, 20, 5, 1306, "B")
     ia = fc.Index(fc.to_device_words(a.points), 256, 10, seed=3205)
     ib = fc.Index(fc.to_device_words(b.points), 1024, 20, seed=3206)
-    srv = Server({"A": ia, "B": ib}, max_batch=256, streams=3, mem_budget=64 << 20, ids_per_query=4)
+    srv = Server({"A": ia, "B": ib}, max_batch=256, streams=3, mem_budget=1 << 30, ids_per_query=4)
+    # admission counted what is really resident: both indexes and every
+    # workspace the slots reserved (plus the slots' own small buffers)
+    held = sum(ix.memory()["index_bytes"] + ix.memory()["workspace_bytes"] for ix in (ia, ib))
+    assert held <= srv.resident_bytes <= held + (8 << 20)
     rng = np.random.default_rng(21)
     reqs = []
     arrivals = poisson_trace(2000.0, 0.03, rng)
@@ -52,5 +56,8 @@ def test_served_requests_exact_alone_and_in_mix():
         alone = csr_lists(*ix.query(fc.to_device_words(q), rad))
         assert_same_lists(got, alone, what="alone vs mix")
     print(f"[serve] ok {st}", flush=True)
+    # a budget below the indexes' own bytes is refused
+    with pytest.raises(ValueError):
+        Server({"A": ia, "B": ib}, max_batch=256, streams=1, mem_budget=ia.memory()["index_bytes"])
     ia.close()
     ib.close()
