@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--serve-rps", type=float, default=100.0, help="Poisson request rate of the served run")
     ap.add_argument("--serve-max", type=int, default=4096, help="largest request (queries) of the served block")
     ap.add_argument("--big-batch", type=int, default=100_000, help="queries in the batched block's batch")
+    ap.add_argument("--study", choices=["fig2", "fig3"], default=None,
+                    help="the precision/recall and #Collisions/#Candidates study of Sec. 4.3 at the shapes "
+                         "of Fig. 2 (n = 10K..50K, r = 6) or Fig. 3 (n = 64K, replication and 2 parts); "
+                         "prints one JSON line of rows instead of the benchmark")
+    ap.add_argument("--study-queries", type=int, default=100)
     ap.add_argument("--kernel-only", choices=["hash", "build"], default=None,
                     help="profiling aid: launch only this part (plus a plain copy of known size "
                          "for counter calibration) --kernel-reps times")
@@ -78,6 +83,9 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.study:
+        print(json.dumps(study(args, fc, torch, synth)), flush=True)
+        return
     dev = torch.device("cuda", 0)
     w = synth.WORKLOADS[args.workload]()
     n, d, r, nq = w.n, w.d, w.r, w.nq
@@ -296,6 +304,61 @@ def main():
     if checks and not args.no_cpu_baseline:
         out["cpu_baseline"]["answers_checked"] = verify_samples(checks)
     print(json.dumps(out), flush=True)
+
+
+# Settings of the study (Sec. 4.3): Fig. 2 without pre-processing, Fig. 3
+# with Alg. 1's replication (copies 4, 3, 2, 2 for r = 2..5) and with two
+# parts (r = 10, 12, 14, 16).  (n, r, copies, parts)
+STUDY = {
+    "fig2": [(n, 6, 1, 1) for n in (10_000, 20_000, 30_000, 40_000, 50_000)],
+    "fig3": [(65_536, r, k, 1) for r, k in ((2, 4), (3, 3), (4, 2), (5, 2))]
+            + [(65_536, r, 1, 2) for r in (10, 12, 14, 16)],
+}
+
+
+def study(args, fc, torch, synth):
+    """Precision / recall and Sec. 4.1's cost measures of fcLSH on the
+    paper's synthetic sets (d = 128, points around each query at distances
+    spread over 1..128), one index per setting.  Recall is measured against
+    the library's linear scan; precision is reported ids over distinct
+    candidates (what the paper notes equals the speedup over a linear scan
+    when C_lookup is ignored).  The hash time per query is the key
+    computation of a whole query batch divided by its size."""
+    rows = []
+    d, nq = 128, args.study_queries
+    for n, r, copies, parts in STUDY[args.study]:
+        stage(f"study {args.study}: n={n} r={r} copies={copies} parts={parts}")
+        w = synth.hamming_balls(n, d, nq, seed=5000 + n + 100 * r)
+        pts, qs = fc.to_device_words(w.points), fc.to_device_words(w.queries)
+        idx = fc.Index(pts, d, r, seed=args.seed, replicate=copies if copies > 1 else 0,
+                       partitions=parts if parts > 1 else 0)
+        L = idx.info["L"]
+        got = fc.split_csr(*idx.query(qs, r))
+        truth = fc.split_csr(*fc.linear_scan(pts, d, qs, r))
+        coll, cand = (x.cpu().numpy() for x in idx.cost(qs))
+        found = sum(len(np.intersect1d(g, t)) for g, t in zip(got, truth))
+        ntruth = sum(len(t) for t in truth)
+        nrep = sum(len(g) for g in got)
+        keys = torch.empty((L, nq), dtype=torch.int32, device="cuda")
+        idx.hash(qs, out=keys)
+        torch.cuda.synchronize()
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record()
+        for _ in range(10):
+            idx.hash(qs, out=keys)
+        en.record()
+        en.synchronize()
+        per_q = [len(g) / c if c else 1.0 for g, c in zip(got, cand)]
+        rows.append({"n": n, "d": d, "r": r, "copies": copies, "parts": parts, "L": L, "queries": nq,
+                     "recall": found / ntruth if ntruth else 1.0, "exact": nrep == found == ntruth,
+                     "precision": nrep / float(cand.sum()) if cand.sum() else 1.0,
+                     "precision_mean_per_query": float(np.mean(per_q)),
+                     "neighbours_per_query": ntruth / nq,
+                     "collisions_per_query": float(coll.mean()), "candidates_per_query": float(cand.mean()),
+                     "hash_us_per_query": st.elapsed_time(en) * 1e3 / 10 / nq})
+        idx.close()
+    return {"study": args.study, "data": "synthetic: d=128, points around each query at distances U{1..128}",
+            "rows": rows}
 
 
 def roof(nbytes, ms, kernel, n, d, r, basis):

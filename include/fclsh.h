@@ -311,6 +311,19 @@ FCLSH_API fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d
 FCLSH_API fclsh_status fclsh_query_cost(fclsh_index idx, const uint64_t *d_queries, int64_t nq,
                                         void *stream, uint64_t *d_collisions, uint64_t *d_candidates);
 
+/* Linear scan, the baseline of the paper's evaluation (Sec. 4) and the
+ * ground truth its recall is measured against: for each query, every point
+ * at Hamming distance <= r, ids ascending, without any index.  d_points:
+ * device n*W uint64 (n in [1, 2^31-1]); d_queries: device nq*W uint64, nq in
+ * [0, 65535].  Outputs and FCLSH_ECAPACITY as fclsh_query_batch.  Allocates
+ * per-call tile counts (16 bytes per query and 4096 points); synchronises
+ * `stream`.  Errors: FCLSH_EINVAL, FCLSH_ENOMEM, FCLSH_ECAPACITY,
+ * FCLSH_EDEVICE. */
+FCLSH_API fclsh_status fclsh_linear_scan(const uint64_t *d_points, int64_t n, int32_t d,
+                                         const uint64_t *d_queries, int64_t nq, int32_t r, void *stream,
+                                         uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
+                                         int64_t *total_out);
+
 /* The plain path: one query at a time, each answered by its own launch
  * sequence (hash, lookup and verify, compaction) and a synchronisation; the
  * baseline the batched path is measured against.  Same outputs and errors as

@@ -36,7 +36,7 @@ EXPORTS = [
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
     "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
     "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
-    "fclsh_query_batch_noalloc",
+    "fclsh_query_batch_noalloc", "fclsh_linear_scan",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -96,6 +96,7 @@ def lib():
             "fclsh_preprocessing": [i64, i32, ctypes.c_double, P(i32), P(i32)],
             "fclsh_query_collisions": [vp, vp, i64, vp, vp],
             "fclsh_query_cost": [vp, vp, i64, vp, vp, vp],
+            "fclsh_linear_scan": [vp, i64, i32, vp, i64, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_batch_radii": [vp, vp, i64, vp, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_query_batch_finish": [vp, vp, vp, vp, i64, P(i64)],
             "fclsh_query_reserve": [vp, i64, i64, i64, vp],
@@ -151,6 +152,28 @@ def derive_params(d: int, r: int, seed: int, partitions: int = 0, replicate: int
     _check(lib().fclsh_derive_params(d, r, seed & (2**64 - 1), ctypes.byref(opts), ctypes.byref(t),
                                      ctypes.byref(rp), part.ctypes.data, col.ctypes.data, b.ctypes.data))
     return {"t": t.value, "r_part": rp.value, "part": part, "col": col, "b": b}
+
+
+def linear_scan(points, d: int, queries, r: int, stream=None):
+    """fclsh_linear_scan: every point within r of each query, without an
+    index (offsets int64 [nq+1], ids int32 [total])."""
+    torch = _torch()
+    pts = _dev_words(points, d, "points")
+    q = _dev_words(queries, d, "queries")
+    offsets = torch.empty(q.shape[0] + 1, dtype=torch.int64, device=q.device)
+    total = ctypes.c_int64()
+    cap = max(1024, 16 * q.shape[0])
+    for _ in range(2):
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
+        st = lib().fclsh_linear_scan(ctypes.c_void_p(pts.data_ptr()), pts.shape[0], d, ctypes.c_void_p(q.data_ptr()),
+                                     q.shape[0], r, _stream_ptr(stream), ctypes.c_void_p(offsets.data_ptr()),
+                                     ctypes.c_void_p(ids.data_ptr()), cap, ctypes.byref(total))
+        if st == FCLSH_ECAPACITY:
+            cap = total.value
+            continue
+        _check(st)
+        return offsets, ids[:total.value]
+    raise FclshError(FCLSH_ECAPACITY, "result did not fit after resizing")
 
 
 def _torch():

@@ -611,6 +611,26 @@ fclsh_status fclsh_query_cost(fclsh_index idx, const uint64_t *d_queries, int64_
     return query_cost(h->ix, *h->workspace(st), d_queries, nq, d_collisions, d_candidates, st);
 }
 
+fclsh_status fclsh_linear_scan(const uint64_t *d_points, int64_t n, int32_t d, const uint64_t *d_queries,
+                               int64_t nq, int32_t r, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
+                               int64_t ids_capacity, int64_t *total_out) {
+    if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
+    if (n < 1 || n > 0x7FFFFFFFll || !d_points) return fail(FCLSH_EINVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
+    if (d < 1) return fail(FCLSH_EINVAL, "d=%d must be positive", d);
+    if (r < 0) return fail(FCLSH_EINVAL, "negative radius");
+    if (nq < 0 || nq > 65535 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "nq=%lld outside [0, 65535]", (long long)nq);
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (nq == 0) {
+        static const uint64_t zero = 0;
+        FCLSH_HIP(hipMemcpyAsync(d_offsets, &zero, 8, hipMemcpyHostToDevice, st));
+        FCLSH_HIP(hipStreamSynchronize(st));
+        *total_out = 0;
+        return FCLSH_OK;
+    }
+    return linear_scan(d_points, n, d, d_queries, nq, r, st, d_offsets, d_ids, ids_capacity, total_out);
+}
+
 fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                void *stream, uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                int64_t *total_out) {

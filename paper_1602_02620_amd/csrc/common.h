@@ -210,5 +210,9 @@ int64_t scan_partials_needed(int64_t n);
 fclsh_status exclusive_scan_u64_ws(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *partials,
                                    hipStream_t st);
 const char *last_error_cstr();
+// Linear scan (linear.hip): CSR of every point within r of each query, ids
+// ascending; synchronises st once for the result size.
+fclsh_status linear_scan(const uint64_t *pts, int64_t n, int d, const uint64_t *qs, int64_t nq, int r,
+                         hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap, int64_t *total_out);
 
 }  // namespace fclsh

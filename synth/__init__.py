@@ -15,6 +15,9 @@ shapes, see the design notes for which stands in for what):
   mixture                points drawn from random centres with independent
                          per-bit flip noise (learned binary codes / document
                          fingerprints, Table 2 shapes)
+  hamming_balls          the synthetic sets of the precision/recall study
+                         (Sec. 4.3): around each uniform query, points at
+                         distances spread uniformly over 1..max_radius
 """
 from __future__ import annotations
 
@@ -140,6 +143,26 @@ def mixture(n: int, d: int, r: int, n_centers: int, p, nq: int, seed: int,
     return Workload(name, d, r, pts, qs, None,
                     {"centers": n_centers, "p": p, "seed": seed, "cluster": pc_of,
                      "query_cluster": qc_of})
+
+
+def hamming_balls(n: int, d: int, nq: int, seed: int, max_radius: int | None = None,
+                  name: str = "hamming_balls") -> Workload:
+    """nq uniform queries; the n points are split evenly among them (point i
+    belongs to query i % nq), and each point is its query with k ~ U{1..R}
+    distinct uniformly chosen bits flipped, R = max_radius (default d)."""
+    rng = np.random.default_rng(seed)
+    R = d if max_radius is None else int(max_radius)
+    queries = uniform_points(nq, d, rng)
+    owner = np.arange(n) % nq
+    k = rng.integers(1, R + 1, size=n)
+    # the k smallest of d random keys per row pick k distinct coordinates
+    order = np.argsort(rng.random((n, d)), axis=1)
+    flip = np.zeros((n, d), np.uint8)
+    rows = np.repeat(np.arange(n), k)
+    cols = order[np.arange(d)[None, :] < k[:, None]]  # row-major: the first k of each row
+    flip[rows, cols] = 1
+    pts = queries[owner] ^ _pack_bits(flip, d)
+    return Workload(name, d, 0, pts, queries, None, {"owner": owner, "flips": k, "seed": seed})
 
 
 # ---------------------------------------------------------------------------
