@@ -15,6 +15,9 @@ with gcc and marshals numpy arrays through ctypes.
     tables          hash tables of non-empty buckets, sorted by (key, id)
     query_batch     Strategy 2 with S1-S3 of Sec. 4.1 and an n-bit bitmap
     brute_force     linear scan ground truth (Sec. 4.2)
+    keys_sparse     Eq. (1) keys of points given by their nonzero coordinates
+                    (O(nnz L) per point)
+    brute_force_sparse  linear scan over such points
 """
 from __future__ import annotations
 
@@ -70,6 +73,10 @@ def lib():
                                       vp, vp, vp, vp]
         L.orc_brute_force.restype = None
         L.orc_brute_force.argtypes = [vp, i64, i32, vp, i64, i32, i64, vp, vp]
+        L.orc_keys_sparse.restype = None
+        L.orc_keys_sparse.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, u64, vp]
+        L.orc_brute_force_sparse.restype = None
+        L.orc_brute_force_sparse.argtypes = [vp, vp, i64, vp, vp, i64, i32, i32, i64, vp, vp]
         L.orc_num_threads.restype = i32
         L.orc_num_threads.argtypes = []
         L.orc_set_num_threads.restype = None
@@ -237,6 +244,44 @@ def brute_force(points, d, queries, rq, cap=None) -> QueryResult:
     out = np.zeros((max(nq, 1), max(cap, 1)), np.uint32)
     counts = np.zeros(max(nq, 1), np.int64)
     lib().orc_brute_force(_p(points), n, d, _p(queries), nq, rq, max(cap, 1), _p(out), _p(counts))
+    ids = [out[i, :min(counts[i], cap)].copy() for i in range(nq)]
+    return QueryResult(counts[:nq], ids)
+
+
+def _csr(ptr, cols, d: int | None = None):
+    ptr = np.ascontiguousarray(ptr, np.int64)
+    cols = np.ascontiguousarray(cols, np.int32)
+    if ptr.ndim != 1 or ptr.size < 1 or ptr[0] != 0 or ptr[-1] != cols.size or np.any(np.diff(ptr) < 0):
+        raise ValueError("ptr must run from 0 to len(cols), non-decreasing")
+    if d is not None and cols.size and (cols.min() < 0 or cols.max() >= d):
+        raise ValueError("column outside [0, d)")
+    return ptr, cols
+
+
+def keys_sparse(ptr, cols, pr: Params) -> np.ndarray:
+    """uint32 [L, m]: Eq. (1) keys of the m points whose nonzero coordinates
+    are cols[ptr[i]:ptr[i+1]] (no repeats within a point)."""
+    ptr, cols = _csr(ptr, cols, pr.d)
+    m = ptr.size - 1
+    out = np.zeros((pr.L, m), np.uint32)
+    if m:
+        lib().orc_keys_sparse(_p(ptr), _p(cols), m, pr.t, pr.rpart, _p(pr.part), _p(pr.col), _p(pr.b), pr.P,
+                              _p(out))
+    return out
+
+
+def brute_force_sparse(ptr, cols, qptr, qcols, d: int, rq: int, cap=None) -> QueryResult:
+    """Linear scan over points and queries given by their nonzero
+    coordinates (d coordinates)."""
+    ptr, cols = _csr(ptr, cols, d)
+    qptr, qcols = _csr(qptr, qcols, d)
+    n = ptr.size - 1
+    nq = qptr.size - 1
+    cap = n if cap is None else cap
+    out = np.zeros((max(nq, 1), max(cap, 1)), np.uint32)
+    counts = np.zeros(max(nq, 1), np.int64)
+    lib().orc_brute_force_sparse(_p(ptr), _p(cols), n, _p(qptr), _p(qcols), nq, d, rq, max(cap, 1), _p(out),
+                                 _p(counts))
     ids = [out[i, :min(counts[i], cap)].copy() for i in range(nq)]
     return QueryResult(counts[:nq], ids)
 

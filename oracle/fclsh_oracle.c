@@ -13,7 +13,8 @@
  * work per point.  On top of that: hash tables of non-empty buckets
  * (Sec. 2.2), the Strategy-2 query with an n-bit bitmap for duplicate
  * removal (Sec. 2.2 and Steps S1-S3 of Sec. 4.1), and a linear scan
- * (Sec. 4.2) as ground truth.  No blocking, fusion or reordering beyond what
+ * (Sec. 4.2) as ground truth; for points given by their nonzero
+ * coordinates, the keys and the linear scan over the nonzeros.  No blocking, fusion or reordering beyond what
  * those definitions state.
  *
  * Conventions (the paper is silent on them; each is a stated reading):
@@ -238,6 +239,33 @@ void orc_keys(const uint64_t *points, int d, const int64_t *which, int64_t npick
     }
 }
 
+/* The same keys for points given by their nonzero coordinates (Sec. 3.2's
+ * sparse setting): point i has the coordinates cols[ptr[i] .. ptr[i+1]) set
+ * and no others.  The key of table T = p*(D-1)+(v-1) sums b_c over the set
+ * coordinates c of part p whose Hadamard column has <col[c], v> = 1, i.e.
+ * over the set coordinates under the mask g_v, mod P: Eq. (1) restricted to
+ * the nonzeros, O(nnz L) per point.  keys[T*m + i] for the m points. */
+void orc_keys_sparse(const int64_t *ptr, const int32_t *cols, int64_t m,
+                     int t, int rp, const int32_t *part, const int32_t *col,
+                     const uint64_t *b, uint64_t P, uint32_t *keys)
+{
+    int32_t D = 1 << (rp + 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; i++) {
+        for (int p = 0; p < t; p++)
+            for (int32_t v = 1; v < D; v++) {
+                uint64_t s = 0;
+                for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) {
+                    int32_t c = cols[e];
+                    if (part[c] == p && orc_parity((uint32_t)v & (uint32_t)col[c]))
+                        s = (s + b[c]) % P;
+                }
+                int64_t T = (int64_t)p * (D - 1) + (v - 1);
+                keys[T * m + i] = (uint32_t)s;
+            }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Hash tables of non-empty buckets (Sec. 2.2)                               */
 /* ------------------------------------------------------------------------ */
@@ -404,6 +432,43 @@ void orc_brute_force(const uint64_t *points, int64_t n, int d,
                 c++;
             }
         counts[i] = c;
+    }
+}
+
+/* Linear scan over points given by their nonzero coordinates (as in
+ * orc_keys_sparse; d coordinates): the Hamming distance of two such points is
+ * the size of the symmetric difference of their coordinate sets,
+ * |X| + |Q| - 2 |X and Q|, the intersection counted with a d-entry marker of
+ * the query's coordinates.  Same output layout as orc_brute_force. */
+void orc_brute_force_sparse(const int64_t *ptr, const int32_t *cols, int64_t n,
+                            const int64_t *qptr, const int32_t *qcols, int64_t nq,
+                            int d, int rq, int64_t cap, uint32_t *out, int64_t *counts)
+{
+#pragma omp parallel
+    {
+        uint8_t *mark = (uint8_t *)calloc((size_t)(d > 0 ? d : 1), 1);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < nq; i++) {
+            int64_t nqi = qptr[i + 1] - qptr[i];
+            for (int64_t e = qptr[i]; e < qptr[i + 1]; e++)
+                mark[qcols[e]] = 1;
+            int64_t c = 0;
+            for (int64_t id = 0; id < n; id++) {
+                int64_t both = 0;
+                for (int64_t e = ptr[id]; e < ptr[id + 1]; e++)
+                    both += mark[cols[e]];
+                int64_t dist = (ptr[id + 1] - ptr[id]) + nqi - 2 * both;
+                if (dist <= rq) {
+                    if (c < cap)
+                        out[i * cap + c] = (uint32_t)id;
+                    c++;
+                }
+            }
+            counts[i] = c;
+            for (int64_t e = qptr[i]; e < qptr[i + 1]; e++)
+                mark[qcols[e]] = 0;
+        }
+        free(mark);
     }
 }
 

@@ -18,6 +18,13 @@ shapes, see the design notes for which stands in for what):
   hamming_balls          the synthetic sets of the precision/recall study
                          (Sec. 4.3): around each uniform query, points at
                          distances spread uniformly over 1..max_radius
+  sparse_planted         very high-dimensional sparse binary vectors (the
+                         bag-of-words and user-rating shapes of Table 2) as
+                         CSR rows of ascending nonzero coordinates, with
+                         neighbours planted around some queries
+
+Sparse layout: ptr int64 [n+1] (ptr[0] = 0), cols int32 [ptr[n]]; point i has
+the coordinates cols[ptr[i]:ptr[i+1]] set, ascending and distinct.
 """
 from __future__ import annotations
 
@@ -229,6 +236,148 @@ def fig3_replication(scale: float = 1.0) -> Workload:
     w = uniform_with_planted(n, 128, 3, nq, 10, seed=1007, name="fig3_replication")
     w.meta["replicate"] = 3
     return w
+
+
+# ---------------------------------------------------------------------------
+# Sparse high-dimensional workloads
+# ---------------------------------------------------------------------------
+
+def csr_to_words(ptr: np.ndarray, cols: np.ndarray, d: int) -> np.ndarray:
+    """CSR rows -> packed uint64 [n, W] (coordinate c = bit c&63 of word c>>6)."""
+    n = len(ptr) - 1
+    W = words(d)
+    out = np.zeros((n, W), np.uint64)
+    rows = np.repeat(np.arange(n), np.diff(ptr))
+    c = np.asarray(cols, np.int64)
+    np.bitwise_or.at(out, (rows, c >> 6), np.left_shift(np.uint64(1), (c & 63).astype(np.uint64)))
+    return out
+
+
+def sparse_rows(n: int, d: int, mean_nnz: float, sigma: float, zipf_a: float,
+                rng: np.random.Generator) -> tuple[np.ndarray, np.ndarray]:
+    """n rows whose lengths are log-normal (mean about mean_nnz, shape sigma,
+    at least 1) and whose coordinates follow a Zipf-like popularity
+    (probability of the column of popularity rank k proportional to
+    (k+1)^-zipf_a, ranks shuffled over the d columns): each row draws twice
+    its length with replacement and keeps a random subset of that length of
+    its distinct columns (fewer if there are fewer).  Returns (ptr, cols)."""
+    mu = np.log(mean_nnz) - sigma * sigma / 2
+    k = np.clip(np.rint(rng.lognormal(mu, sigma, size=n)), 1, d).astype(np.int64)
+    w = (np.arange(d, dtype=np.float64) + 1.0) ** (-zipf_a)
+    cdf = np.cumsum(w[rng.permutation(d)])
+    cdf /= cdf[-1]
+    # twice the draws, then a random k of each row's distinct columns
+    rows = np.repeat(np.arange(n, dtype=np.int64), 2 * k)
+    c = np.minimum(np.searchsorted(cdf, rng.random(rows.size), side="right"), d - 1)
+    pair = np.unique(rows * d + c)
+    r_of, c_of = pair // d, pair % d
+    # (pairs are in (row, column) order; rank them within a row at random)
+    order = np.argsort(r_of + rng.random(pair.size), kind="stable")
+    first = np.searchsorted(r_of, np.arange(n))
+    keep = np.empty(pair.size, bool)
+    keep[order] = np.arange(pair.size) - first[r_of[order]] < k[r_of[order]]
+    r_of, c_of = r_of[keep], c_of[keep]
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, r_of + 1, 1)
+    return np.cumsum(ptr), c_of.astype(np.int32)
+
+
+def perturb_row(row: np.ndarray, d: int, k: int, rng: np.random.Generator) -> np.ndarray:
+    """The row with k distinct coordinates flipped: each flip removes a
+    present coordinate or adds an absent one (even odds while both exist)."""
+    have = set(int(x) for x in row)
+    out = set(have)
+    touched = set()
+    while len(touched) < k:
+        if out & have - touched and (rng.random() < 0.5 or len(touched) >= d - len(have)):
+            c = int(rng.choice(sorted(out & have - touched)))
+            out.discard(c)
+        else:
+            c = int(rng.integers(0, d))
+            if c in have or c in touched:
+                continue
+            out.add(c)
+        touched.add(c)
+    return np.array(sorted(out), np.int32)
+
+
+@dataclass
+class SparseWorkload:
+    name: str
+    d: int
+    r: int
+    ptr: np.ndarray    # int64 [n+1]
+    cols: np.ndarray   # int32 [nnz]
+    qptr: np.ndarray   # int64 [nq+1]
+    qcols: np.ndarray  # int32 [qnnz]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(len(self.ptr) - 1)
+
+    @property
+    def nq(self) -> int:
+        return int(len(self.qptr) - 1)
+
+    def dense_points(self) -> np.ndarray:
+        return csr_to_words(self.ptr, self.cols, self.d)
+
+    def dense_queries(self) -> np.ndarray:
+        return csr_to_words(self.qptr, self.qcols, self.d)
+
+
+def _rows_to_csr(rows) -> tuple[np.ndarray, np.ndarray]:
+    ptr = np.zeros(len(rows) + 1, np.int64)
+    ptr[1:] = np.cumsum([len(x) for x in rows])
+    cols = np.concatenate(rows).astype(np.int32) if rows else np.zeros(0, np.int32)
+    return ptr, cols
+
+
+def sparse_planted(n: int, d: int, r: int, nq: int, mean_nnz: float, sigma: float, zipf_a: float,
+                   planted_queries: int, per_query: int, seed: int, name: str = "sparse") -> SparseWorkload:
+    """n + nq rows from sparse_rows; the last nq are the queries (held out
+    from the data, as the paper draws its queries from the data sets).
+    Around each of the first planted_queries queries, per_query data rows
+    are replaced by the query with k ~ U{0..r} coordinates flipped."""
+    rng = np.random.default_rng(seed)
+    ptr, cols = sparse_rows(n + nq, d, mean_nnz, sigma, zipf_a, rng)
+    rows = [cols[ptr[i]:ptr[i + 1]] for i in range(n + nq)]
+    data, queries = rows[:n], rows[n:]
+    need = planted_queries * per_query
+    if need > n:
+        raise ValueError("not enough points to plant neighbours")
+    slots = rng.choice(n, size=need, replace=False).reshape(planted_queries, per_query) if need else \
+        np.zeros((planted_queries, 0), np.int64)
+    for j in range(planted_queries):
+        for s in slots[j]:
+            data[int(s)] = perturb_row(queries[j], d, int(rng.integers(0, r + 1)), rng)
+    p, c = _rows_to_csr(data)
+    qp, qc = _rows_to_csr(queries)
+    return SparseWorkload(name, d, r, p, c, qp, qc, {"planted": slots, "seed": seed, "mean_nnz": mean_nnz})
+
+
+def enron_like(scale: float = 1.0, r: int = 29) -> SparseWorkload:
+    """Bag-of-words shape (Table 2's Enron): n = 40,000 documents over
+    d = 28,102 words, about 150 distinct words per document (log-normal
+    lengths, Zipf word frequencies), 100 queries, 20 of them with 5 planted
+    neighbours within r."""
+    n = max(500, int(40_000 * scale))
+    nq = max(8, int(100 * scale))
+    return sparse_planted(n, 28_102, r, nq, 150.0, 0.8, 1.0, min(nq, 20), 5, seed=1101, name="enron_like")
+
+
+def movielens_like(scale: float = 1.0, r: int = 13) -> SparseWorkload:
+    """User-rating shape (Table 2's MovieLens): n = 234,834 users over
+    d = 140,214 movies, about 80 positive ratings per user with a heavy tail
+    (log-normal, shape 1.2; Zipf movie popularity), 100 queries, 20 of them
+    with 5 planted neighbours within r."""
+    n = max(500, int(234_834 * scale))
+    nq = max(8, int(100 * scale))
+    return sparse_planted(n, 140_214, r, nq, 80.0, 1.2, 0.9, min(nq, 20), 5, seed=1102, name="movielens_like")
+
+
+SPARSE_WORKLOADS = {"enron_like": enron_like, "movielens_like": movielens_like}
 
 
 WORKLOADS = {"small": small, "mid": mid, "learned_code": learned_code, "batched": batched,

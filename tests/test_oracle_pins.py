@@ -504,3 +504,57 @@ def test_query_smaller_radius_is_exact():
         bf = oracle.brute_force(w.points, w.d, w.queries, rq)
         for i in range(w.nq):
             assert np.array_equal(res.ids[i], bf.ids[i])
+
+
+# --------------------------------------------------------------------------
+# Points given by their nonzero coordinates (Sec. 3.2's sparse setting): the
+# sparse keys and linear scan reduce to the dense ones on the same points,
+# which are pinned above.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,r,t,seed", [(700, 9, 0, 21), (3000, 29, 3, 22), (257, 4, 0, 23), (1500, 13, 2, 24)])
+def test_sparse_keys_equal_dense_keys(d, r, t, seed):
+    rng = np.random.default_rng(seed)
+    ptr, cols = synth.sparse_rows(40, d, 25.0, 1.0, 0.9, rng)
+    ptr = np.concatenate([ptr, [ptr[-1]]])  # and an empty row
+    pr = oracle.derive_params(d, r, seed, override_t=t)
+    dense = synth.csr_to_words(ptr, cols, d)
+    assert np.array_equal(oracle.keys_sparse(ptr, cols, pr), oracle.keys(dense, pr))
+
+
+def test_sparse_keys_closed_forms():
+    # one set coordinate c: key b_c in the tables of its part whose codeword
+    # has a one in its column, 0 elsewhere; no coordinate: all keys 0
+    d, r = 200, 11
+    pr = oracle.derive_params(d, r, 31, override_t=2)
+    ptr = np.array([0, 1, 1], np.int64)
+    for c in (0, 57, 199):
+        k = oracle.keys_sparse(ptr, np.array([c], np.int32), pr)
+        for p in range(pr.t):
+            for v in range(1, pr.D):
+                T = p * pr.Lp + v - 1
+                on = p == pr.part[c] and bin(v & int(pr.col[c])).count("1") % 2 == 1
+                assert int(k[T, 0]) == (int(pr.b[c]) if on else 0)
+        assert not k[:, 1].any()
+
+
+def test_sparse_brute_force_equal_dense():
+    rng = np.random.default_rng(25)
+    d = 5000
+    ptr, cols = synth.sparse_rows(300, d, 12.0, 1.2, 1.1, rng)
+    qptr, qcols = synth.sparse_rows(10, d, 12.0, 1.2, 1.1, rng)
+    for rq in (0, 3, 12, 40):
+        want = oracle.brute_force(synth.csr_to_words(ptr, cols, d), d, synth.csr_to_words(qptr, qcols, d), rq)
+        got = oracle.brute_force_sparse(ptr, cols, qptr, qcols, d, rq)
+        assert np.array_equal(got.counts, want.counts)
+        for a, b in zip(got.ids, want.ids):
+            assert np.array_equal(a, b)
+
+
+def test_sparse_brute_force_tiny_sets():
+    # distance = size of the symmetric difference of the coordinate sets
+    ptr = np.array([0, 2, 5, 5], np.int64)
+    cols = np.array([1, 9, 1, 2, 9], np.int32)
+    qptr = np.array([0, 1], np.int64)
+    res = oracle.brute_force_sparse(ptr, cols, qptr, np.array([9], np.int32), 10, 1)
+    assert list(res.ids[0]) == [0, 2]  # {1,9}: 1 away, {1,2,9}: 2, {}: 1

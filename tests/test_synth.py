@@ -33,3 +33,26 @@ def test_uniform_with_planted_distances():
     for j in range(30):
         dist = _popcount_rows(w.points[planted[j]] ^ w.queries[j])
         assert dist.max() <= 8
+
+
+def test_sparse_rows_valid_csr():
+    rng = np.random.default_rng(5)
+    ptr, cols = synth.sparse_rows(500, 3000, 40.0, 1.0, 1.0, rng)
+    assert ptr[0] == 0 and ptr[-1] == cols.size and np.all(np.diff(ptr) >= 1)
+    for i in range(500):
+        row = cols[ptr[i]:ptr[i + 1]]
+        assert np.all(np.diff(row) > 0) and row.min() >= 0 and row.max() < 3000
+    assert 30 < np.diff(ptr).mean() < 50
+
+
+def test_sparse_planted_neighbours_within_radius():
+    w = synth.enron_like(0.02, r=9)
+    assert w.nq >= 8 and w.d == 28_102
+    for j, slots in enumerate(w.meta["planted"]):
+        q = set(w.qcols[w.qptr[j]:w.qptr[j + 1]].tolist())
+        for s in slots:
+            x = set(w.cols[w.ptr[s]:w.ptr[s + 1]].tolist())
+            assert len(q ^ x) <= 9
+    dense = w.dense_points()
+    assert dense.shape == (w.n, (w.d + 63) // 64)
+    assert int(sum(bin(int(v)).count("1") for v in dense[3])) == w.ptr[4] - w.ptr[3]
