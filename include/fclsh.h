@@ -13,6 +13,10 @@
  *  - Points and queries are bit vectors of d coordinates, packed row-major as
  *    W = ceil(d/64) uint64 words per vector; coordinate c is bit (c & 63) of
  *    word (c >> 6).  Bits beyond d in the last word are ignored.
+ *  - A sparse index (fclsh_build_index_sparse) takes its points and queries
+ *    as rows of nonzero coordinates instead (the "_sparse" calls, layout
+ *    given there); every call on bit vectors rejects it with FCLSH_EINVAL,
+ *    and every "_sparse" call rejects a dense index.
  *  - Pointers named d_* are DEVICE pointers (HIP device memory of the current
  *    device); all others are host pointers.  Input buffers stay owned by the
  *    caller and are only read during the call (and, for asynchronous calls,
@@ -115,7 +119,9 @@ typedef struct {
  *
  * Outputs (host arrays of d' entries, d' = d without replication): part[c]
  * in [0,t), col[c] in [0, 2^(r'+1)), b[c] in [0, P).  *t_out and
- * *r_part_out receive t and r'.
+ * *r_part_out receive t and r'.  d up to 4096 (replicated: d' up to 4096)
+ * for indexes on bit vectors, up to 2^19 for sparse indexes (whose draws are
+ * the same; replication is not offered for them).
  * Errors: FCLSH_EINVAL (d <= 0, r < 0, null pointer), FCLSH_EUNSUPPORTED
  * (r' > 11, t > 64 or t > d, prime other than 2^31-1).
  * ------------------------------------------------------------------------- */
@@ -169,6 +175,50 @@ FCLSH_API fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, i
                                            const int32_t *col, const uint64_t *b,
                                            uint64_t prime, void *stream,
                                            fclsh_index *out);
+
+/* ---------------------------------------------------------------------------
+ * Sparse high-dimensional points (the bag-of-words and rating data of
+ * Sec. 4, where Alg. 2 costs O(nnz + L log L) per point: its sketch only
+ * sums over the nonzero coordinates).
+ *
+ * Rows: d_ptr (device, m+1 int64) and d_cols (device, nnz int32); row i is
+ * the point whose coordinates d_cols[d_ptr[i] .. d_ptr[i+1]) are 1 and all
+ * others 0.  d_ptr[0] = 0, d_ptr[m] = nnz, non-decreasing; each row's columns
+ * strictly ascending and in [0, d).  nnz < 2^31.  d in [1, 2^19] (so a
+ * point's sketch stays below 2^51 and the FHT exact in fp64).
+ *
+ * fclsh_build_index_sparse: as fclsh_build_index (same parameters for the
+ * same d, r, seed and opts; opts->replicate must be 0 or 1).  The rows are
+ * checked first (one device pass and a synchronisation); malformed rows give
+ * FCLSH_EINVAL.  The index keeps its own copy of the rows (8 (n+1) + 4 nnz
+ * bytes in place of the bit vectors).
+ * Errors: FCLSH_EINVAL, FCLSH_EUNSUPPORTED, FCLSH_ENOMEM, FCLSH_EDEVICE.
+ * ------------------------------------------------------------------------- */
+FCLSH_API fclsh_status fclsh_build_index_sparse(const int64_t *d_ptr, const int32_t *d_cols,
+                                                int64_t n, int64_t nnz, int32_t d, int32_t r,
+                                                uint64_t seed, const fclsh_build_opts *opts,
+                                                void *stream, fclsh_index *out);
+
+/* Alg. 2 on m rows: their L keys under the index's family, laid out as in
+ * fclsh_hash (d_keys: device [L][m] uint32), equal to the keys of the same
+ * points given as bit vectors.  Asynchronous; rows are not checked (a row is
+ * clamped to [0, nnz) and columns outside [0, d) are skipped, so malformed
+ * rows give meaningless keys, never stray memory accesses).  Sparse index
+ * only. */
+FCLSH_API fclsh_status fclsh_hash_sparse(fclsh_index idx, const int64_t *d_ptr,
+                                         const int32_t *d_cols, int64_t m, int64_t nnz,
+                                         uint32_t *d_keys, void *stream);
+
+/* fclsh_query_batch for nq queries given as rows (sparse index only): the
+ * same outputs, ids ascending per query, and the same FCLSH_ECAPACITY
+ * protocol (fclsh_query_batch_finish applies).  The rows are checked on the
+ * device within the batch; malformed rows give FCLSH_EINVAL.  The stream's
+ * workspace also holds the queries as bit vectors (nq * ceil(d/64) words). */
+FCLSH_API fclsh_status fclsh_query_batch_sparse(fclsh_index idx, const int64_t *d_ptr,
+                                                const int32_t *d_cols, int64_t nq, int64_t nnz,
+                                                int32_t r_query, void *stream,
+                                                uint64_t *d_offsets, uint32_t *d_ids,
+                                                int64_t ids_capacity, int64_t *total_out);
 
 /* ---------------------------------------------------------------------------
  * Exact r-NN reporting for a batch of queries (Def. 2, Strategy 2 of

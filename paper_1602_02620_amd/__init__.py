@@ -8,6 +8,9 @@ call raises.
     idx = Index(points, d=256, r=8, seed=3002)       # points: int64 [n, W] on the GPU
     offsets, ids = idx.query(queries, r=8)           # CSR: ids of query i in ids[offsets[i]:offsets[i+1]]
     keys = idx.hash(points)                          # [L, n] uint32 keys (as int32 storage)
+
+    sidx = SparseIndex(ptr, cols, d=28102, r=29)     # rows of nonzero coordinates (int64 / int32 on the GPU)
+    offsets, ids = sidx.query(qptr, qcols, r=29)
 """
 from __future__ import annotations
 
@@ -36,7 +39,8 @@ EXPORTS = [
     "fclsh_graph_launch", "fclsh_graph_free", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
     "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
     "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
-    "fclsh_query_batch_noalloc", "fclsh_linear_scan",
+    "fclsh_query_batch_noalloc", "fclsh_linear_scan", "fclsh_build_index_sparse", "fclsh_hash_sparse",
+    "fclsh_query_batch_sparse",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -107,6 +111,9 @@ def lib():
             "fclsh_index_set_tuning": [vp, i32, i32],
             "fclsh_index_get_tuning": [vp, P(i32), P(i32)],
             "fclsh_autotune": [vp, vp, i64, i32, vp, P(i32), P(i32), P(ctypes.c_float)],
+            "fclsh_build_index_sparse": [vp, vp, i64, i64, i32, i32, u64, P(BuildOpts), vp, P(vp)],
+            "fclsh_hash_sparse": [vp, vp, vp, i64, i64, vp, vp],
+            "fclsh_query_batch_sparse": [vp, vp, vp, i64, i64, i32, vp, vp, vp, i64, P(i64)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -476,6 +483,70 @@ class Index:
         _check(lib().fclsh_query_cost(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0], _stream_ptr(stream),
                                       ctypes.c_void_p(coll.data_ptr()), ctypes.c_void_p(cand.data_ptr())))
         return coll, cand
+
+
+def to_device_rows(ptr: np.ndarray, cols: np.ndarray, device="cuda"):
+    """numpy CSR rows -> (int64 [m+1], int32 [nnz]) CUDA tensors."""
+    torch = _torch()
+    return (torch.from_numpy(np.ascontiguousarray(ptr, np.int64)).to(device),
+            torch.from_numpy(np.ascontiguousarray(cols, np.int32)).to(device))
+
+
+def _dev_rows(ptr, cols, what: str):
+    torch = _torch()
+    for x, dt, nm in ((ptr, torch.int64, "ptr"), (cols, torch.int32, "cols")):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != dt or x.dim() != 1:
+            raise TypeError(f"{what} {nm} must be a 1-D {dt} CUDA tensor")
+    if ptr.numel() < 1:
+        raise ValueError(f"{what} ptr needs m+1 >= 1 entries")
+    return ptr.contiguous(), cols.contiguous()
+
+
+class SparseIndex(Index):
+    """An exact r-NN index over points given as rows of nonzero coordinates
+    (fclsh_build_index_sparse): ptr int64 [n+1], cols int32 [nnz] CUDA
+    tensors, d up to 2^19.  Queries are rows too."""
+
+    def __init__(self, ptr, cols, d: int, r: int, seed: int = 0, partitions: int = 0, mem_budget_bytes: int = 0,
+                 stream=None, *, exclude_column0: bool = False, keep_build_scratch: bool = False):
+        ptr, cols = _dev_rows(ptr, cols, "points")
+        h = ctypes.c_void_p()
+        opts = BuildOpts.make(partitions, 0, exclude_column0, mem_budget_bytes, keep_build_scratch)
+        _check(lib().fclsh_build_index_sparse(ctypes.c_void_p(ptr.data_ptr()), ctypes.c_void_p(cols.data_ptr()),
+                                              ptr.numel() - 1, cols.numel(), d, r, seed & (2**64 - 1),
+                                              ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.d = d
+        self.replicate = 1
+        self.device = ptr.device
+        self._ids_per_query = 64.0
+
+    def hash(self, ptr, cols, out=None, stream=None):
+        """[L, m] keys (int32 storage) of m rows."""
+        torch = _torch()
+        ptr, cols = _dev_rows(ptr, cols, "points")
+        m = ptr.numel() - 1
+        if out is None:
+            out = torch.empty((self.info["L"], m), dtype=torch.int32, device=ptr.device)
+        _check(lib().fclsh_hash_sparse(self._h, ctypes.c_void_p(ptr.data_ptr()), ctypes.c_void_p(cols.data_ptr()), m,
+                                       cols.numel(), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def query(self, ptr, cols, r: int, ids_capacity=None, stream=None):
+        """Exact r-NN reporting for a batch of query rows: (offsets int64
+        [nq+1], ids int32 [total])."""
+        torch = _torch()
+        ptr, cols = _dev_rows(ptr, cols, "queries")
+        nq = ptr.numel() - 1
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=ptr.device)
+        cap = int(ids_capacity) if ids_capacity is not None else self._default_capacity(nq)
+        total = ctypes.c_int64()
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=ptr.device)
+        st = lib().fclsh_query_batch_sparse(self._h, ctypes.c_void_p(ptr.data_ptr()), ctypes.c_void_p(cols.data_ptr()),
+                                            nq, cols.numel(), r, _stream_ptr(stream),
+                                            ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                                            cap, ctypes.byref(total))
+        return self._collect(st, offsets, ids, total, nq, stream, True, ids_capacity is not None)
 
 
 class QueryGraph:

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfclsh.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["params.cpp", "hash.hip", "scan.hip", "tables.hip", "query.hip", "linear.hip", "api.hip"]
+SOURCES = ["params.cpp", "hash.hip", "scan.hip", "tables.hip", "query.hip", "linear.hip", "rows.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall", "-fvisibility=hidden",

@@ -129,9 +129,9 @@ static void destroy_handle(IndexHandle *h) {
 
 static void lookup_tuning(Index &ix);
 
-static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int dir_bits) {
+static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int64_t nnz, int dir_bits) {
     const size_t L = size_t(p.L());
-    size_t b = size_t(n) * W * 8;                        // point copy
+    size_t b = p.sparse ? size_t(n + 1) * 8 + size_t(nnz) * 4 : size_t(n) * W * 8;  // point copy
     b += 2 * L * size_t(n) * 4;                          // table keys + ids
     b += L * ((size_t(1) << dir_bits) + 1) * 4;          // directories
     b += 3 * L * size_t(n) * 4;                          // build scratch: keys + 2 partition buffers
@@ -184,7 +184,10 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
     FCLSH_TRY(take_build_counts(h));
     FCLSH_TRY(alloc_build_scratch(h));
     if (marks) FCLSH_HIP(hipEventRecord(marks[0], st));
-    FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
+    if (ix.prm.sparse)
+        FCLSH_TRY(launch_hash_sparse(ix, CsrRows{ix.sptr, ix.scols, ix.nnz}, ix.n, h->keys, ix.n, st));
+    else
+        FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
                                  ix.build_mode, st, marks ? marks + 2 : nullptr));
@@ -201,11 +204,39 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
     return FCLSH_OK;
 }
 
-static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&prm, uint64_t budget,
-                                 bool keep_scratch, hipStream_t st, fclsh_index *out) {
+// The device rows of a sparse build, checked before the index copies them.
+static fclsh_status check_rows(const CsrRows &rows, int64_t m, int d, hipStream_t st) {
+    uint32_t *flag = nullptr;
+    if (hipMalloc(&flag, sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FCLSH_ENOMEM, "device allocation of a check flag failed");
+    }
+    uint32_t bad = 0;
+    fclsh_status s = FCLSH_OK;
+    if (hipMemsetAsync(flag, 0, sizeof(uint32_t), st) != hipSuccess) s = fail(FCLSH_EDEVICE, "hipMemsetAsync failed");
+    if (s == FCLSH_OK) s = csr_check(rows, m, d, flag, 0, st);
+    if (s == FCLSH_OK && (hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                          hipStreamSynchronize(st) != hipSuccess))
+        s = fail(FCLSH_EDEVICE, "reading the row check failed");
+    (void)hipFree(flag);
+    if (s != FCLSH_OK) return s;
+    if (bad)
+        return fail(FCLSH_EINVAL, "malformed rows:%s%s%s", bad & kCsrBadPtr ? " bad row bounds" : "",
+                    bad & kCsrBadCol ? " column outside [0, d)" : "",
+                    bad & kCsrBadOrder ? " columns not strictly ascending" : "");
+    return FCLSH_OK;
+}
+
+// d_points (dense [n][W] words) or rows (sparse; prm.sparse) is the input.
+static fclsh_status build_common(const uint64_t *d_points, const CsrRows *rows, int64_t n, Params &&prm,
+                                 uint64_t budget, bool keep_scratch, hipStream_t st, fclsh_index *out) {
     if (!out) return fail(FCLSH_EINVAL, "out is null");
     *out = nullptr;
-    if (!d_points) return fail(FCLSH_EINVAL, "d_points is null");
+    if (prm.sparse != (rows != nullptr)) return fail(FCLSH_EINVAL, "point format does not match the parameters");
+    if (!rows && !d_points) return fail(FCLSH_EINVAL, "d_points is null");
+    if (rows && (!rows->ptr || rows->nnz < 0 || (rows->nnz > 0 && !rows->cols)))
+        return fail(FCLSH_EINVAL, "null row arrays or negative nnz");
+    if (rows && rows->nnz > 0x7FFFFFFFll) return fail(FCLSH_EUNSUPPORTED, "nnz above 2^31-1");
     if (n < 1 || n > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
     FCLSH_TRY(check_params(prm));
     if (int64_t(prm.L()) > 65535) return fail(FCLSH_EUNSUPPORTED, "L=%d tables exceed 65535", prm.L());
@@ -229,16 +260,24 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
         destroy_handle(h);
         return s;
     };
+    if (rows) ix.nnz = rows->nnz;
     if (budget) {
-        const size_t need = estimate_index_bytes(ix.prm, n, ix.W, ix.dir_bits);
+        const size_t need = estimate_index_bytes(ix.prm, n, ix.W, ix.nnz, ix.dir_bits);
         if (need > budget)
             return bail(fail(FCLSH_ENOMEM, "index needs about %zu bytes, budget is %llu", need,
                              (unsigned long long)budget));
     }
     const int64_t L = ix.prm.L();
     fclsh_status s;
-    if ((s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.pts), size_t(n) * ix.W * 8, "points")) ||
-        (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tkeys), size_t(L * n) * 4, "table keys")) ||
+    if (rows && (s = check_rows(*rows, n, ix.prm.d, st))) return bail(s);
+    if (rows) {
+        if ((s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.sptr), size_t(n + 1) * 8, "point rows")) ||
+            (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.scols), size_t(ix.nnz) * 4, "point columns")))
+            return bail(s);
+    } else if ((s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.pts), size_t(n) * ix.W * 8, "points"))) {
+        return bail(s);
+    }
+    if ((s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tkeys), size_t(L * n) * 4, "table keys")) ||
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tids), size_t(L * n) * 4, "table ids")) ||
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dir),
                        size_t(L) * ((size_t(1) << ix.dir_bits) + 1) * 4, "directory")) ||
@@ -254,11 +293,18 @@ static fclsh_status build_common(const uint64_t *d_points, int64_t n, Params &&p
         if (hipMemcpy(ix.dpc, pc.data(), pc.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(FCLSH_EDEVICE, "parameter upload failed"));
     }
-    const int64_t total = n * ix.W;
-    unsigned g = unsigned(std::min<int64_t>((total + 255) / 256, 65536));
-    hipLaunchKernelGGL(copy_points_kernel, dim3(g), dim3(256), 0, st, d_points, ix.pts, total, ix.W,
-                       last_word_mask(ix.prm.d));
-    if (hipGetLastError() != hipSuccess) return bail(fail(FCLSH_EDEVICE, "point copy launch failed"));
+    if (rows) {
+        if (hipMemcpyAsync(ix.sptr, rows->ptr, size_t(n + 1) * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            (ix.nnz > 0 &&
+             hipMemcpyAsync(ix.scols, rows->cols, size_t(ix.nnz) * 4, hipMemcpyDeviceToDevice, st) != hipSuccess))
+            return bail(fail(FCLSH_EDEVICE, "point row copy failed"));
+    } else {
+        const int64_t total = n * ix.W;
+        unsigned g = unsigned(std::min<int64_t>((total + 255) / 256, 65536));
+        hipLaunchKernelGGL(copy_points_kernel, dim3(g), dim3(256), 0, st, d_points, ix.pts, total, ix.W,
+                           last_word_mask(ix.prm.d));
+        if (hipGetLastError() != hipSuccess) return bail(fail(FCLSH_EDEVICE, "point copy launch failed"));
+    }
     if ((s = hash_and_bucket(h, st))) return bail(s);
     *out = reinterpret_cast<fclsh_index>(h);
     return FCLSH_OK;
@@ -377,6 +423,16 @@ static bool usable(fclsh_index idx) {
     return idx && !reinterpret_cast<IndexHandle *>(idx)->released;
 }
 
+// A usable handle whose points have the format of the call (dense words or
+// sparse rows).
+static fclsh_status need_format(fclsh_index idx, bool sparse) {
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    if (reinterpret_cast<IndexHandle *>(idx)->ix.prm.sparse != sparse)
+        return fail(FCLSH_EINVAL, sparse ? "the index holds dense points: use the calls on bit vectors"
+                                         : "the index holds sparse points: use the calls on rows");
+    return FCLSH_OK;
+}
+
 }  // namespace fclsh
 
 using namespace fclsh;
@@ -399,11 +455,13 @@ fclsh_status fclsh_preprocessing(int64_t n, int32_t r, double c, int32_t *replic
 fclsh_status fclsh_derive_params(int32_t d, int32_t r, uint64_t seed, const fclsh_build_opts *opts,
                                  int32_t *t_out, int32_t *r_part_out, int32_t *part, int32_t *col, uint64_t *b) {
     if (!t_out || !r_part_out || !part || !col || !b) return fail(FCLSH_EINVAL, "null output pointer");
-    if (d > kMaxDims) return fail(FCLSH_EUNSUPPORTED, "d=%d exceeds %d", d, kMaxDims);
+    if (d > kMaxSparseDims) return fail(FCLSH_EUNSUPPORTED, "d=%d exceeds %d", d, kMaxSparseDims);
     fclsh_build_opts o;
     FCLSH_TRY(read_opts(opts, &o));
     Params p;
-    FCLSH_TRY(derive_params(d, r, seed, &o, &p));
+    // the draws do not depend on the point format; d above kMaxDims is for
+    // sparse points only
+    FCLSH_TRY(derive_params(d, r, seed, &o, &p, d > kMaxDims));
     *t_out = p.t;
     *r_part_out = p.rp;
     for (int c = 0; c < p.dd(); ++c) {
@@ -422,7 +480,21 @@ fclsh_status fclsh_build_index(const uint64_t *d_points, int64_t n, int32_t d, i
     FCLSH_TRY(read_opts(opts, &o));
     Params p;
     FCLSH_TRY(derive_params(d, r, seed, &o, &p));
-    return build_common(d_points, n, std::move(p), o.mem_budget_bytes, o.keep_build_scratch != 0,
+    return build_common(d_points, nullptr, n, std::move(p), o.mem_budget_bytes, o.keep_build_scratch != 0,
+                        reinterpret_cast<hipStream_t>(stream), out);
+}
+
+fclsh_status fclsh_build_index_sparse(const int64_t *d_ptr, const int32_t *d_cols, int64_t n, int64_t nnz, int32_t d,
+                                      int32_t r, uint64_t seed, const fclsh_build_opts *opts, void *stream,
+                                      fclsh_index *out) {
+    if (out) *out = nullptr;
+    if (d > kMaxSparseDims) return fail(FCLSH_EUNSUPPORTED, "d=%d exceeds %d", d, kMaxSparseDims);
+    fclsh_build_opts o;
+    FCLSH_TRY(read_opts(opts, &o));
+    Params p;
+    FCLSH_TRY(derive_params(d, r, seed, &o, &p, true));
+    const CsrRows rows{d_ptr, d_cols, nnz};
+    return build_common(nullptr, &rows, n, std::move(p), o.mem_budget_bytes, o.keep_build_scratch != 0,
                         reinterpret_cast<hipStream_t>(stream), out);
 }
 
@@ -441,7 +513,7 @@ fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, int64_t n, 
     p.part.assign(part, part + d);
     p.col.assign(col, col + d);
     p.b.assign(b, b + d);
-    return build_common(d_points, n, std::move(p), 0, false, reinterpret_cast<hipStream_t>(stream), out);
+    return build_common(d_points, nullptr, n, std::move(p), 0, false, reinterpret_cast<hipStream_t>(stream), out);
 }
 
 void fclsh_index_free(fclsh_index idx) {
@@ -506,10 +578,19 @@ fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_t *col, ui
 }
 
 fclsh_status fclsh_hash(fclsh_index idx, const uint64_t *d_pts, int64_t m, uint32_t *d_keys, void *stream) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (m < 0 || m > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "m=%lld out of range", (long long)m);
     if (m && (!d_pts || !d_keys)) return fail(FCLSH_EINVAL, "null buffer");
     return launch_hash(handle(idx)->ix, d_pts, m, d_keys, m, reinterpret_cast<hipStream_t>(stream));
+}
+
+fclsh_status fclsh_hash_sparse(fclsh_index idx, const int64_t *d_ptr, const int32_t *d_cols, int64_t m, int64_t nnz,
+                               uint32_t *d_keys, void *stream) {
+    FCLSH_TRY(need_format(idx, true));
+    if (m < 0 || m > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "m=%lld out of range", (long long)m);
+    if (nnz < 0 || (m && (!d_ptr || !d_keys)) || (nnz > 0 && !d_cols)) return fail(FCLSH_EINVAL, "bad buffers");
+    return launch_hash_sparse(handle(idx)->ix, CsrRows{d_ptr, d_cols, nnz}, m, d_keys, m,
+                              reinterpret_cast<hipStream_t>(stream));
 }
 
 fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const uint32_t **d_tids,
@@ -563,10 +644,28 @@ fclsh_status fclsh_index_rebuild_timed(fclsh_index idx, void *stream, float *pha
     return s;
 }
 
+fclsh_status fclsh_query_batch_sparse(fclsh_index idx, const int64_t *d_ptr, const int32_t *d_cols, int64_t nq,
+                                      int64_t nnz, int32_t r_query, void *stream, uint64_t *d_offsets,
+                                      uint32_t *d_ids, int64_t ids_capacity, int64_t *total_out) {
+    FCLSH_TRY(need_format(idx, true));
+    if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
+    if (nq < 0 || nq > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "nq=%lld out of range", (long long)nq);
+    if (nnz < 0 || (nq && !d_ptr) || (nnz > 0 && !d_cols)) return fail(FCLSH_EINVAL, "bad query rows");
+    if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
+    IndexHandle *h = handle(idx);
+    if (r_query < 0) return fail(FCLSH_EINVAL, "negative query radius");
+    if (r_query > h->ix.prm.r)
+        return fail(FCLSH_ERADIUS, "query radius %d exceeds the index radius %d", r_query, h->ix.prm.r);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const CsrRows rows{d_ptr, d_cols, nnz};
+    return query_batch(h->ix, *h->workspace(st), nullptr, nq, r_query, nullptr, st, d_offsets, d_ids, ids_capacity,
+                       total_out, &rows);
+}
+
 fclsh_status fclsh_query_batch(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                void *stream, uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                int64_t *total_out) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || nq > 0x7FFFFFFFll) return fail(FCLSH_EINVAL, "nq=%lld out of range", (long long)nq);
     if (nq && !d_queries) return fail(FCLSH_EINVAL, "null queries");
@@ -592,7 +691,7 @@ fclsh_status fclsh_query_batch_finish(fclsh_index idx, void *stream, const uint6
 
 fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries, int64_t nq, void *stream,
                                     uint64_t *d_collisions) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (nq < 0 || (nq && (!d_queries || !d_collisions))) return fail(FCLSH_EINVAL, "bad arguments");
     if (nq == 0) return FCLSH_OK;
     IndexHandle *h = handle(idx);
@@ -602,7 +701,7 @@ fclsh_status fclsh_query_collisions(fclsh_index idx, const uint64_t *d_queries, 
 
 fclsh_status fclsh_query_cost(fclsh_index idx, const uint64_t *d_queries, int64_t nq, void *stream,
                               uint64_t *d_collisions, uint64_t *d_candidates) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (nq < 0 || nq > 0x7FFFFFFFll || (nq && (!d_queries || !d_collisions || !d_candidates)))
         return fail(FCLSH_EINVAL, "bad arguments");
     if (nq == 0) return FCLSH_OK;
@@ -634,7 +733,7 @@ fclsh_status fclsh_linear_scan(const uint64_t *d_points, int64_t n, int32_t d, c
 fclsh_status fclsh_query_plain(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                void *stream, uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                int64_t *total_out) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
     IndexHandle *h = handle(idx);
@@ -650,7 +749,7 @@ fclsh_status fclsh_query_batch_radii(fclsh_index idx, const uint64_t *d_queries,
                                      const int32_t *d_radii, int32_t max_radius, void *stream,
                                      uint64_t *d_offsets, uint32_t *d_ids, int64_t ids_capacity,
                                      int64_t *total_out) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (!total_out || !d_offsets) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || nq > 0x7FFFFFFFll || (nq && (!d_queries || !d_radii))) return fail(FCLSH_EINVAL, "bad queries");
     if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
@@ -676,7 +775,7 @@ fclsh_status fclsh_query_reserve(fclsh_index idx, int64_t max_nq, int64_t pair_c
 fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                      const int32_t *d_radii, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
                                      int64_t ids_capacity, uint64_t *d_result) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
     if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
@@ -693,7 +792,7 @@ fclsh_status fclsh_query_batch_async(fclsh_index idx, const uint64_t *d_queries,
 fclsh_status fclsh_query_batch_noalloc(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                                        const int32_t *d_radii, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
                                        int64_t ids_capacity, uint64_t *d_result) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || nq > 0x7FFFFFFFll || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
     if (ids_capacity < 0 || (ids_capacity > 0 && !d_ids)) return fail(FCLSH_EINVAL, "bad id buffer");
@@ -716,7 +815,7 @@ fclsh_status fclsh_query_graph_create(fclsh_index idx, const uint64_t *d_queries
                                       fclsh_graph *out) {
     if (!out) return fail(FCLSH_EINVAL, "null output pointer");
     *out = nullptr;
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (!stream) return fail(FCLSH_EINVAL, "graph capture needs a non-null stream");
     if (!d_offsets || !d_result) return fail(FCLSH_EINVAL, "null output pointer");
     if (nq < 0 || (nq && !d_queries)) return fail(FCLSH_EINVAL, "bad queries");
@@ -801,7 +900,7 @@ fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, int32_t *blo
 
 fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t nq, int32_t r_query,
                             void *stream, int32_t *tile_out, int32_t *blocks_out, float *best_ms_out) {
-    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    FCLSH_TRY(need_format(idx, false));
     if (nq < 1 || !d_queries) return fail(FCLSH_EINVAL, "autotuning needs a sample batch");
     IndexHandle *h = handle(idx);
     if (r_query < 0 || r_query > h->ix.prm.r) return fail(FCLSH_ERADIUS, "bad query radius");

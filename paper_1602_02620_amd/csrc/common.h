@@ -18,6 +18,11 @@ constexpr uint32_t kPrime = 0x7FFFFFFFu;
 constexpr int kMaxLogD = 12;
 constexpr int kMaxParts = 64;
 constexpr int kMaxDims = 4096;
+// Coordinates of points given by their nonzeros.  The sketch of such a point
+// sums at most d even representatives b'' < 2^32, so S'' < 2^51 and every
+// FHT value and S'' - F''_v (< 2^52) stay exact integers in fp64, with the
+// key extraction's exponent fixed at 2^52.
+constexpr int kMaxSparseDims = 1 << 19;
 
 void set_error(const char *fmt, ...);
 fclsh_status fail(fclsh_status st, const char *fmt, ...);
@@ -52,6 +57,7 @@ inline int ilog2_ceil(uint64_t x) {
 // bit c' mod d.  part, col and b have dd() entries.
 struct Params {
     int d = 0, r = 0, t = 1, rp = 0, rep = 1;
+    bool sparse = false;  // points given by their nonzero coordinates (d up to kMaxSparseDims)
     std::vector<int32_t> part, col;
     std::vector<uint64_t> b;
     int dd() const { return rep * d; }
@@ -61,7 +67,7 @@ struct Params {
 };
 
 fclsh_status derive_params(int d, int r, uint64_t seed, const fclsh_build_opts *opts,
-                           Params *out);
+                           Params *out, bool sparse = false);
 fclsh_status check_params(const Params &p);
 
 // ----------------------------------------------------------------------------
@@ -78,6 +84,18 @@ struct HashPlan {
     bool specific = true;        // at most one coordinate per Hadamard column
     int32_t *seg = nullptr;      // [t][V+1] entry ranges per in-lane column k
     uint2 *gtab = nullptr;       // [t][E][G] (even representative of b mod P, coordinate)
+    uint2 *coord = nullptr;      // sparse points: [d] (even representative, part << 16 | column)
+};
+
+// Points given by their nonzero coordinates: row i holds cols[ptr[i] ..
+// ptr[i+1]), ascending and distinct, each below d; ptr[0] = 0 and
+// ptr[m] = nnz.  Kernels clamp every row to [0, nnz) and skip columns
+// outside [0, d), so malformed rows give wrong answers, never stray accesses;
+// csr_check reports them.
+struct CsrRows {
+    const int64_t *ptr = nullptr;
+    const int32_t *cols = nullptr;
+    int64_t nnz = 0;
 };
 
 // Launch shape of the batched verify kernels, chosen by the autotuner.
@@ -111,6 +129,10 @@ struct Index {
     uint32_t *dir = nullptr;   // [L][2^dir_bits + 1]
     // per-index device copies of part/col for the duplicate-elimination rule
     uint32_t *dpc = nullptr;  // part(c) << 16 | column(c) per coordinate
+    // sparse points (prm.sparse): the index's copy of the rows, pts unused
+    int64_t *sptr = nullptr;   // [n+1]
+    int32_t *scols = nullptr;  // [nnz]
+    int64_t nnz = 0;
     std::vector<DevBuf> owned;
     size_t bytes_owned = 0;
 };
@@ -124,6 +146,18 @@ void dev_free_all(Index *ix);
 fclsh_status build_hash_plan(Index *ix);
 fclsh_status launch_hash(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys,
                          int64_t key_stride, hipStream_t st);
+// The same keys for m points given by their nonzeros (a sparse index).
+fclsh_status launch_hash_sparse(const Index &ix, const CsrRows &rows, int64_t m, uint32_t *keys, int64_t key_stride,
+                                hipStream_t st);
+// Checks m CSR rows over d coordinates on the device: ORs the kCsrBad* bits
+// found, shifted left by `shift`, into *flag (device word, not cleared here).
+constexpr uint32_t kCsrBadPtr = 1u;     // ptr[0] != 0, ptr[m] != nnz or a row ends before it starts
+constexpr uint32_t kCsrBadCol = 2u;     // a column outside [0, d)
+constexpr uint32_t kCsrBadOrder = 4u;   // a row's columns not strictly ascending
+fclsh_status csr_check(const CsrRows &rows, int64_t m, int d, uint32_t *flag, int shift, hipStream_t st);
+// The m rows as bit vectors of words_of(d) words each (out: m * words_of(d)
+// words, overwritten).
+fclsh_status csr_densify(const CsrRows &rows, int64_t m, int d, uint64_t *out, hipStream_t st);
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) in turn.  The
 // streaming kernels map workgroup b of a 1-D grid (a multiple of kXcds) to
@@ -168,6 +202,9 @@ struct QueryCtrl {
 constexpr uint32_t kQueryPairOverflow = 1u;
 constexpr uint32_t kQuerySpillOverflow = 2u;
 constexpr uint32_t kQueryIdsOverflow = 4u;
+// the sparse queries failed csr_check (its bits shifted by kQueryBadShift)
+constexpr int kQueryBadShift = 3;
+constexpr uint32_t kQueryBadRows = (kCsrBadPtr | kCsrBadCol | kCsrBadOrder) << kQueryBadShift;
 
 // Scratch of the query path for one index and stream, grown on demand.
 struct QueryWorkspace {
@@ -177,25 +214,29 @@ struct QueryWorkspace {
     QueryCtrl *ctrl = nullptr;
     uint32_t *pq = nullptr, *pid = nullptr, *sorttmp = nullptr;
     uint4 *spill = nullptr;
-    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0, cap_spill = 0;
+    uint64_t *qdense = nullptr;  // sparse queries as bit vectors
+    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0, cap_spill = 0, cap_qdense = 0;
     // a synchronous batch whose ids did not fit the caller's buffer: its
     // pairs stay here until the next query call on the stream
     int64_t pending_nq = -1, pending_total = 0;
     const uint64_t *pending_offsets = nullptr;
 };
 
-fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills);
+fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills,
+                        int64_t dense_words = 0);
 void ws_release(QueryWorkspace &ws);
 // A workspace laid out in one caller-owned device buffer (no allocation).
 fclsh_status ws_carve(QueryWorkspace &ws, void *base, size_t bytes, int64_t nq, int L);
 // Device bytes the workspace holds.
 uint64_t ws_bytes(const QueryWorkspace &ws);
+// queries: dense [nq][W] words, or null with sq the queries' rows (sparse
+// index).
 fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                                const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids,
-                               int64_t ids_cap);
+                               int64_t ids_cap, const CsrRows *sq = nullptr);
 fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                          const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap,
-                         int64_t *total_out);
+                         int64_t *total_out, const CsrRows *sq = nullptr);
 fclsh_status query_finish(Index &ix, QueryWorkspace &ws, hipStream_t st, const uint64_t *offsets, uint32_t *ids,
                           int64_t ids_cap, int64_t *total_out);
 fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,

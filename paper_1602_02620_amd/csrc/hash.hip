@@ -27,6 +27,12 @@
 // holds F_v for v = s*V + k (natural order).  Lanes are unit-fastest within a
 // wave, so for each k the lanes of one sub-index write consecutive points of
 // one table: keys are stored table-major [T][n], T = p*(D-1) + (v-1).
+//
+// Points given by their nonzero coordinates take a second kernel that builds
+// the sketch from the nonzeros alone (O(nnz + L log L) per point) and shares
+// the FHT, key extraction and write-out.
+#include <algorithm>
+
 #include "common.h"
 
 namespace fclsh {
@@ -158,6 +164,10 @@ __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
 template <int LOGD>
 constexpr int hash_waves() { return LOGD == 9 || LOGD == 10 ? 8 : LOGD == 11 ? 16 : 4; }
 
+// Waves per workgroup of the sparse kernel (its accumulators, 8 bytes per
+// column and point, take twice the stage's LDS).
+constexpr int kSparseWaves = 4;
+
 // LDS staging of a block's keys: rows indexed by the Hadamard row v in
 // [0, D) (row 0, the dropped all-zero codeword, is never written), each of
 // PB = NW*U points, row v at v*PB + (v >> SH)*PAD.  (PAD, SH) per order from
@@ -186,6 +196,104 @@ constexpr size_t stage_words() {
     return size_t(stage_index<LOGD, PB>((1 << LOGD) - 1, PB - 1)) + 1;
 }
 
+// Index bits of the output held by this lane (see Shape).
+template <int LOGD, int LOGV>
+__device__ inline int lane_rows(int lane) {
+    using S = Shape<LOGD, LOGV>;
+    int vlane = 0;
+#pragma unroll
+    for (int b = 0; b < S::LOGG; ++b)
+        if ((lane >> (S::LOGU + b)) & 1) vlane |= 1 << (S::swap_stage(b) ? S::swap_reg(b) : LOGV + b);
+    return vlane;
+}
+
+// The FHT of a unit's sketch (Alg. 2) and its keys h_v, v >= 1, into the
+// stage at column wave*U + u.  t holds the lane's V sketch entries.
+template <int LOGD, int LOGV, int NW>
+__device__ inline void fht_keys_to_stage(double (&t)[1 << LOGV], int lane, int wave, uint32_t *stage) {
+    using S = Shape<LOGD, LOGV>;
+    constexpr int V = S::V, U = S::U, PB = NW * U;
+    constexpr int PAD = stage_pad<LOGD>(), SH = stage_shift<LOGD>();
+    static_assert(SH <= S::LOGG, "the stage padding must split over lane and register index bits");
+    const int u = lane & (U - 1);
+    const int vlane = lane_rows<LOGD, LOGV>(lane);
+    // Fast Hadamard transform (Alg. 2): in-register stages ...
+#pragma unroll
+    for (int h = 1; h < V; h <<= 1) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (!(k & h)) {
+                const double a = t[k], b = t[k | h];
+                t[k] = a + b;
+                t[k | h] = a - b;
+            }
+        }
+    }
+    // ... then the stages across the G lanes of a unit, nearest partners
+    // first (the stages commute; this order keeps the register pressure of
+    // the DPP stages away from the key extraction)
+    cross_stages<LOGD, LOGV, 0>(t, lane);
+
+    // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
+    const double Sm = __shfl(t[0], u, 64) + kTwo52;
+    // stage_index(vlane | vr, wave * U + u), split into a lane base and a
+    // per-register constant
+    const int sbase = vlane * PB + (vlane >> SH) * PAD + wave * U + u;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int vr = S::vreg(k);
+        if (vr == 0 && vlane == 0) continue;  // row 0: all-zero codeword, dropped
+        // z = 2^52 + 2y exactly, 2y < 2^44: the high word is the exponent
+        // word kHiWord52 plus 2y >> 32, so y mod P (2^31 = 1) is
+        // (lo >> 1) + hi - kHiWord52, below 2P
+        const double z = Sm - t[k];
+        const uint64_t zb = __double_as_longlong(z);
+        const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
+        const uint32_t y = min(half + hi - kHiWord52, half + hi - (kHiWord52 + kPrime));
+        stage[sbase + vr * PB + (vr >> SH) * PAD] = y;
+    }
+}
+
+// The block's staged keys to the table-major key array: thread t writes
+// column t % PB of rows v = t / PB + G k (the 64 NW threads cover G rows at
+// a time), stage row v going to table p (D-1) + v - 1, for the PB points
+// from first_point on.  Rows of at least 64 bytes are written with
+// non-temporal stores (the kernel never reads them back); shorter rows keep
+// the normal path, whose L2 merges the neighbouring workgroups' pieces of a
+// line.
+template <int LOGD, int LOGV, int NW>
+__device__ inline void write_stage(const uint32_t *stage, uint32_t *__restrict__ keys, int64_t key_stride, int p,
+                                   int64_t first_point, int64_t m) {
+    using S = Shape<LOGD, LOGV>;
+    constexpr int G = S::G, U = S::U, D = S::D, PB = NW * U;
+    constexpr int PAD = stage_pad<LOGD>(), SH = stage_shift<LOGD>();
+    const int v0 = threadIdx.x / PB;
+    const int col = threadIdx.x % PB;
+    const int64_t i = first_point + col;
+    if (i >= m) return;
+    const uint32_t *src = stage + stage_index<LOGD, PB>(v0, col);
+    uint32_t *row1 = keys + (int64_t(p) * (D - 1) + v0) * key_stride + i;  // table of v = v0 + 1
+    constexpr int NK = D / G;
+    constexpr int CH = NK < 16 ? NK : 16;
+    constexpr int KSTEP = G * PB + (G >> SH) * PAD;  // stage_index(v + G, c) - stage_index(v, c)
+#pragma unroll
+    for (int k0 = 0; k0 < NK; k0 += CH) {
+        uint32_t val[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) val[c] = src[(k0 + c) * KSTEP];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int k = k0 + c;
+            if (k == 0 && v0 == 0) continue;  // v = 0: the dropped row
+            uint32_t *dst = row1 + (int64_t(k) * G - 1) * key_stride;
+            if constexpr (PB * 4 >= 64)
+                __builtin_nontemporal_store(val[c], dst);
+            else
+                *dst = val[c];
+        }
+    }
+}
+
 // One workgroup of NW waves per (part, `rounds` x NW consecutive point
 // groups), in XCD-contiguous order; in each round every wave takes one group
 // of U consecutive points and the block writes the keys of its NW*U points
@@ -201,10 +309,7 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
                                                        uint32_t *__restrict__ keys, int64_t key_stride,
                                                        int64_t nblk, int64_t nitems, int rounds) {
     using S = Shape<LOGD, LOGV>;
-    constexpr int V = S::V, G = S::G, U = S::U, D = S::D;
-    constexpr int PB = NW * U;  // points per stage row
-    constexpr int PAD = stage_pad<LOGD>(), SH = stage_shift<LOGD>();
-    static_assert(SH <= S::LOGG, "the stage padding must split over lane and register index bits");
+    constexpr int V = S::V, G = S::G, U = S::U;
     extern __shared__ __align__(16) uint32_t lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -223,14 +328,8 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
     for (int i = threadIdx.x; i < E * G; i += 64 * NW) tab[i] = gtab[int64_t(p) * E * G + i];
     __syncthreads();
 
-    // index bits of the output held by this lane (see Shape)
-    int vlane = 0;
-#pragma unroll
-    for (int b = 0; b < S::LOGG; ++b)
-        if ((lane >> (S::LOGU + b)) & 1) vlane |= 1 << (S::swap_stage(b) ? S::swap_reg(b) : LOGV + b);
-
-    // The block's keys are staged in LDS as rows of PB points, then written
-    // out row by row: PB consecutive points of a table per row segment
+    // The block's keys are staged in LDS as rows of NW*U points, then written
+    // out row by row: NW*U consecutive points of a table per row segment
     // instead of the U of one wave.
     uint32_t *stage = lds + 2 * E * G + NW * U * stride;
     const int64_t ngroups = (m + U - 1) / U;
@@ -275,80 +374,73 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
             }
             __asm__ volatile("" ::: "memory");
             __builtin_amdgcn_wave_barrier();
-
-            // Fast Hadamard transform (Alg. 2): in-register stages ...
-#pragma unroll
-            for (int h = 1; h < V; h <<= 1) {
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    if (!(k & h)) {
-                        const double a = t[k], b = t[k | h];
-                        t[k] = a + b;
-                        t[k | h] = a - b;
-                    }
-                }
-            }
-            // ... then the stages across the G lanes of a unit, nearest partners
-            // first (the stages commute; this order keeps the register pressure of
-            // the DPP stages away from the key extraction)
-            cross_stages<LOGD, LOGV, 0>(t, lane);
-
-            // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
-            const double Sm = __shfl(t[0], u, 64) + kTwo52;
-            // stage_index(vlane | vr, wave * U + u), split into a lane base and
-            // a per-register constant
-            const int sbase = vlane * PB + (vlane >> SH) * PAD + wave * U + u;
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const int vr = S::vreg(k);
-                if (vr == 0 && vlane == 0) continue;  // row 0: all-zero codeword, dropped
-                // z = 2^52 + 2y exactly, 2y < 2^44: the high word is the exponent
-                // word kHiWord52 plus 2y >> 32, so y mod P (2^31 = 1) is
-                // (lo >> 1) + hi - kHiWord52, below 2P
-                const double z = Sm - t[k];
-                const uint64_t zb = __double_as_longlong(z);
-                const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
-                const uint32_t y = min(half + hi - kHiWord52, half + hi - (kHiWord52 + kPrime));
-                stage[sbase + vr * PB + (vr >> SH) * PAD] = y;
-            }
+            fht_keys_to_stage<LOGD, LOGV, NW>(t, lane, wave, stage);
         }
         __syncthreads();
-        {
-            // thread t writes column t % PB of rows v = t / PB + G k (the
-            // 64 NW threads cover G rows at a time), stage row v going to
-            // table p (D-1) + v - 1.  Rows of at least 64 bytes are written
-            // with non-temporal stores (this kernel never reads them back);
-            // shorter rows keep the normal path, whose L2 merges the
-            // neighbouring workgroups' pieces of a line.
-            const int v0 = threadIdx.x / PB;
-            const int col = threadIdx.x % PB;
-            const int64_t i = g0 * U + col;
-            if (i < m) {
-                const uint32_t *src = stage + stage_index<LOGD, PB>(v0, col);
-                uint32_t *row1 = keys + (int64_t(p) * (D - 1) + v0) * key_stride + i;  // table of v = v0 + 1
-                constexpr int NK = D / G;
-                constexpr int CH = NK < 16 ? NK : 16;
-                constexpr int KSTEP = G * PB + (G >> SH) * PAD;  // stage_index(v + G, c) - stage_index(v, c)
-#pragma unroll
-                for (int k0 = 0; k0 < NK; k0 += CH) {
-                    uint32_t val[CH];
-#pragma unroll
-                    for (int c = 0; c < CH; ++c) val[c] = src[(k0 + c) * KSTEP];
-#pragma unroll
-                    for (int c = 0; c < CH; ++c) {
-                        const int k = k0 + c;
-                        if (k == 0 && v0 == 0) continue;  // v = 0: the dropped row
-                        uint32_t *dst = row1 + (int64_t(k) * G - 1) * key_stride;
-                        if constexpr (PB * 4 >= 64)
-                            __builtin_nontemporal_store(val[c], dst);
-                        else
-                            *dst = val[c];
-                    }
-                }
-            }
-        }
+        write_stage<LOGD, LOGV, NW>(stage, keys, key_stride, p, g0 * U, m);
         __syncthreads();
     }
+}
+
+// The same keys for points given by their nonzero coordinates (CSR rows),
+// in O(nnz + L log L) per point (the sparse case of Sec. 3.2): each wave
+// accumulates its U points' sketches in LDS, one 64-bit atomic add per
+// nonzero coordinate of the workgroup's part (two nonzeros may share a
+// column), reads them into registers, and the FHT, key extraction, staging
+// and write-out are the dense kernel's.  The stage reuses the accumulators'
+// LDS once every wave has read its sketches.  coord[c] = (even
+// representative b''_c, part(c) << 16 | column(c)).  Rows are clamped to
+// [0, nnz) and columns outside [0, d) skipped.
+template <int LOGD, int LOGV>
+__global__ __launch_bounds__(64 * kSparseWaves) void fht_hash_sparse_kernel(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ cols, int64_t nnz, int d, int64_t m,
+    const uint2 *__restrict__ coord, uint32_t *__restrict__ keys, int64_t key_stride, int64_t nblk,
+    int64_t nitems) {
+    using S = Shape<LOGD, LOGV>;
+    constexpr int NW = kSparseWaves;
+    constexpr int V = S::V, U = S::U, D = S::D;
+    extern __shared__ __align__(16) uint64_t lds64[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int s = lane >> S::LOGU;
+    const int u = lane & (U - 1);
+    const int64_t witem = xcd_contiguous_item(blockIdx.x, gridDim.x);
+    if (witem >= nitems) return;  // grid padding
+    const int p = int(witem / nblk);
+    const int64_t g0 = (witem % nblk) * NW;  // the workgroup's first point group
+    const int64_t grp = g0 + wave;
+    const int64_t ngroups = (m + U - 1) / U;
+    double t[V];
+    if (grp < ngroups) {  // wave-uniform
+        uint64_t *acc = lds64 + int64_t(wave) * U * D;
+        for (int i = lane; i < U * D; i += 64) acc[i] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int uu = 0; uu < U; ++uu) {
+            const int64_t i = grp * U + uu;
+            if (i >= m) break;  // wave-uniform
+            const int64_t e0 = min(max(ptr[i], int64_t(0)), nnz);
+            const int64_t e1 = min(max(ptr[i + 1], e0), nnz);
+            for (int64_t e = e0 + lane; e < e1; e += 64) {
+                const uint32_t c = uint32_t(cols[e]);
+                if (c >= uint32_t(d)) continue;
+                const uint2 cw = coord[c];
+                if (int(cw.y >> 16) == p)
+                    __hip_atomic_fetch_add(&acc[uu * D + int(cw.y & 0xFFFFu)], uint64_t(cw.x), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t *mine = acc + u * D + s * V;
+#pragma unroll
+        for (int k = 0; k < V; ++k) t[k] = double(mine[k]);
+    }
+    __syncthreads();  // every wave has its sketch: the stage may overwrite the accumulators
+    uint32_t *stage = reinterpret_cast<uint32_t *>(lds64);
+    if (grp < ngroups) fht_keys_to_stage<LOGD, LOGV, NW>(t, lane, wave, stage);
+    __syncthreads();
+    write_stage<LOGD, LOGV, NW>(stage, keys, key_stride, p, g0 * U, m);
 }
 
 // Rounds of NW point groups per workgroup (the gather table is staged once
@@ -384,6 +476,27 @@ fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t 
     return FCLSH_OK;
 }
 
+template <int LOGD, int LOGV>
+fclsh_status launch_sparse_t(const Index &ix, const CsrRows &rows, int64_t m, uint32_t *keys, int64_t key_stride,
+                             hipStream_t st) {
+    using S = Shape<LOGD, LOGV>;
+    constexpr int NW = kSparseWaves;
+    const HashPlan &pl = ix.plan;
+    const size_t acc = size_t(NW) * S::U * S::D * 8;
+    const size_t stage = stage_words<LOGD, NW * S::U>() * 4;
+    const size_t lds = std::max(acc, stage);
+    if (lds > 160 * 1024) return fail(FCLSH_EUNSUPPORTED, "sparse hash kernel LDS need %zu bytes", lds);
+    const int64_t ngroups = (m + S::U - 1) / S::U;
+    const int64_t nblk = (ngroups + NW - 1) / NW;  // work items per part
+    const int64_t nitems = nblk * pl.t;
+    const int64_t grid = xcd_grid(nitems);
+    if (grid > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "%lld points need too many workgroups", (long long)m);
+    hipLaunchKernelGGL((fht_hash_sparse_kernel<LOGD, LOGV>), dim3(unsigned(grid)), dim3(64 * NW), lds, st, rows.ptr,
+                       rows.cols, rows.nnz, ix.prm.d, m, pl.coord, keys, key_stride, nblk, nitems);
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
+}
+
 }  // namespace
 
 // 32 sketch entries per lane (64 VGPRs of fp64) keep several waves per SIMD;
@@ -401,6 +514,18 @@ fclsh_status build_hash_plan(Index *ix) {
     pl.U = 64 / pl.G;
     pl.t = p.t;
     pl.W = ix->W;
+    if (p.sparse) {
+        // one (even representative, part << 16 | column) word pair per coordinate
+        std::vector<uint32_t> coord(size_t(p.d) * 2);
+        for (int c = 0; c < p.d; ++c) {
+            const uint64_t b = p.b[c];
+            coord[size_t(c) * 2] = uint32_t((b & 1) ? b + kPrime : b);
+            coord[size_t(c) * 2 + 1] = uint32_t(p.part[c]) << 16 | uint32_t(p.col[c]);
+        }
+        FCLSH_TRY(dev_alloc(ix, reinterpret_cast<void **>(&pl.coord), coord.size() * 4, "hash plan"));
+        FCLSH_HIP(hipMemcpy(pl.coord, coord.data(), coord.size() * 4, hipMemcpyHostToDevice));
+        return FCLSH_OK;
+    }
     const int G = pl.G, V = pl.V;
     const uint32_t zero_slot = coord_entry(uint32_t(64 * ix->W));  // reads the staged zero dword
 
@@ -467,6 +592,27 @@ fclsh_status launch_hash(const Index &ix, const uint64_t *pts, int64_t m, uint32
         case 10: return launch_t<10, 5>(ix, pts, m, keys, key_stride, st);
         case 11: return launch_t<11, 5>(ix, pts, m, keys, key_stride, st);
         case 12: return launch_t<12, 6>(ix, pts, m, keys, key_stride, st);
+        default: return fail(FCLSH_EUNSUPPORTED, "Hadamard order 2^%d", ix.plan.logD);
+    }
+}
+
+fclsh_status launch_hash_sparse(const Index &ix, const CsrRows &rows, int64_t m, uint32_t *keys, int64_t key_stride,
+                                hipStream_t st) {
+    if (m == 0) return FCLSH_OK;
+    if (!ix.plan.coord) return fail(FCLSH_EINVAL, "the index holds dense points");
+    switch (ix.plan.logD) {
+        case 1: return launch_sparse_t<1, 1>(ix, rows, m, keys, key_stride, st);
+        case 2: return launch_sparse_t<2, 2>(ix, rows, m, keys, key_stride, st);
+        case 3: return launch_sparse_t<3, 3>(ix, rows, m, keys, key_stride, st);
+        case 4: return launch_sparse_t<4, 4>(ix, rows, m, keys, key_stride, st);
+        case 5: return launch_sparse_t<5, 5>(ix, rows, m, keys, key_stride, st);
+        case 6: return launch_sparse_t<6, 5>(ix, rows, m, keys, key_stride, st);
+        case 7: return launch_sparse_t<7, 5>(ix, rows, m, keys, key_stride, st);
+        case 8: return launch_sparse_t<8, 5>(ix, rows, m, keys, key_stride, st);
+        case 9: return launch_sparse_t<9, 5>(ix, rows, m, keys, key_stride, st);
+        case 10: return launch_sparse_t<10, 5>(ix, rows, m, keys, key_stride, st);
+        case 11: return launch_sparse_t<11, 5>(ix, rows, m, keys, key_stride, st);
+        case 12: return launch_sparse_t<12, 6>(ix, rows, m, keys, key_stride, st);
         default: return fail(FCLSH_EUNSUPPORTED, "Hadamard order 2^%d", ix.plan.logD);
     }
 }

@@ -74,11 +74,13 @@ fclsh_status fail(fclsh_status st, const char *fmt, ...) {
 const char *last_error_cstr() { return g_last_error.c_str(); }
 
 fclsh_status check_params(const Params &p) {
-    if (p.d <= 0 || p.d > kMaxDims) return fail(FCLSH_EUNSUPPORTED, "d=%d outside [1, %d]", p.d, kMaxDims);
+    const int dmax = p.sparse ? kMaxSparseDims : kMaxDims;
+    if (p.d <= 0 || p.d > dmax) return fail(FCLSH_EUNSUPPORTED, "d=%d outside [1, %d]", p.d, dmax);
     if (p.rep < 1 || (p.rep > 1 && p.t != 1))
         return fail(FCLSH_EINVAL, "replication (%d copies) needs a single part", p.rep);
-    if (p.dd() > kMaxDims)
-        return fail(FCLSH_EUNSUPPORTED, "%d copies of d=%d exceed %d coordinates", p.rep, p.d, kMaxDims);
+    if (p.sparse && p.rep != 1) return fail(FCLSH_EUNSUPPORTED, "replication of sparse points");
+    if (p.dd() > dmax)
+        return fail(FCLSH_EUNSUPPORTED, "%d copies of d=%d exceed %d coordinates", p.rep, p.d, dmax);
     if (p.t < 1 || p.t > kMaxParts || p.t > p.d)
         return fail(FCLSH_EUNSUPPORTED, "t=%d parts unsupported for d=%d", p.t, p.d);
     if (p.rp < 0 || p.rp + 1 > kMaxLogD)
@@ -102,8 +104,10 @@ fclsh_status check_params(const Params &p) {
     return FCLSH_OK;
 }
 
-fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts *opts, Params *out) {
+fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts *opts, Params *out, bool sparse) {
     if (d0 <= 0 || r < 0) return fail(FCLSH_EINVAL, "need d > 0 and r >= 0 (d=%d r=%d)", d0, r);
+    const int dmax = sparse ? kMaxSparseDims : kMaxDims;
+    if (d0 > dmax) return fail(FCLSH_EUNSUPPORTED, "d=%d exceeds %d", d0, dmax);
     if (opts && opts->replicate < 0) return fail(FCLSH_EINVAL, "negative replicate");
     if (opts && opts->prime != 0 && opts->prime != kPrime)
         return fail(FCLSH_EUNSUPPORTED, "only the prime 2^31-1 is supported");
@@ -112,8 +116,9 @@ fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts 
     const int rep = (opts && opts->replicate > 1) ? opts->replicate : 1;
     if (rep > 1 && opts->partitions > 1)
         return fail(FCLSH_EINVAL, "replication and partitioning are exclusive (Alg. 1)");
-    if (int64_t(rep) * d0 > kMaxDims)
-        return fail(FCLSH_EUNSUPPORTED, "%d copies of d=%d exceed %d coordinates", rep, d0, kMaxDims);
+    if (rep > 1 && sparse) return fail(FCLSH_EUNSUPPORTED, "replication of sparse points");
+    if (int64_t(rep) * d0 > dmax)
+        return fail(FCLSH_EUNSUPPORTED, "%d copies of d=%d exceed %d coordinates", rep, d0, dmax);
     const int d = rep * d0;  // coordinates the family is drawn for
     r *= rep;
     // Sec. 4.1 / Sec. 4.3: partition only for large radii (r >= 10, two parts).
@@ -130,6 +135,7 @@ fclsh_status derive_params(int d0, int r, uint64_t seed, const fclsh_build_opts 
     const int ncols = skip0 ? D - 1 : D, col0 = skip0 ? 1 : 0;
 
     Params p;
+    p.sparse = sparse;
     p.d = d0;
     p.r = r / rep;
     p.rep = rep;

@@ -46,6 +46,26 @@ namespace {
 // coordinates are the rep * d0 bits of the replicated point: a differing bit
 // c differs in every copy, and each copy i constrains by its own column
 // pc[i * d0 + c].
+// Restricts the basis B (distinct leading bits) to the v with <v, uc> = 0:
+// the odd vector with the lowest leading bit is dropped and XORed into the
+// other odd ones (their leading bits are higher, so they stay distinct).
+__device__ inline void constrain_basis(uint32_t (&B)[kMaxLogD], uint32_t uc) {
+    int star = -1;
+    uint32_t bs = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxLogD; ++l) {
+        if (B[l] && (__popc(B[l] & uc) & 1)) {
+            if (star < 0) {
+                star = l;
+                bs = B[l];
+                B[l] = 0u;
+            } else {
+                B[l] ^= bs;
+            }
+        }
+    }
+}
+
 __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t *__restrict__ q, int W,
                                   const uint32_t *__restrict__ pc, int t, int mbits, int Lp, uint64_t last_mask,
                                   int d0, int rep) {
@@ -77,29 +97,47 @@ __device__ int first_shared_table(const uint64_t *__restrict__ x, const uint64_t
                     diff &= diff - 1;
                     for (int i = 0, c = c0; i < rep; ++i, c += d0) {
                         const uint32_t pcc = pc[c];
-                        if (int(pcc >> 16) != p) continue;
-                        const uint32_t uc = pcc & 0xFFFFu;
-                        // constrain the basis to v with <v, uc> = 0: the odd
-                        // vector with the lowest leading bit is dropped and
-                        // XORed into the other odd ones (their leading bits
-                        // are higher, so they stay distinct)
-                        int star = -1;
-                        uint32_t bs = 0;
-#pragma unroll
-                        for (int l = 0; l < kMaxLogD; ++l) {
-                            if (B[l] && (__popc(B[l] & uc) & 1)) {
-                                if (star < 0) {
-                                    star = l;
-                                    bs = B[l];
-                                    B[l] = 0u;
-                                } else {
-                                    B[l] ^= bs;
-                                }
-                            }
-                        }
+                        if (int(pcc >> 16) == p) constrain_basis(B, pcc & 0xFFFFu);
                     }
                 }
             }
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxLogD; ++l)
+            if (B[l]) return p * Lp + int(B[l]) - 1;
+    }
+    return -1;
+}
+
+// The same for a point x and a query q given by their ascending coordinate
+// lists: the coordinates where they differ are those in exactly one list
+// (one merge per part).  Query columns outside [0, d) are skipped.
+__device__ int first_shared_table_sparse(const int32_t *__restrict__ xs, int nx, const int32_t *__restrict__ qs,
+                                         int nq, const uint32_t *__restrict__ pc, int t, int mbits, int Lp, int d) {
+    for (int p = 0; p < t; ++p) {
+        uint32_t B[kMaxLogD];
+#pragma unroll
+        for (int l = 0; l < kMaxLogD; ++l) B[l] = l < mbits ? (1u << l) : 0u;
+        int i = 0, j = 0;
+        while (i < nx || j < nq) {
+            const int32_t a = i < nx ? xs[i] : 0x7FFFFFFF;
+            const int32_t b = j < nq ? qs[j] : 0x7FFFFFFF;
+            int32_t c;
+            if (a == b) {
+                ++i;
+                ++j;
+                continue;
+            }
+            if (a < b) {
+                c = a;
+                ++i;
+            } else {
+                c = b;
+                ++j;
+            }
+            if (uint32_t(c) >= uint32_t(d)) continue;
+            const uint32_t pcc = pc[c];
+            if (int(pcc >> 16) == p) constrain_basis(B, pcc & 0xFFFFu);
         }
 #pragma unroll
         for (int l = 0; l < kMaxLogD; ++l)
@@ -114,8 +152,12 @@ struct VerifyArgs {
     int d0, rep;  // dimensions of a point and copies per point (d = rep * d0 staged words)
     uint64_t last_mask;
     const uint32_t *pc;  // part << 16 | column per coordinate (global; staged in LDS per workgroup)
-    const uint64_t *queries;
+    const uint64_t *queries;  // [nq][W] bit vectors (sparse queries: densified)
     int64_t nq;
+    // sparse index: the points' rows and the queries' rows (pts unused)
+    const int64_t *xptr, *qptr;
+    const int32_t *xcols, *qcols;
+    int64_t qnnz;
     const int32_t *rq_vec;  // per-query radius, or null: rq for all
     int rq;
     const uint32_t *tkeys, *tids, *dir;
@@ -249,26 +291,65 @@ __device__ inline void emit_pair(const VerifyArgs &a, const PairStage &ps, int64
     }
 }
 
+// Sparse index: |x| + |q| - 2 |x and q|, the common coordinates counted by
+// testing x's coordinates against q's bit vector (independent loads, four at
+// a time), after the length filter ||x| - |q|| <= rq.
+__device__ inline bool near_sparse(const VerifyArgs &a, const uint32_t *pc, int64_t qi, int T, int rq, uint32_t id) {
+    const int64_t xb = a.xptr[id], xe = a.xptr[int64_t(id) + 1];  // the index's own rows, checked at build
+    const int64_t qb = min(max(a.qptr[qi], int64_t(0)), a.qnnz);
+    const int64_t qe = min(max(a.qptr[qi + 1], qb), a.qnnz);
+    const int nx = int(xe - xb), nqi = int(qe - qb);
+    if (abs(nx - nqi) > rq) return false;
+    const uint64_t *qw = a.queries + qi * a.W;
+    const int32_t *xs = a.xcols + xb;
+    int common = 0;
+    for (int e0 = 0; e0 < nx; e0 += 4) {
+        int32_t c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = xs[min(e0 + k, nx - 1)];
+        uint64_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = qw[c[k] >> 6];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) common += (e0 + k < nx) ? int((w[k] >> (c[k] & 63)) & 1ull) : 0;
+    }
+    if (nx + nqi - 2 * common > rq) return false;
+    return first_shared_table_sparse(xs, nx, a.qcols + qb, nqi, pc, a.t, a.mbits, a.Lp, a.d) == T;
+}
+
 // Checks one bin entry j of table T against query qi: same key, within the
 // query's radius, and T is the first table the two share (dedupe).
+template <bool SPARSE>
 __device__ inline bool near_in_table(const VerifyArgs &a, const uint32_t *spc, int64_t qi, int T, uint32_t qkey,
                                      int rq, uint32_t key, uint32_t id) {
     if (key != qkey) return false;
-    const uint64_t *xp = a.pts + int64_t(id) * a.W;
-    const uint64_t *qp = a.queries + qi * a.W;
-    if (hamming(xp, qp, a.W, a.last_mask) > rq) return false;
-    return first_shared_table(xp, qp, a.W, spc, a.t, a.mbits, a.Lp, a.last_mask, a.d0, a.rep) == T;
+    if constexpr (SPARSE) {
+        return near_sparse(a, spc, qi, T, rq, id);
+    } else {
+        const uint64_t *xp = a.pts + int64_t(id) * a.W;
+        const uint64_t *qp = a.queries + qi * a.W;
+        if (hamming(xp, qp, a.W, a.last_mask) > rq) return false;
+        return first_shared_table(xp, qp, a.W, spc, a.t, a.mbits, a.Lp, a.last_mask, a.d0, a.rep) == T;
+    }
 }
 
-// Stages the per-coordinate (part, column) words in the workgroup's LDS.
+// Stages the per-coordinate (part, column) words in the workgroup's LDS
+// (dense points, at most 4096 coordinates); a sparse index reads them from
+// global memory.
+template <bool SPARSE>
 __device__ inline const uint32_t *stage_pc(const VerifyArgs &a, uint32_t *spc) {
-    for (int i = threadIdx.x; i < a.d; i += blockDim.x) spc[i] = a.pc[i];
-    __syncthreads();
-    return spc;
+    if constexpr (SPARSE) {
+        return a.pc;
+    } else {
+        for (int i = threadIdx.x; i < a.d; i += blockDim.x) spc[i] = a.pc[i];
+        __syncthreads();
+        return spc;
+    }
 }
 
 // Whole wave, uniform arguments: entries [j0, j1) of table T (absolute
 // positions), a lane per entry.
+template <bool SPARSE>
 __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, const uint32_t *spc, int64_t qi,
                                     int T, uint32_t j0, uint32_t j1) {
     const int lane = threadIdx.x & 63;
@@ -299,7 +380,7 @@ __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, co
             uint32_t idk = id[0];
 #pragma unroll
             for (int h = 1; h < R4; ++h) idk = k == h ? id[h] : idk;
-            if (near_in_table(a, spc, qi, T, qkey, rq, qkey, idk)) emit_pair(a, ps, qi, idk);
+            if (near_in_table<SPARSE>(a, spc, qi, T, qkey, rq, qkey, idk)) emit_pair(a, ps, qi, idk);
         }
     }
 }
@@ -355,10 +436,11 @@ __global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill,
 // probes the directory; a bin of at most kLaneBin entries is scanned and
 // verified by the lane alone, a larger one is cut into `tile`-entry chunks on
 // the spill queue.
+template <bool SPARSE>
 __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyArgs a) {
     __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
     extern __shared__ uint32_t dyn_pc[];
-    const uint32_t *spc = stage_pc(a, dyn_pc);
+    const uint32_t *spc = stage_pc<SPARSE>(a, dyn_pc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const PairStage ps{stq[wave], sti[wave], &stc[wave]};
     if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -428,7 +510,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
             const uint32_t c = uint32_t(__builtin_ctz(mm));
             mm &= mm - 1;
             const uint32_t id = ids[lo + c];
-            if (near_in_table(a, spc, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
+            if (near_in_table<SPARSE>(a, spc, qi, T, qkey, rq, qkey, id)) emit_pair(a, ps, qi, id);
         }
     }
     flush_pairs(a, ps, stage_count(ps));
@@ -439,10 +521,11 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
 // batch number up to the hundreds of thousands: a shared claim counter would
 // serialise that many atomics on one address, while the fixed stride spreads
 // the chunks' uneven costs over tens of chunks per wave.
+template <bool SPARSE>
 __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyArgs a) {
     __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
     extern __shared__ uint32_t dyn_pc[];
-    const uint32_t *spc = stage_pc(a, dyn_pc);
+    const uint32_t *spc = stage_pc<SPARSE>(a, dyn_pc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const PairStage ps{stq[wave], sti[wave], &stc[wave]};
     if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -453,7 +536,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyA
         int64_t qi;
         int T;
         item_coords(a, r.x, qi, T);
-        verify_range(a, ps, spc, qi, T, r.y, r.z);
+        verify_range<SPARSE>(a, ps, spc, qi, T, r.y, r.z);
     }
     flush_pairs(a, ps, stage_count(ps));
 }
@@ -474,10 +557,11 @@ __global__ void finish_offsets_kernel(uint64_t *offsets, int64_t nq, QueryCtrl *
     if (tot > (unsigned long long)pair_cap) st |= kQueryPairOverflow;
     if (ctrl->spills > (unsigned long long)spill_cap) st |= kQuerySpillOverflow;
     if (tot > (unsigned long long)ids_cap) st |= kQueryIdsOverflow;
-    ctrl->status = st;
+    ctrl->status = st | (ctrl->status & kQueryBadRows);
 }
 
-constexpr uint32_t kAnyOverflow = kQueryPairOverflow | kQuerySpillOverflow | kQueryIdsOverflow;
+// Conditions under which the scatter and sort leave the id buffer alone.
+constexpr uint32_t kAnyOverflow = kQueryPairOverflow | kQuerySpillOverflow | kQueryIdsOverflow | kQueryBadRows;
 
 // Pairs into per-query segments (order inside a segment fixed by the sort).
 __global__ void scatter_pairs_kernel(const uint32_t *__restrict__ pq, const uint32_t *__restrict__ pid,
@@ -601,7 +685,7 @@ uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 
 // released and the new ones and their capacities installed.  A failed
 // allocation leaves the workspace exactly as it was (old buffers, old
 // capacities), so a later call never runs on a half-grown workspace.
-fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills) {
+fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills, int64_t dense_words) {
     ws.pending_nq = -1;  // buffers may be replaced: nothing pending survives
     const int64_t items = nq * L;
     struct Grow {
@@ -618,6 +702,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
     const bool g_q = nq + 1 > ws.cap_q || !ws.qcount;
     const bool g_pairs = pairs > ws.cap_pairs || !ws.pq;
     const bool g_spill = spills > ws.cap_spill || !ws.spill;
+    const bool g_dense = dense_words > ws.cap_qdense;
     if (g_items) {
         want(&ws.qkeys, items, "query keys");
         want(&ws.rstart, items, "query ranges");
@@ -638,6 +723,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
         want(&ws.sorttmp, pairs, "result sort");
     }
     if (g_spill) want(&ws.spill, spills, "spill queue");
+    if (g_dense) want(&ws.qdense, dense_words, "query bit vectors");
     std::vector<void *> fresh(grow.size(), nullptr);
     for (size_t i = 0; i < grow.size(); ++i) {
         if (hipMalloc(&fresh[i], grow[i].bytes) != hipSuccess) {
@@ -654,6 +740,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
     if (g_q) ws.cap_q = nq + 1;
     if (g_pairs) ws.cap_pairs = pairs;
     if (g_spill) ws.cap_spill = spills;
+    if (g_dense) ws.cap_qdense = dense_words;
     return FCLSH_OK;
 }
 
@@ -713,12 +800,12 @@ uint64_t ws_bytes(const QueryWorkspace &ws) {
     if (!ws.ctrl) return 0;
     return uint64_t(ws.cap_items) * 16 + uint64_t(ws.cap_q) * 16 +
            uint64_t(scan_partials_needed(ws.cap_q)) * 8 + sizeof(QueryCtrl) + 16 + uint64_t(ws.cap_pairs) * 12 +
-           uint64_t(ws.cap_spill) * 16;
+           uint64_t(ws.cap_spill) * 16 + uint64_t(ws.cap_qdense) * 8;
 }
 
 void ws_release(QueryWorkspace &ws) {
     void *ps[] = {ws.qkeys, ws.rstart, ws.rlen, ws.rmatch, ws.qcount, ws.qfill, ws.qcount64, ws.scan_part,
-                  ws.offs1, ws.ctrl, ws.pq, ws.pid, ws.sorttmp, ws.spill};
+                  ws.offs1, ws.ctrl, ws.pq, ws.pid, ws.sorttmp, ws.spill, ws.qdense};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     ws = QueryWorkspace{};
@@ -875,18 +962,32 @@ fclsh_status launch_scatter_sort(Index &ix, QueryWorkspace &ws, int64_t nq, cons
 
 fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                                const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids,
-                               int64_t ids_cap) {
+                               int64_t ids_cap, const CsrRows *sq) {
     const int L = ix.prm.L();
     ws.pending_nq = -1;
     const QueryTuning &tu = ix.tuning;
+    const bool sparse = ix.prm.sparse;
+    if (sparse != (sq != nullptr)) return fail(FCLSH_EINVAL, "query rows do not match the index's point format");
     if (nq * L > ws.cap_items || nq + 1 > ws.cap_q || !ws.ctrl || !ws.pq || !ws.spill)
         return fail(FCLSH_EINVAL, "query workspace not reserved for %lld queries", (long long)nq);
+    if (sparse && nq * ix.W > ws.cap_qdense)
+        return fail(FCLSH_EINVAL, "query workspace not reserved for %lld sparse queries", (long long)nq);
     if (nq * L > int64_t(0xFFFFFFFF))  // spill chunks name their item in 32 bits
         return fail(FCLSH_EINVAL, "%lld queries x %d tables exceed 2^32 items per batch", (long long)nq, L);
     hipLaunchKernelGGL(reset_kernel, dim3(grid_for(nq, 256, 1024)), dim3(256), 0, st, ws.ctrl, ws.qcount, ws.qfill,
                        nq);
     FCLSH_HIP(hipGetLastError());
-    if (nq > 0) FCLSH_TRY(launch_hash(ix, queries, nq, ws.qkeys, nq, st));
+    if (sparse && nq > 0) {
+        // the rows are checked (any fault is reported in the status word and
+        // the ids are left alone), then hashed from their nonzeros and
+        // densified for the distance tests
+        FCLSH_TRY(csr_check(*sq, nq, ix.prm.d, &ws.ctrl->status, kQueryBadShift, st));
+        FCLSH_TRY(csr_densify(*sq, nq, ix.prm.d, ws.qdense, st));
+        FCLSH_TRY(launch_hash_sparse(ix, *sq, nq, ws.qkeys, nq, st));
+        queries = ws.qdense;
+    } else if (nq > 0) {
+        FCLSH_TRY(launch_hash(ix, queries, nq, ws.qkeys, nq, st));
+    }
     VerifyArgs a{};
     a.pts = ix.pts;
     a.W = ix.W;
@@ -918,15 +1019,29 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.qcount = ws.qcount;
     a.tile = uint32_t(tu.tile);
     a.table_major = nq > kTableMajorBatch ? 1 : 0;
+    if (sparse) {
+        a.xptr = ix.sptr;
+        a.xcols = ix.scols;
+        a.qptr = sq->ptr;
+        a.qcols = sq->cols;
+        a.qnnz = sq->nnz;
+    }
     const unsigned vblocks = unsigned(std::max(1, tu.blocks_per_cu * ix.num_cus));
     if (nq > 0) {
         // the item pass needs no more waves than rounds of 64 items
         const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 64 * kVerifyWaves));
-        const size_t pc_lds = size_t(ix.prm.dd()) * 4;  // staged (part, column) words, at most 4096
-        hipLaunchKernelGGL(verify_items_kernel, dim3(iblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
-        FCLSH_HIP(hipGetLastError());
-        hipLaunchKernelGGL(verify_spill_kernel, dim3(vblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
-        FCLSH_HIP(hipGetLastError());
+        if (sparse) {
+            hipLaunchKernelGGL(verify_items_kernel<true>, dim3(iblocks), dim3(64 * kVerifyWaves), 0, st, a);
+            FCLSH_HIP(hipGetLastError());
+            hipLaunchKernelGGL(verify_spill_kernel<true>, dim3(vblocks), dim3(64 * kVerifyWaves), 0, st, a);
+            FCLSH_HIP(hipGetLastError());
+        } else {
+            const size_t pc_lds = size_t(ix.prm.dd()) * 4;  // staged (part, column) words, at most 4096
+            hipLaunchKernelGGL(verify_items_kernel<false>, dim3(iblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
+            FCLSH_HIP(hipGetLastError());
+            hipLaunchKernelGGL(verify_spill_kernel<false>, dim3(vblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
+            FCLSH_HIP(hipGetLastError());
+        }
     }
     hipLaunchKernelGGL(widen_counts_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.qcount, nq, ws.qcount64);
     FCLSH_HIP(hipGetLastError());
@@ -963,16 +1078,22 @@ fclsh_status query_finish(Index &ix, QueryWorkspace &ws, hipStream_t st, const u
 // internal buffer overflowed.
 fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, int rq,
                          const int32_t *rq_vec, hipStream_t st, uint64_t *offsets, uint32_t *ids, int64_t ids_cap,
-                         int64_t *total_out) {
+                         int64_t *total_out, const CsrRows *sq) {
     const int L = ix.prm.L();
     int64_t pairs = std::max<int64_t>(ws.cap_pairs, std::max<int64_t>(1 << 16, nq * 16));
     int64_t spills = std::max<int64_t>(ws.cap_spill, 1 << 16);
+    const int64_t dense_words = ix.prm.sparse ? nq * ix.W : 0;
     QueryCtrl h{};
     for (int attempt = 0; attempt < 3; ++attempt) {
-        FCLSH_TRY(ws_reserve(ws, nq, L, pairs, spills));
-        FCLSH_TRY(query_batch_async(ix, ws, queries, nq, rq, rq_vec, st, offsets, ids, ids_cap));
+        FCLSH_TRY(ws_reserve(ws, nq, L, pairs, spills, dense_words));
+        FCLSH_TRY(query_batch_async(ix, ws, queries, nq, rq, rq_vec, st, offsets, ids, ids_cap, sq));
         FCLSH_HIP(hipMemcpyAsync(&h, ws.ctrl, sizeof h, hipMemcpyDeviceToHost, st));
         FCLSH_HIP(hipStreamSynchronize(st));
+        if (h.status & kQueryBadRows)
+            return fail(FCLSH_EINVAL, "malformed query rows:%s%s%s",
+                        (h.status >> kQueryBadShift) & kCsrBadPtr ? " bad row bounds" : "",
+                        (h.status >> kQueryBadShift) & kCsrBadCol ? " column outside [0, d)" : "",
+                        (h.status >> kQueryBadShift) & kCsrBadOrder ? " columns not strictly ascending" : "");
         if (!(h.status & (kQueryPairOverflow | kQuerySpillOverflow))) break;
         if (h.status & kQueryPairOverflow) pairs = int64_t(h.pairs) + int64_t(h.pairs >> 3) + 1;
         if (h.status & kQuerySpillOverflow) spills = int64_t(h.spills) + int64_t(h.spills >> 3) + 1;

@@ -114,7 +114,7 @@ def test_replication_errors(d, r, t, times, status):
 @pytest.mark.parametrize("d,r,t,status", [(0, 3, 0, fc.FCLSH_EINVAL), (10, -1, 0, fc.FCLSH_EINVAL),
                                           (64, 24, 0, fc.FCLSH_EUNSUPPORTED),  # r' = 12: 2^13 columns
                                           (4, 2, 5, fc.FCLSH_EUNSUPPORTED),    # more parts than coordinates
-                                          (5000, 2, 0, fc.FCLSH_EUNSUPPORTED)])
+                                          (600_000, 2, 0, fc.FCLSH_EUNSUPPORTED)])  # above 2^19
 def test_param_errors(d, r, t, status):
     with pytest.raises(fc.FclshError) as e:
         fc.derive_params(d, r, 1, partitions=t)
