@@ -56,6 +56,10 @@ def parse():
                          "of Fig. 2 (n = 10K..50K, r = 6) or Fig. 3 (n = 64K, replication and 2 parts); "
                          "prints one JSON line of rows instead of the benchmark")
     ap.add_argument("--study-queries", type=int, default=100)
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the sparse section (bag-of-words and user-rating shapes as rows of nonzeros)")
+    ap.add_argument("--sparse-batch", type=int, default=4096, help="queries in the sparse section's large batch")
+    ap.add_argument("--sparse-only", action="store_true", help="run the sparse section alone")
     ap.add_argument("--kernel-only", choices=["hash", "build"], default=None,
                     help="profiling aid: launch only this part (plus a plain copy of known size "
                          "for counter calibration) --kernel-reps times")
@@ -85,6 +89,9 @@ def main():
     torch.cuda.set_device(0)
     if args.study:
         print(json.dumps(study(args, fc, torch, synth)), flush=True)
+        return
+    if args.sparse_only:
+        print(json.dumps({"sparse": sparse_section(args, fc, torch)}), flush=True)
         return
     dev = torch.device("cuda", 0)
     w = synth.WORKLOADS[args.workload]()
@@ -303,6 +310,9 @@ def main():
         checks.append(chk)
     if checks and not args.no_cpu_baseline:
         out["cpu_baseline"]["answers_checked"] = verify_samples(checks)
+    if not args.no_sparse:
+        stage("sparse section")
+        out["sparse"] = sparse_section(args, fc, torch)
     print(json.dumps(out), flush=True)
 
 
@@ -536,6 +546,102 @@ def served_section(args, fc, torch):
     ia.close()
     ib.close()
     return res, chk
+
+
+# The sparse shapes (Table 2's Enron and MovieLens as synthetic rows), with
+# the paper's partitions for them (Sec. 4.4): Enron up to r = 29 with 3
+# parts, MovieLens r = 8..13 with 2 parts and r <= 7 with 1.
+SPARSE_RUNS = [("enron_like", 29, 3, 4101), ("movielens_like", 13, 2, 4102), ("movielens_like", 7, 1, 4103)]
+
+
+def sparse_section(args, fc, torch):
+    """Per shape: the sparse index's build (hash kernel and table kernels
+    timed by events between them), the hash kernel's roofline (algorithmic
+    bytes: per point its row, 8 + 4 nnz bytes, and its L keys), the 100-query
+    batch and a large batch of those queries repeated, every answer of the
+    100 queries checked against the oracle's linear scan, and the oracle's
+    own per-query time on a sample beside it."""
+    import oracle
+    import synth
+
+    runs = []
+    cache = {}
+    for name, r, t, seed in SPARSE_RUNS:
+        if name not in cache:
+            cache[name] = synth.SPARSE_WORKLOADS[name](1.0)
+        w = cache[name]
+        stage(f"sparse {name}: n={w.n} d={w.d} nnz={w.cols.size} r={r} t={t}")
+        ptr, cols = fc.to_device_rows(w.ptr, w.cols)
+        qptr, qcols = fc.to_device_rows(w.qptr, w.qcols)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        idx = fc.SparseIndex(ptr, cols, w.d, r, seed=seed, partitions=t, keep_build_scratch=True)
+        build_wall = (time.perf_counter() - a) * 1e3
+        L = idx.info["L"]
+        idx.rebuild_timed()
+        phases = [idx.rebuild_timed() for _ in range(args.kernel_reps)]
+        ph = {("fht_hash_sparse_kernel" if k == "fht_hash_kernel" else k): float(np.mean([p[k] for p in phases]))
+              for k in phases[0]}
+        ms_hash = ph["fht_hash_sparse_kernel"]
+        ms_tables = sum(v for k, v in ph.items() if k != "fht_hash_sparse_kernel")
+        hash_bytes = w.n * (8 + 4 * L) + 4 * w.cols.size
+        offs, ids = idx.query(qptr, qcols, r)  # sizes the workspace
+        got = fc.split_csr(offs, ids)
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        st.record()
+        for _ in range(5):
+            idx.query(qptr, qcols, r)
+        en.record()
+        en.synchronize()
+        ms_q100 = st.elapsed_time(en) / 5
+        reps = -(-args.sparse_batch // w.nq)
+        sizes = np.diff(w.qptr)
+        bptr = np.concatenate([[0], np.cumsum(np.tile(sizes, reps))]).astype(np.int64)
+        bptr_d, bcols_d = fc.to_device_rows(bptr, np.tile(w.qcols, reps))
+        boffs, _ = idx.query(bptr_d, bcols_d, r)
+        torch.cuda.synchronize()
+        st.record()
+        for _ in range(3):
+            boffs, _ = idx.query(bptr_d, bcols_d, r)
+        en.record()
+        en.synchronize()
+        ms_big = st.elapsed_time(en) / 3
+        cnt = (boffs[1:] - boffs[:-1]).cpu().numpy()
+        same_rep = bool(np.array_equal(cnt, np.tile(cnt[:w.nq], reps)))
+        stage(f"sparse {name}: oracle linear scan of {w.nq} queries")
+        a = time.perf_counter()
+        want = oracle.brute_force_sparse(w.ptr, w.cols, w.qptr, w.qcols, w.d, r).ids
+        t_bf = time.perf_counter() - a
+        equal = len(got) == len(want) and all(np.array_equal(g, x) for g, x in zip(got, want))
+        pr = oracle.derive_params(w.d, r, seed, override_t=t)
+        pick = np.arange(0, w.n, max(1, w.n // 200))[:200]
+        sp = np.concatenate([[0], np.cumsum(w.ptr[pick + 1] - w.ptr[pick])]).astype(np.int64)
+        sc = np.concatenate([w.cols[w.ptr[i]:w.ptr[i + 1]] for i in pick])
+        a = time.perf_counter()
+        oracle.keys_sparse(sp, sc, pr)
+        t_keys = time.perf_counter() - a
+        runs.append({
+            "workload": f"{name}: n={w.n} d={w.d} nnz={w.cols.size} r={r} t={t} L={L} nq={w.nq}",
+            "build_ms_wall": build_wall, "hash_ms": ms_hash, "tables_ms": ms_tables, "kernel_ms": ph,
+            "hash_points_per_s": w.n / (ms_hash * 1e-3),
+            "hash_roofline": roof(hash_bytes, ms_hash, None, w.n, w.d, r,
+                                  "per point 8 + 4 nnz bytes of its row and 4L bytes of keys"),
+            "query_batch100_ms": ms_q100, "query_ms_per_query_batch100": ms_q100 / w.nq,
+            "big_batch_queries": int(reps * w.nq), "big_batch_ms": ms_big,
+            "big_batch_queries_per_s": reps * w.nq / (ms_big * 1e-3),
+            "reported_ids_per_query": sum(len(g) for g in got) / w.nq,
+            "answers_equal_oracle": bool(equal), "repeats_answer_alike": same_rep,
+            "cpu_baseline": {"kind": "oracle", "cores": oracle.num_threads(),
+                             "linear_scan_ms_per_query": t_bf * 1e3 / w.nq,
+                             "keys_points_per_s": len(pick) / t_keys,
+                             "sample": f"linear scan of the {w.nq} queries; O(nnz L) keys of {len(pick)} points"},
+        })
+        idx.close()
+        del ptr, cols
+        torch.cuda.empty_cache()
+    return {"data": "synthetic sparse rows: log-normal row lengths, Zipf column popularity, planted neighbours",
+            "runs": runs}
 
 
 def verify_samples(checks):

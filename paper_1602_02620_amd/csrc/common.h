@@ -197,7 +197,7 @@ struct QueryCtrl {
     unsigned long long pairs;       // reported (query, id) pairs
     unsigned long long total;       // pairs, as published with the offsets
     uint32_t status;                // kQuery*Overflow bits
-    uint32_t pad;
+    uint32_t nlong;                 // segments the sort hands to its long-segment kernel
 };
 constexpr uint32_t kQueryPairOverflow = 1u;
 constexpr uint32_t kQuerySpillOverflow = 2u;

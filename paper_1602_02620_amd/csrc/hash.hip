@@ -166,7 +166,8 @@ constexpr int hash_waves() { return LOGD == 9 || LOGD == 10 ? 8 : LOGD == 11 ? 1
 
 // Waves per workgroup of the sparse kernel (its accumulators, 8 bytes per
 // column and point, take twice the stage's LDS).
-constexpr int kSparseWaves = 4;
+template <int LOGD>
+constexpr int sparse_waves() { return 4; }
 
 // LDS staging of a block's keys: rows indexed by the Hadamard row v in
 // [0, D) (row 0, the dropped all-zero codeword, is never written), each of
@@ -383,21 +384,23 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
 }
 
 // The same keys for points given by their nonzero coordinates (CSR rows),
-// in O(nnz + L log L) per point (the sparse case of Sec. 3.2): each wave
-// accumulates its U points' sketches in LDS, one 64-bit atomic add per
-// nonzero coordinate of the workgroup's part (two nonzeros may share a
-// column), reads them into registers, and the FHT, key extraction, staging
-// and write-out are the dense kernel's.  The stage reuses the accumulators'
-// LDS once every wave has read its sketches.  coord[c] = (even
-// representative b''_c, part(c) << 16 | column(c)).  Rows are clamped to
-// [0, nnz) and columns outside [0, d) skipped.
-template <int LOGD, int LOGV>
-__global__ __launch_bounds__(64 * kSparseWaves) void fht_hash_sparse_kernel(
+// in O(nnz + L log L) per point (the sparse case of Sec. 3.2).  Each wave
+// accumulates its U points' sketches in LDS: the U rows are consecutive, so
+// their nonzeros form one range, which the lanes stride over four loads at a
+// time (a lane's row index only moves forward); every nonzero coordinate of
+// the workgroup's part adds its even representative to its column with a
+// 64-bit LDS atomic (two nonzeros may share a column).  The wave then reads
+// its sketches into registers, and the FHT, key extraction, staging and
+// write-out are the dense kernel's; the stage reuses the accumulators' LDS
+// once every wave has read its sketches.  coord[c] = (even representative
+// b''_c, part(c) << 16 | column(c)).  Row bounds are clamped to [0, nnz]
+// and made non-decreasing, and columns outside [0, d) are skipped.
+template <int LOGD, int LOGV, int NW>
+__global__ __launch_bounds__(64 * NW) void fht_hash_sparse_kernel(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ cols, int64_t nnz, int d, int64_t m,
     const uint2 *__restrict__ coord, uint32_t *__restrict__ keys, int64_t key_stride, int64_t nblk,
     int64_t nitems) {
     using S = Shape<LOGD, LOGV>;
-    constexpr int NW = kSparseWaves;
     constexpr int V = S::V, U = S::U, D = S::D;
     extern __shared__ __align__(16) uint64_t lds64[];
     const int lane = threadIdx.x & 63;
@@ -413,21 +416,42 @@ __global__ __launch_bounds__(64 * kSparseWaves) void fht_hash_sparse_kernel(
     double t[V];
     if (grp < ngroups) {  // wave-uniform
         uint64_t *acc = lds64 + int64_t(wave) * U * D;
+        int64_t *starts = reinterpret_cast<int64_t *>(lds64 + NW * U * D) + wave * (U + 1);
+        const int64_t r0 = grp * U;
+        const int rows = int(min(int64_t(U), m - r0));
+        // row starts: clamped, then a running maximum across the lanes
+        long long v = lane <= rows ? (long long)min(max(ptr[r0 + lane], int64_t(0)), nnz) : 0ll;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long y = __shfl_up(v, o, 64);
+            if (lane >= o) v = max(v, y);
+        }
+        if (lane <= rows) starts[lane] = v;
+        if (rows == 64 && lane == 63) starts[64] = max(v, (long long)min(max(ptr[r0 + 64], int64_t(0)), nnz));
         for (int i = lane; i < U * D; i += 64) acc[i] = 0ull;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (int uu = 0; uu < U; ++uu) {
-            const int64_t i = grp * U + uu;
-            if (i >= m) break;  // wave-uniform
-            const int64_t e0 = min(max(ptr[i], int64_t(0)), nnz);
-            const int64_t e1 = min(max(ptr[i + 1], e0), nnz);
-            for (int64_t e = e0 + lane; e < e1; e += 64) {
-                const uint32_t c = uint32_t(cols[e]);
-                if (c >= uint32_t(d)) continue;
-                const uint2 cw = coord[c];
-                if (int(cw.y >> 16) == p)
-                    __hip_atomic_fetch_add(&acc[uu * D + int(cw.y & 0xFFFFu)], uint64_t(cw.x), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int64_t E0 = starts[0], E1 = starts[rows];
+        int row = 0;  // the lane's current row: starts[row] <= e < starts[row + 1]
+        constexpr int R = 4;
+        for (int64_t e0 = E0 + lane; e0 < E1; e0 += 64 * R) {
+            int32_t c[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int64_t e = e0 + 64 * k;
+                c[k] = e < E1 ? cols[e] : -1;
+            }
+            uint2 cw[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) cw[k] = uint32_t(c[k]) < uint32_t(d) ? coord[c[k]] : make_uint2(0u, ~0u);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int64_t e = e0 + 64 * k;
+                if (e >= E1) break;
+                while (e >= starts[row + 1]) ++row;
+                if (int(cw[k].y >> 16) == p)
+                    __hip_atomic_fetch_add(&acc[row * D + int(cw[k].y & 0xFFFFu)], uint64_t(cw[k].x),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -480,9 +504,9 @@ template <int LOGD, int LOGV>
 fclsh_status launch_sparse_t(const Index &ix, const CsrRows &rows, int64_t m, uint32_t *keys, int64_t key_stride,
                              hipStream_t st) {
     using S = Shape<LOGD, LOGV>;
-    constexpr int NW = kSparseWaves;
+    constexpr int NW = sparse_waves<LOGD>();
     const HashPlan &pl = ix.plan;
-    const size_t acc = size_t(NW) * S::U * S::D * 8;
+    const size_t acc = size_t(NW) * S::U * S::D * 8 + size_t(NW) * (S::U + 1) * 8;  // sketches + row starts
     const size_t stage = stage_words<LOGD, NW * S::U>() * 4;
     const size_t lds = std::max(acc, stage);
     if (lds > 160 * 1024) return fail(FCLSH_EUNSUPPORTED, "sparse hash kernel LDS need %zu bytes", lds);
@@ -491,8 +515,8 @@ fclsh_status launch_sparse_t(const Index &ix, const CsrRows &rows, int64_t m, ui
     const int64_t nitems = nblk * pl.t;
     const int64_t grid = xcd_grid(nitems);
     if (grid > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "%lld points need too many workgroups", (long long)m);
-    hipLaunchKernelGGL((fht_hash_sparse_kernel<LOGD, LOGV>), dim3(unsigned(grid)), dim3(64 * NW), lds, st, rows.ptr,
-                       rows.cols, rows.nnz, ix.prm.d, m, pl.coord, keys, key_stride, nblk, nitems);
+    hipLaunchKernelGGL((fht_hash_sparse_kernel<LOGD, LOGV, NW>), dim3(unsigned(grid)), dim3(64 * NW), lds, st,
+                       rows.ptr, rows.cols, rows.nnz, ix.prm.d, m, pl.coord, keys, key_stride, nblk, nitems);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }

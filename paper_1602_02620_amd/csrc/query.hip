@@ -564,108 +564,153 @@ __global__ void finish_offsets_kernel(uint64_t *offsets, int64_t nq, QueryCtrl *
 constexpr uint32_t kAnyOverflow = kQueryPairOverflow | kQuerySpillOverflow | kQueryIdsOverflow | kQueryBadRows;
 
 // Pairs into per-query segments (order inside a segment fixed by the sort).
+// Pairs arrive in runs of one query, and a query with tens of thousands of
+// answers would serialise that many atomics on its fill counter: the lanes
+// of a wave that hold pairs of the same query reserve their slots with one
+// atomic.  Block 0 also clears the long-segment count of the sort.
 __global__ void scatter_pairs_kernel(const uint32_t *__restrict__ pq, const uint32_t *__restrict__ pid,
-                                     const QueryCtrl *__restrict__ ctrl, int64_t pair_cap,
+                                     QueryCtrl *__restrict__ ctrl, int64_t pair_cap,
                                      const uint64_t *__restrict__ offsets, uint32_t *__restrict__ qfill,
                                      uint32_t *__restrict__ ids, int64_t ids_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->nlong = 0;
     if (ctrl->status & kAnyOverflow) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t tot = int64_t(min((unsigned long long)pair_cap, ctrl->pairs));
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const uint32_t q = pq[i];
-        const uint64_t slot = offsets[q] + atomicAdd(&qfill[q], 1u);
-        if (slot < uint64_t(ids_cap)) ids[slot] = pid[i];
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    // whole waves step together, so that every lane takes part in the ballots
+    for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); i0 < tot; i0 += stride) {
+        const int64_t i = i0 + lane;
+        const bool valid = i < tot;
+        const uint32_t q = valid ? pq[i] : 0u;
+        const uint32_t id = valid ? pid[i] : 0u;
+        for (uint64_t rem = __ballot(valid); rem;) {
+            const int l = __builtin_ctzll(rem);
+            const uint32_t q0 = uint32_t(__shfl(int(q), l, 64));
+            const uint64_t same = __ballot(valid && q == q0) & rem;
+            uint32_t base = 0;
+            if (lane == l) base = atomicAdd(&qfill[q0], uint32_t(__popcll(same)));
+            base = uint32_t(__shfl(int(base), l, 64));
+            if ((same >> lane) & 1) {
+                const uint64_t slot = offsets[q0] + base + uint32_t(__popcll(same & lt));
+                if (slot < uint64_t(ids_cap)) ids[slot] = id;
+            }
+            rem &= ~same;
+        }
     }
 }
 
-// Sorts each query's segment of ids ascending: a bitonic sort in LDS for
-// segments up to kSortCap ids; longer segments run a stable LSD radix sort
-// over global memory inside the workgroup, with tmp as the second buffer.
+// Sorts each query's segment of ids ascending.  Segments up to kSortCap ids:
+// a bitonic sort in LDS, a workgroup per query.  Longer ones are listed
+// (list[k], k < ctrl->nlong) for segment_sort_long_kernel.
 constexpr int kSortNT = 256;
 constexpr int kSortCap = 4096;
 
 __global__ __launch_bounds__(kSortNT) void segment_sort_kernel(const uint64_t *__restrict__ offsets,
-                                                               const QueryCtrl *__restrict__ ctrl,
-                                                               uint32_t *__restrict__ ids,
-                                                               uint32_t *__restrict__ tmp, int idbits) {
+                                                               QueryCtrl *__restrict__ ctrl,
+                                                               uint32_t *__restrict__ ids, int64_t q0,
+                                                               uint32_t *__restrict__ list) {
     __shared__ uint32_t s[kSortCap];
-    __shared__ uint32_t cnt[256];
-    __shared__ uint32_t sh[kSortNT / 64 + 1];
     if (ctrl->status & kAnyOverflow) return;
     const int64_t q = blockIdx.x;
     const uint64_t b = offsets[q], e = offsets[q + 1];
     const uint32_t m = uint32_t(e - b);
     if (m <= 1) return;
     uint32_t *seg = ids + b;
-    if (m <= uint32_t(kSortCap)) {
-        uint32_t P = 1;
-        while (P < m) P <<= 1;
-        for (uint32_t i = threadIdx.x; i < P; i += kSortNT) s[i] = i < m ? seg[i] : 0xFFFFFFFFu;
-        __syncthreads();
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = threadIdx.x; i < P; i += kSortNT) {
-                    const uint32_t l = i ^ j;
-                    if (l > i) {
-                        const uint32_t x = s[i], y = s[l];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            s[i] = y;
-                            s[l] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) seg[i] = s[i];
+    if (m > uint32_t(kSortCap)) {
+        if (threadIdx.x == 0) list[atomicAdd(&ctrl->nlong, 1u)] = uint32_t(q0 + q);
         return;
     }
-    // long segment: 8-bit LSD passes, each a histogram, a scan of the 256
-    // digit counts and a stable scatter, chunk by chunk, in which thread d
-    // moves the chunk's entries with digit d in their order
-    uint32_t *src = seg, *dst = tmp + b;
-    const int npass = (idbits + 7) / 8;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int ps = 0; ps < npass; ++ps) {
-        const int sft = 8 * ps;
-        cnt[threadIdx.x] = 0;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) atomicAdd(&cnt[(src[i] >> sft) & 255u], 1u);
-        __syncthreads();
-        const uint32_t c = cnt[threadIdx.x];
-        uint32_t x = c;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) sh[wave] = x;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (int w = 0; w < kSortNT / 64; ++w) {
-                const uint32_t cc = sh[w];
-                sh[w] = run;
-                run += cc;
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += kSortNT) s[i] = i < m ? seg[i] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P; i += kSortNT) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t x = s[i], y = s[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
             }
-        }
-        __syncthreads();
-        uint32_t pos = x - c + sh[wave];  // running start of digit threadIdx.x
-        __syncthreads();
-        for (uint32_t c0 = 0; c0 < m; c0 += kSortCap) {
-            const uint32_t c1 = min(m, c0 + uint32_t(kSortCap));
-            for (uint32_t i = c0 + threadIdx.x; i < c1; i += kSortNT) s[i - c0] = src[i];
-            __syncthreads();
-            for (uint32_t i = 0; i < c1 - c0; ++i)
-                if (((s[i] >> sft) & 255u) == threadIdx.x) dst[pos++] = s[i];
             __syncthreads();
         }
-        uint32_t *tsw = src;
-        src = dst;
-        dst = tsw;
     }
-    if (src != seg)
-        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) seg[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < m; i += kSortNT) seg[i] = s[i];
+}
+
+// Long segments (listed by segment_sort_kernel), a workgroup at a time each:
+// a segment's ids are distinct (the first-shared-table rule reports a point
+// once) and below n, so they are marked in an LDS bitmap of the id universe,
+// kLongBits ids per pass, and read back in ascending order into tmp (thread
+// t reads a run of `per` consecutive words, per odd so that the 64 lanes of
+// a wave hit 64 different banks, and a block scan of the runs' popcounts
+// places its ids); then tmp is copied over the segment.  O(m + n/32) per
+// pass over the universe, instead of a sort's O(m log m) passes over global
+// memory.
+constexpr int64_t kLongBits = int64_t(1) << 20;  // 128 KB of LDS
+
+__global__ __launch_bounds__(kSortNT) void segment_sort_long_kernel(const uint64_t *__restrict__ offsets,
+                                                                    const QueryCtrl *__restrict__ ctrl,
+                                                                    const uint32_t *__restrict__ list,
+                                                                    uint32_t *__restrict__ ids,
+                                                                    uint32_t *__restrict__ tmp, int64_t n) {
+    extern __shared__ uint32_t bm[];
+    __shared__ uint32_t wsum[kSortNT / 64];
+    if (ctrl->status & kAnyOverflow) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t nlong = ctrl->nlong;
+    for (uint32_t k = blockIdx.x; k < nlong; k += gridDim.x) {
+        const uint32_t q = list[k];
+        const uint64_t b = offsets[q];
+        const uint32_t m = uint32_t(offsets[q + 1] - b);
+        uint32_t *seg = ids + b;
+        uint32_t *out = tmp + b;
+        uint32_t written = 0;
+        for (int64_t base = 0; base < n; base += kLongBits) {
+            const uint32_t span = uint32_t(min(kLongBits, n - base));
+            const uint32_t words = (span + 31) / 32;
+            for (uint32_t w = threadIdx.x; w < words; w += kSortNT) bm[w] = 0u;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < m; i += kSortNT) {
+                const int64_t off = int64_t(seg[i]) - base;
+                if (off >= 0 && off < int64_t(span)) atomicOr(&bm[off >> 5], 1u << (off & 31));
+            }
+            __syncthreads();
+            const uint32_t per = ((words + kSortNT - 1) / kSortNT) | 1u;
+            const uint32_t w0 = min(words, threadIdx.x * per), w1 = min(words, w0 + per);
+            uint32_t c = 0;
+            for (uint32_t w = w0; w < w1; ++w) c += uint32_t(__popc(bm[w]));
+            uint32_t x = c;  // inclusive scan over the wave
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = uint32_t(__shfl_up(int(x), o, 64));
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) wsum[wave] = x;
+            __syncthreads();
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < kSortNT / 64; ++w) {
+                before += w < wave ? wsum[w] : 0u;
+                total += wsum[w];
+            }
+            uint32_t pos = written + before + x - c;
+            for (uint32_t w = w0; w < w1; ++w) {
+                for (uint32_t bits = bm[w]; bits; bits &= bits - 1)
+                    if (pos < m) out[pos++] = uint32_t(base) + w * 32u + uint32_t(__builtin_ctz(bits));
+            }
+            written += total;
+            __syncthreads();  // bm and wsum are reused by the next pass
+        }
+        for (uint32_t i = threadIdx.x; i < m; i += kSortNT) seg[i] = out[i];
+        __syncthreads();
+    }
 }
 
 unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
@@ -942,17 +987,25 @@ __global__ void rearm_scatter_kernel(QueryCtrl *ctrl, uint32_t *qfill, int64_t n
     for (int64_t i = i0; i < nq; i += int64_t(gridDim.x) * blockDim.x) qfill[i] = 0;
 }
 
-// Pairs into the per-query segments of ids, then each segment sorted.
+// Pairs into the per-query segments of ids, then each segment sorted (the
+// long segments listed in ws.qcount, free once the offsets are scanned).
 fclsh_status launch_scatter_sort(Index &ix, QueryWorkspace &ws, int64_t nq, const uint64_t *offsets, uint32_t *ids,
                                  int64_t ids_cap, hipStream_t st) {
     hipLaunchKernelGGL(scatter_pairs_kernel, dim3(grid_for(ws.cap_pairs, 256, 4096)), dim3(256), 0, st, ws.pq,
                        ws.pid, ws.ctrl, ws.cap_pairs, offsets, ws.qfill, ids, ids_cap);
     FCLSH_HIP(hipGetLastError());
-    const int idbits = std::max(1, ilog2_ceil(uint64_t(ix.n)));
     for (int64_t q0 = 0; q0 < nq; q0 += 65535) {
         const int64_t qn = std::min<int64_t>(65535, nq - q0);
-        hipLaunchKernelGGL(segment_sort_kernel, dim3(unsigned(qn)), dim3(kSortNT), 0, st, offsets + q0, ws.ctrl,
-                           ids, ws.sorttmp, idbits);
+        hipLaunchKernelGGL(segment_sort_kernel, dim3(unsigned(qn)), dim3(kSortNT), 0, st, offsets + q0, ws.ctrl, ids,
+                           q0, ws.qcount);
+        FCLSH_HIP(hipGetLastError());
+    }
+    // a segment over kSortCap ids holds at least that many distinct points
+    if (ix.n > kSortCap) {
+        const size_t lds = size_t(std::min<int64_t>(kLongBits, ix.n) + 31) / 32 * 4;
+        const unsigned grid = unsigned(std::min<int64_t>(std::max(1, ix.num_cus), nq));
+        hipLaunchKernelGGL(segment_sort_long_kernel, dim3(grid), dim3(kSortNT), lds, st, offsets, ws.ctrl, ws.qcount,
+                           ids, ws.sorttmp, ix.n);
         FCLSH_HIP(hipGetLastError());
     }
     return FCLSH_OK;

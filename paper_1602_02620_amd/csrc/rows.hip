@@ -9,7 +9,6 @@ namespace fclsh {
 
 namespace {
 
-// A thread per row (grid-stride): the row's bounds, then its columns.
 // Densifies m rows into bit vectors of W words each (out must be zero):
 // a wave per row, lanes striding over its nonzeros; columns outside [0, d)
 // are skipped.
@@ -32,23 +31,24 @@ __global__ void zero_words_kernel(unsigned long long *__restrict__ p, int64_t n)
         p[i] = 0ull;
 }
 
+// A wave per row (grid-stride over rows): the row's bounds, then its
+// columns, each lane comparing its column with the one before it.
 __global__ void csr_check_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ cols, int64_t m,
                                  int64_t nnz, int d, uint32_t *flag, int shift) {
     uint32_t bad = 0;
-    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i0 == 0 && (ptr[0] != 0 || ptr[m] != nnz)) bad |= kCsrBadPtr;
-    for (int64_t i = i0; i < m; i += int64_t(gridDim.x) * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (w0 == 0 && lane == 0 && (ptr[0] != 0 || ptr[m] != nnz)) bad |= kCsrBadPtr;
+    for (int64_t i = w0; i < m; i += (int64_t(gridDim.x) * blockDim.x) >> 6) {
         const int64_t a = ptr[i], b = ptr[i + 1];
         if (a < 0 || b < a || b > nnz) {
             bad |= kCsrBadPtr;
             continue;
         }
-        int64_t prev = -1;
-        for (int64_t e = a; e < b; ++e) {
+        for (int64_t e = a + lane; e < b; e += 64) {
             const int32_t c = cols[e];
             if (c < 0 || c >= d) bad |= kCsrBadCol;
-            if (int64_t(c) <= prev) bad |= kCsrBadOrder;
-            prev = c;
+            if (e > a && c <= cols[e - 1]) bad |= kCsrBadOrder;
         }
     }
     if (bad) atomicOr(flag, bad << shift);
@@ -57,7 +57,7 @@ __global__ void csr_check_kernel(const int64_t *__restrict__ ptr, const int32_t 
 }  // namespace
 
 fclsh_status csr_check(const CsrRows &rows, int64_t m, int d, uint32_t *flag, int shift, hipStream_t st) {
-    const int64_t blocks = std::min<int64_t>((m + 255) / 256, 4096);
+    const int64_t blocks = std::min<int64_t>((m + 3) / 4, 4096);  // four rows per block of four waves
     hipLaunchKernelGGL(csr_check_kernel, dim3(unsigned(std::max<int64_t>(blocks, 1))), dim3(256), 0, st, rows.ptr,
                        rows.cols, m, rows.nnz, d, flag, shift);
     FCLSH_HIP(hipGetLastError());

@@ -174,6 +174,34 @@ def test_large_result_segment_sort():
     idx.close()
 
 
+def test_long_segments_over_several_bitmap_passes():
+    # two queries with answers far over 4096 ids spread over ids above 2^21
+    # (the long-segment sort marks 2^20 ids per pass), between queries with
+    # short and empty answers, and the async path with the same buffers
+    rng = np.random.default_rng(13)
+    bases = synth.uniform_points(2, 64, rng)
+    pts = synth.uniform_points(2_500_000, 64, rng)
+    pts[5::97] = bases[0]
+    pts[11::131] = bases[1]
+    qs = np.concatenate([synth.uniform_points(1, 64, rng), bases[:1], pts[7:8], bases[1:2], pts[123:124]])
+    idx = fc.Index(dev(pts), 64, 3, seed=94)
+    want = oracle.brute_force(pts, 64, qs, 3).ids
+    assert len(want[1]) > 20_000 and len(want[3]) > 15_000 and int(want[1][-1]) > 2 ** 21
+    assert_same_lists(csr_lists(*idx.query(dev(qs), 3)), want)
+    total = sum(len(x) for x in want)
+    offs = torch.empty(len(qs) + 1, dtype=torch.int64, device="cuda")
+    ids = torch.empty(total, dtype=torch.int32, device="cuda")
+    res = torch.zeros(2, dtype=torch.int64, device="cuda")
+    idx.reserve(len(qs), pair_capacity=2 * total)
+    for _ in range(2):
+        ids.zero_()
+        idx.query_async(dev(qs), 3, offs, ids, res)
+        torch.cuda.synchronize()
+        assert res.cpu().tolist() == [total, 0]
+        assert_same_lists(csr_lists(offs, ids), want)
+    idx.close()
+
+
 def _heavy_index():
     # 1500 copies of one point: every table holds a bucket of >= 1500 entries
     rng = np.random.default_rng(10)
