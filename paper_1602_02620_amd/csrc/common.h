@@ -215,7 +215,8 @@ struct QueryWorkspace {
     uint32_t *pq = nullptr, *pid = nullptr, *sorttmp = nullptr;
     uint4 *spill = nullptr;
     uint64_t *qdense = nullptr;  // sparse queries as bit vectors
-    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0, cap_spill = 0, cap_qdense = 0;
+    uint32_t *seen = nullptr;    // sparse queries: an n-bit bitmap per query (points already checked)
+    int64_t cap_items = 0, cap_q = 0, cap_pairs = 0, cap_spill = 0, cap_qdense = 0, cap_seen = 0;
     // a synchronous batch whose ids did not fit the caller's buffer: its
     // pairs stay here until the next query call on the stream
     int64_t pending_nq = -1, pending_total = 0;
@@ -223,7 +224,7 @@ struct QueryWorkspace {
 };
 
 fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills,
-                        int64_t dense_words = 0);
+                        int64_t dense_words = 0, int64_t seen_words = 0);
 void ws_release(QueryWorkspace &ws);
 // A workspace laid out in one caller-owned device buffer (no allocation).
 fclsh_status ws_carve(QueryWorkspace &ws, void *base, size_t bytes, int64_t nq, int L);

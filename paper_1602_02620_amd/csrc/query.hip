@@ -158,6 +158,10 @@ struct VerifyArgs {
     const int64_t *xptr, *qptr;
     const int32_t *xcols, *qcols;
     int64_t qnnz;
+    // the paper's duplicate elimination (an n-bit bitmap per query, seen_wpq
+    // words each), or null: the first-shared-table rule
+    uint32_t *seen;
+    int64_t seen_wpq;
     const int32_t *rq_vec;  // per-query radius, or null: rq for all
     int rq;
     const uint32_t *tkeys, *tids, *dir;
@@ -291,14 +295,18 @@ __device__ inline void emit_pair(const VerifyArgs &a, const PairStage &ps, int64
     }
 }
 
-// Sparse index: |x| + |q| - 2 |x and q|, the common coordinates counted by
-// testing x's coordinates against q's bit vector (independent loads, four at
-// a time), after the length filter ||x| - |q|| <= rq.
-__device__ inline bool near_sparse(const VerifyArgs &a, const uint32_t *pc, int64_t qi, int T, int rq, uint32_t id) {
-    const int64_t xb = a.xptr[id], xe = a.xptr[int64_t(id) + 1];  // the index's own rows, checked at build
-    const int64_t qb = min(max(a.qptr[qi], int64_t(0)), a.qnnz);
-    const int64_t qe = min(max(a.qptr[qi + 1], qb), a.qnnz);
-    const int nx = int(xe - xb), nqi = int(qe - qb);
+// Sparse index: |x| + |q| - 2 |x and q| <= rq, the common coordinates
+// counted by testing x's coordinates against q's bit vector (independent
+// loads, four at a time), after the length filter ||x| - |q|| <= rq.  After
+// j of x's coordinates with c common, the distance is at least (j - c) (x's
+// misses so far) + max(0, |q| - c - (|x| - j)) (q's coordinates that x can no
+// longer match): the test stops as soon as that exceeds rq.
+__device__ inline bool within_sparse(const VerifyArgs &a, int64_t qi, int rq, uint32_t id, int64_t &xb, int &nx,
+                                     int64_t &qb, int &nqi) {
+    xb = a.xptr[id];
+    nx = int(a.xptr[int64_t(id) + 1] - xb);  // the index's own rows, checked at build
+    qb = min(max(a.qptr[qi], int64_t(0)), a.qnnz);
+    nqi = int(min(max(a.qptr[qi + 1], qb), a.qnnz) - qb);
     if (abs(nx - nqi) > rq) return false;
     const uint64_t *qw = a.queries + qi * a.W;
     const int32_t *xs = a.xcols + xb;
@@ -312,9 +320,18 @@ __device__ inline bool near_sparse(const VerifyArgs &a, const uint32_t *pc, int6
         for (int k = 0; k < 4; ++k) w[k] = qw[c[k] >> 6];
 #pragma unroll
         for (int k = 0; k < 4; ++k) common += (e0 + k < nx) ? int((w[k] >> (c[k] & 63)) & 1ull) : 0;
+        const int j = min(e0 + 4, nx);
+        if ((j - common) + max(0, nqi - common - (nx - j)) > rq) return false;
     }
-    if (nx + nqi - 2 * common > rq) return false;
-    return first_shared_table_sparse(xs, nx, a.qcols + qb, nqi, pc, a.t, a.mbits, a.Lp, a.d) == T;
+    return nx + nqi - 2 * common <= rq;
+}
+
+// First sighting of point id by query qi in the per-query bitmap (the
+// paper's duplicate elimination): true exactly once per (query, point), for
+// whichever table reaches it first.
+__device__ inline bool first_sighting(const VerifyArgs &a, int64_t qi, uint32_t id) {
+    const uint32_t bit = 1u << (id & 31);
+    return !(atomicOr(a.seen + qi * a.seen_wpq + (id >> 5), bit) & bit);
 }
 
 // Checks one bin entry j of table T against query qi: same key, within the
@@ -324,10 +341,20 @@ __device__ inline bool near_in_table(const VerifyArgs &a, const uint32_t *spc, i
                                      int rq, uint32_t key, uint32_t id) {
     if (key != qkey) return false;
     if constexpr (SPARSE) {
-        return near_sparse(a, spc, qi, T, rq, id);
+        if (a.seen) {
+            if (!first_sighting(a, qi, id)) return false;  // checked in an earlier table
+            int64_t xb, qb;
+            int nx, nqi;
+            return within_sparse(a, qi, rq, id, xb, nx, qb, nqi);
+        }
+        int64_t xb, qb;
+        int nx, nqi;
+        if (!within_sparse(a, qi, rq, id, xb, nx, qb, nqi)) return false;
+        return first_shared_table_sparse(a.xcols + xb, nx, a.qcols + qb, nqi, spc, a.t, a.mbits, a.Lp, a.d) == T;
     } else {
         const uint64_t *xp = a.pts + int64_t(id) * a.W;
         const uint64_t *qp = a.queries + qi * a.W;
+        if (a.seen) return first_sighting(a, qi, id) && hamming(xp, qp, a.W, a.last_mask) <= rq;
         if (hamming(xp, qp, a.W, a.last_mask) > rq) return false;
         return first_shared_table(xp, qp, a.W, spc, a.t, a.mbits, a.Lp, a.last_mask, a.d0, a.rep) == T;
     }
@@ -418,6 +445,11 @@ __global__ void collisions_kernel(const uint32_t *__restrict__ rmatch, int64_t n
     uint64_t s = 0;
     for (int T = 0; T < L; ++T) s += rmatch[qi * L + T];
     coll[qi] = s;
+}
+
+__global__ void zero_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0u;
 }
 
 // Clears the per-batch counters (a kernel, not a memset: graph-safe).
@@ -730,7 +762,8 @@ uint64_t last_word_mask(int d) { return (d % 64) ? ((uint64_t(1) << (d % 64)) - 
 // released and the new ones and their capacities installed.  A failed
 // allocation leaves the workspace exactly as it was (old buffers, old
 // capacities), so a later call never runs on a half-grown workspace.
-fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills, int64_t dense_words) {
+fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, int64_t spills, int64_t dense_words,
+                        int64_t seen_words) {
     ws.pending_nq = -1;  // buffers may be replaced: nothing pending survives
     const int64_t items = nq * L;
     struct Grow {
@@ -748,6 +781,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
     const bool g_pairs = pairs > ws.cap_pairs || !ws.pq;
     const bool g_spill = spills > ws.cap_spill || !ws.spill;
     const bool g_dense = dense_words > ws.cap_qdense;
+    const bool g_seen = seen_words > ws.cap_seen;
     if (g_items) {
         want(&ws.qkeys, items, "query keys");
         want(&ws.rstart, items, "query ranges");
@@ -769,6 +803,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
     }
     if (g_spill) want(&ws.spill, spills, "spill queue");
     if (g_dense) want(&ws.qdense, dense_words, "query bit vectors");
+    if (g_seen) want(&ws.seen, seen_words, "per-query point bitmaps");
     std::vector<void *> fresh(grow.size(), nullptr);
     for (size_t i = 0; i < grow.size(); ++i) {
         if (hipMalloc(&fresh[i], grow[i].bytes) != hipSuccess) {
@@ -786,6 +821,7 @@ fclsh_status ws_reserve(QueryWorkspace &ws, int64_t nq, int L, int64_t pairs, in
     if (g_pairs) ws.cap_pairs = pairs;
     if (g_spill) ws.cap_spill = spills;
     if (g_dense) ws.cap_qdense = dense_words;
+    if (g_seen) ws.cap_seen = seen_words;
     return FCLSH_OK;
 }
 
@@ -845,12 +881,13 @@ uint64_t ws_bytes(const QueryWorkspace &ws) {
     if (!ws.ctrl) return 0;
     return uint64_t(ws.cap_items) * 16 + uint64_t(ws.cap_q) * 16 +
            uint64_t(scan_partials_needed(ws.cap_q)) * 8 + sizeof(QueryCtrl) + 16 + uint64_t(ws.cap_pairs) * 12 +
-           uint64_t(ws.cap_spill) * 16 + uint64_t(ws.cap_qdense) * 8;
+           uint64_t(ws.cap_spill) * 16 + uint64_t(ws.cap_qdense) * 8 +
+           uint64_t(ws.cap_seen) * 4;
 }
 
 void ws_release(QueryWorkspace &ws) {
     void *ps[] = {ws.qkeys, ws.rstart, ws.rlen, ws.rmatch, ws.qcount, ws.qfill, ws.qcount64, ws.scan_part,
-                  ws.offs1, ws.ctrl, ws.pq, ws.pid, ws.sorttmp, ws.spill, ws.qdense};
+                  ws.offs1, ws.ctrl, ws.pq, ws.pid, ws.sorttmp, ws.spill, ws.qdense, ws.seen};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     ws = QueryWorkspace{};
@@ -1079,6 +1116,19 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
         a.qcols = sq->cols;
         a.qnnz = sq->nnz;
     }
+    {
+        // the paper's bitmap dedupe when the workspace holds one bitmap per
+        // query: a point is checked once per query, not once per table it
+        // collides in
+        const int64_t wpq = (ix.n + 31) / 32;
+        if (nq > 0 && ws.cap_seen >= nq * wpq) {
+            a.seen = ws.seen;
+            a.seen_wpq = wpq;
+            hipLaunchKernelGGL(zero_u32_kernel, dim3(grid_for(nq * wpq, 256, 8192)), dim3(256), 0, st, ws.seen,
+                               nq * wpq);
+            FCLSH_HIP(hipGetLastError());
+        }
+    }
     const unsigned vblocks = unsigned(std::max(1, tu.blocks_per_cu * ix.num_cus));
     if (nq > 0) {
         // the item pass needs no more waves than rounds of 64 items
@@ -1126,6 +1176,13 @@ fclsh_status query_finish(Index &ix, QueryWorkspace &ws, hipStream_t st, const u
     return FCLSH_OK;
 }
 
+constexpr int64_t kSeenBudget = int64_t(1) << 30;
+
+// Whether a synchronous batch dedupes with per-query bitmaps.
+bool use_seen(const Index &ix, int64_t nq) {
+    return ix.prm.sparse && nq * ((ix.n + 31) / 32) * 4 <= kSeenBudget;
+}
+
 // Synchronous form (fclsh_query_batch): sizes the workspace, runs the device
 // pipeline, reads the result size back once and grows and reruns if an
 // internal buffer overflowed.
@@ -1136,9 +1193,12 @@ fclsh_status query_batch(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
     int64_t pairs = std::max<int64_t>(ws.cap_pairs, std::max<int64_t>(1 << 16, nq * 16));
     int64_t spills = std::max<int64_t>(ws.cap_spill, 1 << 16);
     const int64_t dense_words = ix.prm.sparse ? nq * ix.W : 0;
+    // sparse queries take a bitmap per query when all of them fit in
+    // kSeenBudget bytes (else the first-shared-table rule)
+    const int64_t seen_words = use_seen(ix, nq) ? nq * ((ix.n + 31) / 32) : 0;
     QueryCtrl h{};
     for (int attempt = 0; attempt < 3; ++attempt) {
-        FCLSH_TRY(ws_reserve(ws, nq, L, pairs, spills, dense_words));
+        FCLSH_TRY(ws_reserve(ws, nq, L, pairs, spills, dense_words, seen_words));
         FCLSH_TRY(query_batch_async(ix, ws, queries, nq, rq, rq_vec, st, offsets, ids, ids_cap, sq));
         FCLSH_HIP(hipMemcpyAsync(&h, ws.ctrl, sizeof h, hipMemcpyDeviceToHost, st));
         FCLSH_HIP(hipStreamSynchronize(st));

@@ -229,3 +229,24 @@ def test_full_size_sampled(name, seed, r, t):
         for j, slots in enumerate(w.meta["planted"]):
             assert set(int(s) for s in slots) <= set(got[j].tolist())
     idx.close()
+
+
+def test_bitmap_and_first_table_dedupe_agree():
+    # a batch whose per-query point bitmaps would exceed 1 GiB (40,000
+    # queries x 234,834 points) uses the first-shared-table rule; the same
+    # queries in a batch of 100 use the bitmaps: both answer alike, and the
+    # small batch equals the oracle
+    w = _full("movielens_like")
+    r = 7
+    idx = fc.SparseIndex(*rows(w.ptr, w.cols), w.d, r, seed=4103, partitions=1)
+    small = csr_lists(*idx.query(*rows(w.qptr, w.qcols), r))
+    assert_same_lists(small, oracle.brute_force_sparse(w.ptr, w.cols, w.qptr, w.qcols, w.d, r).ids)
+    reps = 400
+    sizes = np.diff(w.qptr)
+    bptr = np.concatenate([[0], np.cumsum(np.tile(sizes, reps))]).astype(np.int64)
+    _say(f"[sparse dedupe] {reps * w.nq} queries")
+    big = csr_lists(*idx.query(*rows(bptr, np.tile(w.qcols, reps)), r))
+    assert len(big) == reps * w.nq
+    for k in range(0, reps * w.nq, 997):
+        assert np.array_equal(big[k], small[k % w.nq]), k
+    idx.close()
