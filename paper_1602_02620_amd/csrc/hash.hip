@@ -88,27 +88,16 @@ struct Shape {
     }
 };
 
-__device__ inline double dpp_f64(double x, int ctrl_sel) {
+// The value of lane ^ DIST (DIST in 1, 2, 4, 8): a ds_swizzle in bit mode
+// (and-mask 0x1F, xor-mask DIST within each 32 lanes) per dword.  The
+// swizzle runs in the LDS pipe, so these stages leave the VALU to the
+// butterflies (a DPP move would take a VALU slot per dword).
+template <int DIST>
+__device__ inline double xor_lane_f64(double x) {
+    static_assert(DIST == 1 || DIST == 2 || DIST == 4 || DIST == 8, "swizzle distance");
     const uint64_t u = __double_as_longlong(x);
-    int lo = int(uint32_t(u)), hi = int(uint32_t(u >> 32));
-    switch (ctrl_sel) {
-        case 8:
-            lo = __builtin_amdgcn_mov_dpp(lo, 0x128, 0xf, 0xf, false);  // row_ror:8 = lane ^ 8
-            hi = __builtin_amdgcn_mov_dpp(hi, 0x128, 0xf, 0xf, false);
-            break;
-        case 4:
-            lo = __builtin_amdgcn_ds_swizzle(lo, (4 << 10) | 0x1F);  // lane ^ 4 within 32
-            hi = __builtin_amdgcn_ds_swizzle(hi, (4 << 10) | 0x1F);
-            break;
-        case 2:
-            lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
-            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xf, 0xf, false);
-            break;
-        default:
-            lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
-            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xf, 0xf, false);
-            break;
-    }
+    const int lo = __builtin_amdgcn_ds_swizzle(int(uint32_t(u)), (DIST << 10) | 0x1F);
+    const int hi = __builtin_amdgcn_ds_swizzle(int(uint32_t(u >> 32)), (DIST << 10) | 0x1F);
     return __longlong_as_double((int64_t(uint32_t(hi)) << 32) | uint32_t(lo));
 }
 
@@ -150,7 +139,7 @@ __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
         } else {
             const double sgn = (lane & dist) ? -1.0 : 1.0;
 #pragma unroll
-            for (int k = 0; k < S::V; ++k) t[k] = fma(sgn, t[k], dpp_f64(t[k], dist));
+            for (int k = 0; k < S::V; ++k) t[k] = fma(sgn, t[k], xor_lane_f64<dist>(t[k]));
         }
         cross_stages<LOGD, LOGV, B + 1>(t, lane);
     }
@@ -161,8 +150,10 @@ __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
 // measured on this GPU, writing 2 GB of such rows at a row stride of n keys
 // runs at 1.3 TB/s with 16-byte rows, 3.8 TB/s with 64-byte rows and
 // 5.5 TB/s with 128-byte or wider rows (a contiguous stream: 4.8 TB/s).
-template <int LOGD>
-constexpr int hash_waves() { return LOGD == 9 || LOGD == 10 ? 8 : LOGD == 11 ? 16 : 4; }
+template <int LOGD, int LOGV>
+constexpr int hash_waves() {
+    return LOGV == 4 ? (LOGD == 8 ? 8 : 4) : LOGD == 9 || LOGD == 10 ? 8 : LOGD == 11 ? 16 : 4;
+}
 
 // Waves per workgroup of the sparse kernel (its accumulators, 8 bytes per
 // column and point, take twice the stage's LDS).
@@ -208,16 +199,13 @@ __device__ inline int lane_rows(int lane) {
     return vlane;
 }
 
-// The FHT of a unit's sketch (Alg. 2) and its keys h_v, v >= 1, into the
-// stage at column wave*U + u.  t holds the lane's V sketch entries.
-template <int LOGD, int LOGV, int NW>
-__device__ inline void fht_keys_to_stage(double (&t)[1 << LOGV], int lane, int wave, uint32_t *stage) {
+// The FHT of a unit's sketch (Alg. 2), in place; returns S'' + 2^52 (S'' =
+// F''_0 sits in register 0 of the unit's lane with s = 0).  t holds the
+// lane's V sketch entries.
+template <int LOGD, int LOGV>
+__device__ inline double fht_unit(double (&t)[1 << LOGV], int lane) {
     using S = Shape<LOGD, LOGV>;
-    constexpr int V = S::V, U = S::U, PB = NW * U;
-    constexpr int PAD = stage_pad<LOGD>(), SH = stage_shift<LOGD>();
-    static_assert(SH <= S::LOGG, "the stage padding must split over lane and register index bits");
-    const int u = lane & (U - 1);
-    const int vlane = lane_rows<LOGD, LOGV>(lane);
+    constexpr int V = S::V, U = S::U;
     // Fast Hadamard transform (Alg. 2): in-register stages ...
 #pragma unroll
     for (int h = 1; h < V; h <<= 1) {
@@ -234,9 +222,34 @@ __device__ inline void fht_keys_to_stage(double (&t)[1 << LOGV], int lane, int w
     // first (the stages commute; this order keeps the register pressure of
     // the DPP stages away from the key extraction)
     cross_stages<LOGD, LOGV, 0>(t, lane);
+    return __shfl(t[0], lane & (U - 1), 64) + kTwo52;
+}
 
-    // S'' = F''_0 sits in register 0 of the unit's lane with s = 0.
-    const double Sm = __shfl(t[0], u, 64) + kTwo52;
+// The unit's keys from its transform: y[k] = h_v of the row held in
+// register k (z = 2^52 + 2y exactly, 2y < 2^44: the high word is the
+// exponent word kHiWord52 plus 2y >> 32, so y mod P (2^31 = 1) is
+// (lo >> 1) + hi - kHiWord52, below 2P).
+template <int LOGV>
+__device__ inline void extract_keys(const double (&t)[1 << LOGV], double Sm, uint32_t (&y)[1 << LOGV]) {
+#pragma unroll
+    for (int k = 0; k < (1 << LOGV); ++k) {
+        const uint64_t zb = __double_as_longlong(Sm - t[k]);
+        const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
+        uint32_t y2;  // half + hi - kHiWord52, below 2P, in one three-operand add
+        __asm__("v_add3_u32 %0, %1, %2, %3" : "=v"(y2) : "v"(half), "v"(hi), "s"(0u - kHiWord52));
+        y[k] = min(y2, y2 - kPrime);
+    }
+}
+
+// A unit's keys h_v, v >= 1, into the stage at column wave*U + u.
+template <int LOGD, int LOGV, int NW>
+__device__ inline void stage_keys(const uint32_t (&y)[1 << LOGV], int lane, int wave, uint32_t *stage) {
+    using S = Shape<LOGD, LOGV>;
+    constexpr int V = S::V, U = S::U, PB = NW * U;
+    constexpr int PAD = stage_pad<LOGD>(), SH = stage_shift<LOGD>();
+    static_assert(SH <= S::LOGG, "the stage padding must split over lane and register index bits");
+    const int u = lane & (U - 1);
+    const int vlane = lane_rows<LOGD, LOGV>(lane);
     // stage_index(vlane | vr, wave * U + u), split into a lane base and a
     // per-register constant
     const int sbase = vlane * PB + (vlane >> SH) * PAD + wave * U + u;
@@ -244,14 +257,7 @@ __device__ inline void fht_keys_to_stage(double (&t)[1 << LOGV], int lane, int w
     for (int k = 0; k < V; ++k) {
         const int vr = S::vreg(k);
         if (vr == 0 && vlane == 0) continue;  // row 0: all-zero codeword, dropped
-        // z = 2^52 + 2y exactly, 2y < 2^44: the high word is the exponent
-        // word kHiWord52 plus 2y >> 32, so y mod P (2^31 = 1) is
-        // (lo >> 1) + hi - kHiWord52, below 2P
-        const double z = Sm - t[k];
-        const uint64_t zb = __double_as_longlong(z);
-        const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
-        const uint32_t y = min(half + hi - kHiWord52, half + hi - (kHiWord52 + kPrime));
-        stage[sbase + vr * PB + (vr >> SH) * PAD] = y;
+        stage[sbase + vr * PB + (vr >> SH) * PAD] = y[k];
     }
 }
 
@@ -375,7 +381,9 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
             }
             __asm__ volatile("" ::: "memory");
             __builtin_amdgcn_wave_barrier();
-            fht_keys_to_stage<LOGD, LOGV, NW>(t, lane, wave, stage);
+            uint32_t y[V];
+            extract_keys<LOGV>(t, fht_unit<LOGD, LOGV>(t, lane), y);
+            stage_keys<LOGD, LOGV, NW>(y, lane, wave, stage);
         }
         __syncthreads();
         write_stage<LOGD, LOGV, NW>(stage, keys, key_stride, p, g0 * U, m);
@@ -462,7 +470,11 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_sparse_kernel(
     }
     __syncthreads();  // every wave has its sketch: the stage may overwrite the accumulators
     uint32_t *stage = reinterpret_cast<uint32_t *>(lds64);
-    if (grp < ngroups) fht_keys_to_stage<LOGD, LOGV, NW>(t, lane, wave, stage);
+    if (grp < ngroups) {
+        uint32_t y[V];
+        extract_keys<LOGV>(t, fht_unit<LOGD, LOGV>(t, lane), y);
+        stage_keys<LOGD, LOGV, NW>(y, lane, wave, stage);
+    }
     __syncthreads();
     write_stage<LOGD, LOGV, NW>(stage, keys, key_stride, p, g0 * U, m);
 }
@@ -479,7 +491,7 @@ template <int LOGD, int LOGV>
 fclsh_status launch_t(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys, int64_t key_stride,
                       hipStream_t st) {
     using S = Shape<LOGD, LOGV>;
-    constexpr int NW = hash_waves<LOGD>();
+    constexpr int NW = hash_waves<LOGD, LOGV>();
     const HashPlan &pl = ix.plan;
     const size_t lds = size_t(pl.E) * S::G * 8 + size_t(NW) * S::U * (2 * pl.W + 1) * 4 +
                        stage_words<LOGD, NW * S::U>() * 4;
@@ -523,21 +535,39 @@ fclsh_status launch_sparse_t(const Index &ix, const CsrRows &rows, int64_t m, ui
 
 }  // namespace
 
-// 32 sketch entries per lane (64 VGPRs of fp64) keep several waves per SIMD;
-// 64 only where a unit would otherwise need more than a wave (D = 4096).
-int hash_log_v(int logD) { return logD <= 5 ? logD : (logD - 6 > 5 ? logD - 6 : 5); }
+// 32 sketch entries per lane (64 VGPRs of fp64), 64 only where a unit would
+// otherwise need more than a wave (D = 4096).  The general construction at
+// D = 64..256 takes 16 per lane: its gather loop keeps many loads in flight,
+// and with half the registers for the sketch more waves fit a SIMD (4M
+// points, D = 128: 2.24 -> 1.78 ms), while the specific construction lost
+// with 16 (D = 512: 0.64 -> 0.87 ms).
+int hash_log_v(int logD, bool specific) {
+    if (!specific && logD >= 6 && logD <= 8) return 4;
+    return logD <= 5 ? logD : (logD - 6 > 5 ? logD - 6 : 5);
+}
 
 fclsh_status build_hash_plan(Index *ix) {
     const Params &p = ix->prm;
     HashPlan &pl = ix->plan;
     const int D = p.D();
     pl.logD = p.rp + 1;
-    pl.logV = hash_log_v(pl.logD);
+    pl.t = p.t;
+    pl.W = ix->W;
+    // column -> coordinates of each part
+    std::vector<std::vector<std::vector<int32_t>>> lists(p.sparse ? 0 : p.t, std::vector<std::vector<int32_t>>(D));
+    // (with replication, coordinate c of the replicated point is bit c mod d
+    // of the point: each bit feeds one column per copy)
+    size_t most = 0;
+    if (!p.sparse) {
+        for (int c = 0; c < p.dd(); ++c) lists[p.part[c]][p.col[c]].push_back(c);
+        for (auto &lp : lists)
+            for (auto &l : lp) most = std::max(most, l.size());
+    }
+    pl.specific = most <= 1;
+    pl.logV = hash_log_v(pl.logD, pl.specific);
     pl.V = 1 << pl.logV;
     pl.G = D / pl.V;
     pl.U = 64 / pl.G;
-    pl.t = p.t;
-    pl.W = ix->W;
     if (p.sparse) {
         // one (even representative, part << 16 | column) word pair per coordinate
         std::vector<uint32_t> coord(size_t(p.d) * 2);
@@ -552,16 +582,6 @@ fclsh_status build_hash_plan(Index *ix) {
     }
     const int G = pl.G, V = pl.V;
     const uint32_t zero_slot = coord_entry(uint32_t(64 * ix->W));  // reads the staged zero dword
-
-    // column -> coordinates of each part
-    std::vector<std::vector<std::vector<int32_t>>> lists(p.t, std::vector<std::vector<int32_t>>(D));
-    // (with replication, coordinate c of the replicated point is bit c mod d
-    // of the point: each bit feeds one column per copy)
-    for (int c = 0; c < p.dd(); ++c) lists[p.part[c]][p.col[c]].push_back(c);
-    size_t most = 0;
-    for (auto &lp : lists)
-        for (auto &l : lp) most = std::max(most, l.size());
-    pl.specific = most <= 1;
 
     // in-lane column k of sub-lane s is Hadamard column s*V + k; entries of k
     // are padded to the longest list among the G sub-lanes
@@ -603,6 +623,14 @@ fclsh_status build_hash_plan(Index *ix) {
 fclsh_status launch_hash(const Index &ix, const uint64_t *pts, int64_t m, uint32_t *keys,
                          int64_t key_stride, hipStream_t st) {
     if (m == 0) return FCLSH_OK;
+    if (ix.plan.logV == 4 && ix.plan.logD >= 6) {
+        switch (ix.plan.logD) {
+            case 6: return launch_t<6, 4>(ix, pts, m, keys, key_stride, st);
+            case 7: return launch_t<7, 4>(ix, pts, m, keys, key_stride, st);
+            case 8: return launch_t<8, 4>(ix, pts, m, keys, key_stride, st);
+            default: return fail(FCLSH_EUNSUPPORTED, "Hadamard order 2^%d with 16 entries per lane", ix.plan.logD);
+        }
+    }
     switch (ix.plan.logD) {
         case 1: return launch_t<1, 1>(ix, pts, m, keys, key_stride, st);
         case 2: return launch_t<2, 2>(ix, pts, m, keys, key_stride, st);

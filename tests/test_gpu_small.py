@@ -44,6 +44,7 @@ CASES = {
     "served_b": (lambda: synth.uniform_with_planted(701, 1024, 20, 6, 5, 1106, "served_b"), 3006, 0),  # t=2, D=2048
     "ragged_d": (lambda: synth.uniform_with_planted(1237, 100, 5, 9, 6, 1107, "ragged_d"), 3007, 0),
     "three_parts": (lambda: synth.uniform_with_planted(1500, 96, 9, 6, 6, 1108, "three_parts"), 3008, 3),
+    "general_d256": (lambda: synth.uniform_with_planted(2100, 300, 7, 8, 6, 1109, "general_d256"), 3009, 0),  # D=256
 }
 
 
