@@ -474,8 +474,19 @@ FCLSH_API void fclsh_graph_free(fclsh_graph graph);
 FCLSH_API fclsh_status fclsh_index_set_tuning(fclsh_index idx, int32_t tile, int32_t blocks_per_cu);
 FCLSH_API fclsh_status fclsh_index_get_tuning(fclsh_index idx, int32_t *tile, int32_t *blocks_per_cu);
 
+/* How the persistent verification waves share a batch's work (an
+ * implementation choice, no passage of the paper): 0 = a fixed stride (wave
+ * g of G takes rounds of 64 items g, g + G, ... and spill chunks likewise),
+ * 1 = claims from counters in the batch's control block (2 rounds of items,
+ * or 4 spill chunks, per atomic), which evens out uneven bucket sizes at the
+ * price of the atomics.  Both give identical answers.  Errors: FCLSH_EINVAL
+ * (released index, schedule not 0 or 1, null pointer). */
+FCLSH_API fclsh_status fclsh_index_set_schedule(fclsh_index idx, int32_t schedule);
+FCLSH_API fclsh_status fclsh_index_get_schedule(fclsh_index idx, int32_t *schedule);
+
 /* Autotuner: times the batched pipeline on a sample batch (device queries)
- * for a grid of (tile, blocks_per_cu) and keeps the fastest on the index; the
+ * for a grid of (tile, blocks_per_cu, schedule) and keeps the fastest on the
+ * index (the schedule chosen is read with fclsh_index_get_schedule); the
  * choice is also cached for later indexes of the same shape (d, t, r',
  * ceil(log2 n)) on the same device.  Each shape first runs once through the
  * synchronous path, which grows the stream's workspace until the run is

@@ -40,7 +40,7 @@ EXPORTS = [
     "fclsh_autotune", "fclsh_query_batch_finish", "fclsh_index_rebuild_async", "fclsh_index_build_mode",
     "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
     "fclsh_query_batch_noalloc", "fclsh_linear_scan", "fclsh_build_index_sparse", "fclsh_hash_sparse",
-    "fclsh_query_batch_sparse",
+    "fclsh_query_batch_sparse", "fclsh_index_set_schedule", "fclsh_index_get_schedule",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -114,6 +114,8 @@ def lib():
             "fclsh_build_index_sparse": [vp, vp, i64, i64, i32, i32, u64, P(BuildOpts), vp, P(vp)],
             "fclsh_hash_sparse": [vp, vp, vp, i64, i64, vp, vp],
             "fclsh_query_batch_sparse": [vp, vp, vp, i64, i64, i32, vp, vp, vp, i64, P(i64)],
+            "fclsh_index_set_schedule": [vp, i32],
+            "fclsh_index_get_schedule": [vp, P(i32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -451,10 +453,17 @@ class Index:
     def set_tuning(self, tile: int, blocks_per_cu: int):
         _check(lib().fclsh_index_set_tuning(self._h, tile, blocks_per_cu))
 
+    SCHEDULES = ("static", "claim")
+
+    def set_schedule(self, schedule: str):
+        """fclsh_index_set_schedule: "static" or "claim"."""
+        _check(lib().fclsh_index_set_schedule(self._h, self.SCHEDULES.index(schedule)))
+
     def get_tuning(self):
-        t, b = ctypes.c_int32(), ctypes.c_int32()
+        t, b, sc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().fclsh_index_get_tuning(self._h, ctypes.byref(t), ctypes.byref(b)))
-        return {"tile": t.value, "blocks_per_cu": b.value}
+        _check(lib().fclsh_index_get_schedule(self._h, ctypes.byref(sc)))
+        return {"tile": t.value, "blocks_per_cu": b.value, "schedule": self.SCHEDULES[sc.value]}
 
     def autotune(self, queries, r: int, stream=None):
         """Pick the batched launch shape on a sample batch; returns it with its time."""
@@ -462,7 +471,8 @@ class Index:
         t, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
         _check(lib().fclsh_autotune(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0], r, _stream_ptr(stream),
                                     ctypes.byref(t), ctypes.byref(b), ctypes.byref(ms)))
-        return {"tile": t.value, "blocks_per_cu": b.value, "ms": ms.value}
+        return {"tile": t.value, "blocks_per_cu": b.value, "schedule": self.get_tuning()["schedule"],
+                "ms": ms.value}
 
     def collisions(self, queries, stream=None):
         """#Collisions (Sec. 4.1) per query, int64 [nq]."""

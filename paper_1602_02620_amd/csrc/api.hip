@@ -887,7 +887,22 @@ fclsh_status fclsh_index_set_tuning(fclsh_index idx, int32_t tile, int32_t block
     if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     if (tile < 64 || tile > (1 << 20) || blocks_per_cu < 1 || blocks_per_cu > 64)
         return fail(FCLSH_EINVAL, "tile in [64, 2^20], blocks per CU in [1, 64]");
-    handle(idx)->ix.tuning = QueryTuning{tile, blocks_per_cu};
+    QueryTuning &tu = handle(idx)->ix.tuning;
+    tu.tile = tile;
+    tu.blocks_per_cu = blocks_per_cu;
+    return FCLSH_OK;
+}
+
+fclsh_status fclsh_index_set_schedule(fclsh_index idx, int32_t schedule) {
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    if (schedule != kScheduleStatic && schedule != kScheduleClaim) return fail(FCLSH_EINVAL, "schedule must be 0 or 1");
+    handle(idx)->ix.tuning.schedule = schedule;
+    return FCLSH_OK;
+}
+
+fclsh_status fclsh_index_get_schedule(fclsh_index idx, int32_t *schedule) {
+    if (!usable(idx) || !schedule) return fail(FCLSH_EINVAL, "null argument or released index");
+    *schedule = handle(idx)->ix.tuning.schedule;
     return FCLSH_OK;
 }
 
@@ -922,41 +937,43 @@ fclsh_status fclsh_autotune(fclsh_index idx, const uint64_t *d_queries, int64_t 
         return fail(FCLSH_EDEVICE, "hipEventCreate failed");
     const int tiles[] = {64, 128, 256, 512, 1024, 4096};
     const int bpcs[] = {2, 4, 8, 16};
+    const int schedules[] = {kScheduleStatic, kScheduleClaim};
     float best = -1.0f;
     QueryTuning best_t = saved;
     for (int tl : tiles)
-        for (int bp : bpcs) {
-            ix.tuning = QueryTuning{tl, bp};
-            // the synchronous path first: it grows the spill queue and the
-            // pair buffer until this shape's run is complete
-            int64_t got = 0;
-            s = query_batch(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total, &got);
-            if (s != FCLSH_OK) {
-                ix.tuning = saved;
-                return s;
-            }
-            FCLSH_HIP(hipEventRecord(buf.e0, st));
-            for (int rep = 0; rep < 3; ++rep) {
-                s = query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
+        for (int bp : bpcs)
+            for (int sc : schedules) {
+                ix.tuning = QueryTuning{tl, bp, sc};
+                // the synchronous path first: it grows the spill queue and the
+                // pair buffer until this shape's run is complete
+                int64_t got = 0;
+                s = query_batch(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total, &got);
                 if (s != FCLSH_OK) {
-                    (void)hipStreamSynchronize(st);
                     ix.tuning = saved;
                     return s;
                 }
+                FCLSH_HIP(hipEventRecord(buf.e0, st));
+                for (int rep = 0; rep < 3; ++rep) {
+                    s = query_batch_async(ix, ws, d_queries, nq, r_query, nullptr, st, offs, ids, total);
+                    if (s != FCLSH_OK) {
+                        (void)hipStreamSynchronize(st);
+                        ix.tuning = saved;
+                        return s;
+                    }
+                }
+                FCLSH_HIP(hipEventRecord(buf.e1, st));
+                FCLSH_HIP(hipEventSynchronize(buf.e1));
+                QueryCtrl c{};
+                FCLSH_HIP(hipMemcpy(&c, ws.ctrl, sizeof c, hipMemcpyDeviceToHost));
+                if (c.status != 0) continue;  // an overflowing run skipped work: not a valid timing
+                float ms = 0;
+                FCLSH_HIP(hipEventElapsedTime(&ms, buf.e0, buf.e1));
+                ms /= 3;
+                if (best < 0 || ms < best) {
+                    best = ms;
+                    best_t = ix.tuning;
+                }
             }
-            FCLSH_HIP(hipEventRecord(buf.e1, st));
-            FCLSH_HIP(hipEventSynchronize(buf.e1));
-            QueryCtrl c{};
-            FCLSH_HIP(hipMemcpy(&c, ws.ctrl, sizeof c, hipMemcpyDeviceToHost));
-            if (c.status != 0) continue;  // an overflowing run skipped work: not a valid timing
-            float ms = 0;
-            FCLSH_HIP(hipEventElapsedTime(&ms, buf.e0, buf.e1));
-            ms /= 3;
-            if (best < 0 || ms < best) {
-                best = ms;
-                best_t = ix.tuning;
-            }
-        }
     if (best < 0) {
         ix.tuning = saved;
         return fail(FCLSH_EDEVICE, "no launch shape completed the sample batch");

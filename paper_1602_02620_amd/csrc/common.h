@@ -102,7 +102,16 @@ struct CsrRows {
 struct QueryTuning {
     int tile = 256;          // bucket entries per work item / spill chunk
     int blocks_per_cu = 8;   // persistent workgroups per CU
+    int schedule = 0;        // kScheduleStatic or kScheduleClaim
 };
+// How the persistent verification waves share the work: a fixed stride
+// (wave g takes rounds g, g + G, ...) or claims from a counter in the batch's
+// control block (a wave takes kClaimRounds rounds of items, or kClaimChunks
+// spill chunks, per atomic).
+constexpr int kScheduleStatic = 0;
+constexpr int kScheduleClaim = 1;
+constexpr int kClaimRounds = 2;
+constexpr int kClaimChunks = 4;
 
 // Pass 2's group kernel form of a build (identical tables in every one):
 //   kFull      slot and ballot branches (every index's first build);
@@ -198,6 +207,8 @@ struct QueryCtrl {
     unsigned long long total;       // pairs, as published with the offsets
     uint32_t status;                // kQuery*Overflow bits
     uint32_t nlong;                 // segments the sort hands to its long-segment kernel
+    unsigned long long claim_items; // claimed item rounds x 64 (claim schedule)
+    unsigned long long claim_spill; // claimed spill chunks (claim schedule)
 };
 constexpr uint32_t kQueryPairOverflow = 1u;
 constexpr uint32_t kQuerySpillOverflow = 2u;

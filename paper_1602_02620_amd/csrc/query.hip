@@ -176,6 +176,7 @@ struct VerifyArgs {
     uint32_t *qcount;
     uint32_t tile;
     int table_major;  // item numbering, see item_coords
+    int schedule;     // kScheduleStatic or kScheduleClaim
 };
 
 // (query, table) of a verification item.  Large batches number the items
@@ -479,9 +480,23 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
     const unsigned long long items = (unsigned long long)(a.nq * a.L);
     const int64_t nb = int64_t(1) << a.dir_bits;
     const unsigned long long nw = (unsigned long long)gridDim.x * kVerifyWaves;
-    for (unsigned long long it0 = ((unsigned long long)blockIdx.x * kVerifyWaves + wave) * 64; it0 < items;
-         it0 += nw * 64) {
+    // static: wave g takes rounds g, g + nw, ...; claim: a wave takes
+    // kClaimRounds consecutive rounds per atomic on the control block
+    const bool claim = a.schedule == kScheduleClaim;
+    unsigned long long it0 = 0, claim_end = 0;
+    if (!claim) it0 = ((unsigned long long)blockIdx.x * kVerifyWaves + wave) * 64;
+    for (;;) {
+        if (claim) {
+            if (it0 >= claim_end) {
+                unsigned long long at = 0;
+                if (lane == 0) at = atomicAdd(&a.ctrl->claim_items, (unsigned long long)(kClaimRounds * 64));
+                it0 = __shfl(at, 0, 64);
+                claim_end = it0 + kClaimRounds * 64;
+            }
+        }
+        if (it0 >= items) break;  // wave-uniform
         const unsigned long long it = it0 + lane;
+        it0 += claim ? 64 : nw * 64;
         const bool valid = it < items;
         int64_t qi = 0;
         int T = 0;
@@ -563,12 +578,29 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyA
     if (lane == 0) __hip_atomic_store(ps.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     const unsigned long long nsp = min((unsigned long long)a.spill_cap, a.ctrl->spills);
     const unsigned long long nw = (unsigned long long)gridDim.x * kVerifyWaves;
-    for (unsigned long long k = (unsigned long long)blockIdx.x * kVerifyWaves + wave; k < nsp; k += nw) {
-        const uint4 r = a.spill[k];
-        int64_t qi;
-        int T;
-        item_coords(a, r.x, qi, T);
-        verify_range<SPARSE>(a, ps, spc, qi, T, r.y, r.z);
+    if (a.schedule == kScheduleClaim) {
+        // kClaimChunks chunks per atomic on the control block
+        for (;;) {
+            unsigned long long at = 0;
+            if (lane == 0) at = atomicAdd(&a.ctrl->claim_spill, (unsigned long long)kClaimChunks);
+            const unsigned long long k0 = __shfl(at, 0, 64);
+            if (k0 >= nsp) break;  // wave-uniform
+            for (unsigned long long k = k0; k < k0 + kClaimChunks && k < nsp; ++k) {
+                const uint4 r = a.spill[k];
+                int64_t qi;
+                int T;
+                item_coords(a, r.x, qi, T);
+                verify_range<SPARSE>(a, ps, spc, qi, T, r.y, r.z);
+            }
+        }
+    } else {
+        for (unsigned long long k = (unsigned long long)blockIdx.x * kVerifyWaves + wave; k < nsp; k += nw) {
+            const uint4 r = a.spill[k];
+            int64_t qi;
+            int T;
+            item_coords(a, r.x, qi, T);
+            verify_range<SPARSE>(a, ps, spc, qi, T, r.y, r.z);
+        }
     }
     flush_pairs(a, ps, stage_count(ps));
 }
@@ -1109,6 +1141,7 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     a.qcount = ws.qcount;
     a.tile = uint32_t(tu.tile);
     a.table_major = nq > kTableMajorBatch ? 1 : 0;
+    a.schedule = tu.schedule;
     if (sparse) {
         a.xptr = ix.sptr;
         a.xcols = ix.scols;

@@ -77,14 +77,22 @@ def test_spill_queue_for_large_buckets():
     idx = fc.Index(dev(pts), 128, 4, seed=91)
     want = oracle.brute_force(pts, 128, qs, 4).ids
     for tile, bpc in [(64, 1), (64, 8), (256, 4), (4096, 2)]:
-        idx.set_tuning(tile, bpc)
-        assert idx.get_tuning() == {"tile": tile, "blocks_per_cu": bpc}
-        assert_same_lists(csr_lists(*idx.query(dev(qs), 4)), want)
+        for schedule in ("static", "claim"):
+            idx.set_tuning(tile, bpc)
+            idx.set_schedule(schedule)
+            assert idx.get_tuning() == {"tile": tile, "blocks_per_cu": bpc, "schedule": schedule}
+            assert_same_lists(csr_lists(*idx.query(dev(qs), 4)), want)
+    with pytest.raises(fc.FclshError):
+        fc._check(fc.lib().fclsh_index_set_schedule(idx._h, 2))
     idx.close()
 
 
-def test_async_and_graph_replays(served):
+@pytest.mark.parametrize("schedule", ["static", "claim"])
+def test_async_and_graph_replays(served, schedule):
+    # the claim schedule's counters are cleared by the batch's first kernel,
+    # so every replay starts from zero
     w, idx = served
+    idx.set_schedule(schedule)
     nq = 16
     r = 8
     stream = torch.cuda.Stream()
@@ -119,6 +127,7 @@ def test_async_and_graph_replays(served):
         assert_same_lists(csr_lists(offsets, ids[:int(result[0])]), want)
         _ = torch.randn(1000, device="cuda").sum().item()  # unrelated eager work between replays
     g.close()
+    idx.set_schedule("static")
 
 
 def test_async_reports_overflow(served):
@@ -156,7 +165,8 @@ def test_autotune_keeps_answers(served):
     res = idx.autotune(dev(w.queries), 10)
     assert res["tile"] in (64, 128, 256, 512, 1024, 4096) and 1 <= res["blocks_per_cu"] <= 16
     assert res["ms"] > 0
-    assert idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"]}
+    assert idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"],
+                                "schedule": res["schedule"]}
     want = oracle.brute_force(w.points, w.d, w.queries, 10).ids
     assert_same_lists(csr_lists(*idx.query(dev(w.queries), 10)), want)
 
@@ -251,7 +261,8 @@ def test_autotune_with_heavy_buckets():
     want = oracle.brute_force(pts, 128, qs, 4).ids
     _say("[batch] autotune over heavy buckets")
     res = idx.autotune(dev(qs), 4)
-    assert res["ms"] > 0 and idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"]}
+    assert res["ms"] > 0 and idx.get_tuning() == {"tile": res["tile"], "blocks_per_cu": res["blocks_per_cu"],
+                                                  "schedule": res["schedule"]}
     assert_same_lists(csr_lists(*idx.query(dev(qs), 4)), want)
     idx.close()
 
