@@ -587,6 +587,7 @@ def sparse_section(args, fc, torch):
         hash_bytes = w.n * (8 + 4 * L) + 4 * w.cols.size
         offs, ids = idx.query(qptr, qcols, r)  # sizes the workspace
         got = fc.split_csr(offs, ids)
+        coll, cand = (x.to(torch.float64) for x in idx.cost(qptr, qcols))
         st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         st.record()
@@ -631,6 +632,7 @@ def sparse_section(args, fc, torch):
             "big_batch_queries": int(reps * w.nq), "big_batch_ms": ms_big,
             "big_batch_queries_per_s": reps * w.nq / (ms_big * 1e-3),
             "reported_ids_per_query": sum(len(g) for g in got) / w.nq,
+            "collisions_per_query": float(coll.mean().item()), "candidates_per_query": float(cand.mean().item()),
             "answers_equal_oracle": bool(equal), "repeats_answer_alike": same_rep,
             "cpu_baseline": {"kind": "oracle", "cores": oracle.num_threads(),
                              "linear_scan_ms_per_query": t_bf * 1e3 / w.nq,

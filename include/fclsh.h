@@ -220,6 +220,15 @@ FCLSH_API fclsh_status fclsh_query_batch_sparse(fclsh_index idx, const int64_t *
                                                 uint64_t *d_offsets, uint32_t *d_ids,
                                                 int64_t ids_capacity, int64_t *total_out);
 
+/* fclsh_query_cost for nq query rows (sparse index only): Sec. 4.1's
+ * #Collisions and #Candidates per query, the measures of the paper's sparse
+ * experiments.  The rows are checked first (FCLSH_EINVAL if malformed).
+ * Synchronises `stream`. */
+FCLSH_API fclsh_status fclsh_query_cost_sparse(fclsh_index idx, const int64_t *d_ptr,
+                                               const int32_t *d_cols, int64_t nq, int64_t nnz,
+                                               void *stream, uint64_t *d_collisions,
+                                               uint64_t *d_candidates);
+
 /* ---------------------------------------------------------------------------
  * Exact r-NN reporting for a batch of queries (Def. 2, Strategy 2 of
  * Sec. 2.2 with Steps S1-S3 of Sec. 4.1): for each query, every data point id

@@ -41,6 +41,7 @@ EXPORTS = [
     "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
     "fclsh_query_batch_noalloc", "fclsh_linear_scan", "fclsh_build_index_sparse", "fclsh_hash_sparse",
     "fclsh_query_batch_sparse", "fclsh_index_set_schedule", "fclsh_index_get_schedule",
+    "fclsh_query_cost_sparse",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -115,6 +116,7 @@ def lib():
             "fclsh_hash_sparse": [vp, vp, vp, i64, i64, vp, vp],
             "fclsh_query_batch_sparse": [vp, vp, vp, i64, i64, i32, vp, vp, vp, i64, P(i64)],
             "fclsh_index_set_schedule": [vp, i32],
+            "fclsh_query_cost_sparse": [vp, vp, vp, i64, i64, vp, vp, vp],
             "fclsh_index_get_schedule": [vp, P(i32)],
         }
         for name, args in sig.items():
@@ -557,6 +559,18 @@ class SparseIndex(Index):
                                             ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
                                             cap, ctypes.byref(total))
         return self._collect(st, offsets, ids, total, nq, stream, True, ids_capacity is not None)
+
+    def cost(self, ptr, cols, stream=None):
+        """Sec. 4.1's #Collisions and #Candidates per query row: (int64 [nq], int64 [nq])."""
+        torch = _torch()
+        ptr, cols = _dev_rows(ptr, cols, "queries")
+        nq = ptr.numel() - 1
+        coll = torch.empty(nq, dtype=torch.int64, device=ptr.device)
+        cand = torch.empty_like(coll)
+        _check(lib().fclsh_query_cost_sparse(self._h, ctypes.c_void_p(ptr.data_ptr()), ctypes.c_void_p(cols.data_ptr()),
+                                             nq, cols.numel(), _stream_ptr(stream), ctypes.c_void_p(coll.data_ptr()),
+                                             ctypes.c_void_p(cand.data_ptr())))
+        return coll, cand
 
 
 class QueryGraph:

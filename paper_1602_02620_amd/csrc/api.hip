@@ -710,6 +710,20 @@ fclsh_status fclsh_query_cost(fclsh_index idx, const uint64_t *d_queries, int64_
     return query_cost(h->ix, *h->workspace(st), d_queries, nq, d_collisions, d_candidates, st);
 }
 
+fclsh_status fclsh_query_cost_sparse(fclsh_index idx, const int64_t *d_ptr, const int32_t *d_cols, int64_t nq,
+                                     int64_t nnz, void *stream, uint64_t *d_collisions, uint64_t *d_candidates) {
+    FCLSH_TRY(need_format(idx, true));
+    if (nq < 0 || nq > 0x7FFFFFFFll || nnz < 0 || (nq && (!d_ptr || !d_collisions || !d_candidates)) ||
+        (nnz > 0 && !d_cols))
+        return fail(FCLSH_EINVAL, "bad arguments");
+    if (nq == 0) return FCLSH_OK;
+    IndexHandle *h = handle(idx);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const CsrRows rows{d_ptr, d_cols, nnz};
+    FCLSH_TRY(check_rows(rows, nq, h->ix.prm.d, st));
+    return query_cost(h->ix, *h->workspace(st), nullptr, nq, d_collisions, d_candidates, st, &rows);
+}
+
 fclsh_status fclsh_linear_scan(const uint64_t *d_points, int64_t n, int32_t d, const uint64_t *d_queries,
                                int64_t nq, int32_t r, void *stream, uint64_t *d_offsets, uint32_t *d_ids,
                                int64_t ids_capacity, int64_t *total_out) {

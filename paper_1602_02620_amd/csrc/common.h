@@ -256,7 +256,7 @@ fclsh_status query_plain(Index &ix, QueryWorkspace &ws, const uint64_t *queries,
 fclsh_status query_collisions(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq,
                               uint64_t *coll, hipStream_t st);
 fclsh_status query_cost(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, uint64_t *coll,
-                        uint64_t *cand, hipStream_t st);
+                        uint64_t *cand, hipStream_t st, const CsrRows *sq = nullptr);
 // Exclusive scan of n uint64 (in place allowed) using caller-provided
 // partials (scan_partials_needed(n) entries): no allocation, graph-safe.
 int64_t scan_partials_needed(int64_t n);

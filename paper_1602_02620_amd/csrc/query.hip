@@ -1011,7 +1011,7 @@ __global__ void cost_clear_kernel(uint32_t *__restrict__ bitmap, int64_t words, 
 // #Collisions and #Candidates of Sec. 4.1 for a batch, in chunks of queries
 // whose bitmaps fit a fixed budget.
 fclsh_status query_cost(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, uint64_t *coll,
-                        uint64_t *cand, hipStream_t st) {
+                        uint64_t *cand, hipStream_t st, const CsrRows *sq) {
     const int L = ix.prm.L();
     const int64_t bm_words = (ix.n + 31) / 32;
     constexpr int64_t kBitmapBudget = int64_t(256) << 20;
@@ -1029,7 +1029,8 @@ fclsh_status query_cost(Index &ix, QueryWorkspace &ws, const uint64_t *queries, 
         auto *d0 = reinterpret_cast<unsigned long long *>(cand + q0);
         hipLaunchKernelGGL(cost_clear_kernel, dim3(grid_for(qn * bm_words, 256, 4096)), dim3(256), 0, st, bitmap,
                            qn * bm_words, c0, d0, qn);
-        s = launch_hash(ix, queries + q0 * ix.W, qn, ws.qkeys, qn, st);
+        s = sq ? launch_hash_sparse(ix, CsrRows{sq->ptr + q0, sq->cols, sq->nnz}, qn, ws.qkeys, qn, st)
+               : launch_hash(ix, queries + q0 * ix.W, qn, ws.qkeys, qn, st);
         if (s != FCLSH_OK) break;
         hipLaunchKernelGGL(cost_kernel, dim3(grid_for(qn * L, 4, 1u << 16)), dim3(256), 0, st, ws.qkeys, qn, L,
                            ix.tkeys, ix.tids, ix.dir, ix.n, ix.dir_bits, bitmap, bm_words, c0, d0);

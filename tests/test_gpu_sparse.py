@@ -250,3 +250,22 @@ def test_bitmap_and_first_table_dedupe_agree():
     for k in range(0, reps * w.nq, 997):
         assert np.array_equal(big[k], small[k % w.nq]), k
     idx.close()
+
+
+def test_cost_counters_match_oracle():
+    # Sec. 4.1's #Collisions and #Candidates of query rows against the
+    # oracle's Strategy 2 on the same points as bit vectors
+    w = small_sparse(700, 3000, 6, 9, 20.0, 1211)
+    idx = fc.SparseIndex(*rows(w.ptr, w.cols), w.d, w.r, seed=4011)
+    pr = oracle.derive_params(w.d, w.r, 4011)
+    pts, qs = w.dense_points(), w.dense_queries()
+    keys = oracle.keys(pts, pr)
+    tk, ti = oracle.tables(keys)
+    want = oracle.query_batch(pts, w.d, tk, ti, qs, oracle.keys(qs, pr), w.r)
+    coll, cand = idx.cost(*rows(w.qptr, w.qcols))
+    assert np.array_equal(coll.cpu().numpy(), want.collisions)
+    assert np.array_equal(cand.cpu().numpy(), want.candidates)
+    with pytest.raises(fc.FclshError) as e:
+        idx.cost(*rows(np.array([0, 2], np.int64), np.array([5, 1], np.int32)))
+    assert e.value.status == fc.FCLSH_EINVAL
+    idx.close()
