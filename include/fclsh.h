@@ -300,14 +300,25 @@ FCLSH_API fclsh_status fclsh_index_params(fclsh_index idx, int32_t *part, int32_
 FCLSH_API fclsh_status fclsh_hash(fclsh_index idx, const uint64_t *d_pts, int64_t m,
                         uint32_t *d_keys, void *stream);
 
-/* Device pointers of the index's tables: keys and ids [L][n] uint32 (table T
- * at offset T*n, grouped by directory bin, ids ascending within a bin; see
- * fclsh_build_index), directory [L][2^dir_bits + 1] uint32 (start of the
- * entries whose key has the given top dir_bits bits of 31) and the point
- * copy [n][W] uint64.  Owned by the index; read only. */
-FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys,
-                                const uint32_t **d_tids, const uint32_t **d_dir,
-                                const uint64_t **d_points);
+/* Device pointers of the index's tables: keys [L][n] of *key_bytes bytes
+ * each and ids [L][n] uint32 (table T at offset T*n, grouped by directory
+ * bin, ids ascending within a bin; see fclsh_build_index), directory
+ * [L][2^dir_bits + 1] uint32 (start of the entries whose key has the given
+ * top dir_bits bits of 31) and the point copy [n][W] uint64 (NULL for a
+ * sparse index).  A key is stored whole (key_bytes 4) or, when the 31 -
+ * dir_bits key bits below the bin fit 16 bits (dir_bits >= 15, n >= 2^17),
+ * as its low 16 bits (key_bytes 2): the bin supplies the rest
+ * (fclsh_index_table_keys writes whole keys).  Owned by the index; read
+ * only.  Any output pointer may be NULL. */
+FCLSH_API fclsh_status fclsh_index_tables(fclsh_index idx, const void **d_tkeys,
+                                int32_t *key_bytes, const uint32_t **d_tids,
+                                const uint32_t **d_dir, const uint64_t **d_points);
+
+/* Whole 31-bit keys of tables [T0, T1) into d_keys (device, [T1-T0][n]
+ * uint32), in the tables' order; asynchronous on `stream`.  Errors:
+ * FCLSH_EINVAL (released index, range outside [0, L], null output). */
+FCLSH_API fclsh_status fclsh_index_table_keys(fclsh_index idx, int32_t T0, int32_t T1,
+                                              uint32_t *d_keys, void *stream);
 
 /* Rebuild the tables of an existing index from its own points (the bucketing
  * step alone: hash + table build), for timing.  Synchronises `stream`. */

@@ -41,7 +41,7 @@ EXPORTS = [
     "fclsh_preprocessing", "fclsh_index_memory", "fclsh_query_cost",
     "fclsh_query_batch_noalloc", "fclsh_linear_scan", "fclsh_build_index_sparse", "fclsh_hash_sparse",
     "fclsh_query_batch_sparse", "fclsh_index_set_schedule", "fclsh_index_get_schedule",
-    "fclsh_query_cost_sparse",
+    "fclsh_query_cost_sparse", "fclsh_index_table_keys",
 ]
 
 # status bits of the device result of fclsh_query_batch_async
@@ -93,7 +93,8 @@ def lib():
             "fclsh_index_memory": [vp, P(u64), P(u64), P(u64)],
             "fclsh_index_params": [vp, vp, vp, vp],
             "fclsh_hash": [vp, vp, i64, vp, vp],
-            "fclsh_index_tables": [vp, P(vp), P(vp), P(vp), P(vp)],
+            "fclsh_index_tables": [vp, P(vp), P(i32), P(vp), P(vp), P(vp)],
+            "fclsh_index_table_keys": [vp, i32, i32, vp, vp],
             "fclsh_index_rebuild": [vp, vp],
             "fclsh_index_rebuild_async": [vp, vp],
             "fclsh_index_rebuild_timed": [vp, vp, P(ctypes.c_float), i32],
@@ -325,21 +326,24 @@ class Index:
         return dict(zip(self.REBUILD_PHASES, (float(x) for x in ms)))
 
     def table_pointers(self):
+        """(keys, ids, directory, points) device addresses and the bytes per stored key."""
         k, i, dr, p = (ctypes.c_void_p() for _ in range(4))
-        _check(lib().fclsh_index_tables(self._h, ctypes.byref(k), ctypes.byref(i), ctypes.byref(dr),
-                                        ctypes.byref(p)))
-        return k.value, i.value, dr.value, p.value
+        kb = ctypes.c_int32()
+        _check(lib().fclsh_index_tables(self._h, ctypes.byref(k), ctypes.byref(kb), ctypes.byref(i),
+                                        ctypes.byref(dr), ctypes.byref(p)))
+        return k.value, i.value, dr.value, p.value, kb.value
 
     def tables(self, T0: int = 0, T1: int | None = None):
-        """Copies of tables [T0, T1): (keys, ids) as int32 CUDA tensors [T1-T0, n]."""
+        """Copies of tables [T0, T1): (whole keys, ids) as int32 CUDA tensors [T1-T0, n]."""
         torch = _torch()
         inf = self.info
         n, L = inf["n"], inf["L"]
         T1 = L if T1 is None else T1
-        kp, ip, _, _ = self.table_pointers()
+        _, ip, _, _, _ = self.table_pointers()
         keys = torch.empty((T1 - T0, n), dtype=torch.int32, device=self.device)
         ids = torch.empty_like(keys)
-        _memcpy_d2d(keys.data_ptr(), kp + T0 * n * 4, (T1 - T0) * n * 4)
+        _check(lib().fclsh_index_table_keys(self._h, T0, T1, ctypes.c_void_p(keys.data_ptr()),
+                                            _stream_ptr(None)))
         _memcpy_d2d(ids.data_ptr(), ip + T0 * n * 4, (T1 - T0) * n * 4)
         return keys, ids
 
@@ -347,7 +351,7 @@ class Index:
         torch = _torch()
         inf = self.info
         nb = (1 << inf["dir_bits"]) + 1
-        _, _, dp, _ = self.table_pointers()
+        _, _, dp, _, _ = self.table_pointers()
         out = torch.empty((inf["L"], nb), dtype=torch.int32, device=self.device)
         _memcpy_d2d(out.data_ptr(), dp, inf["L"] * nb * 4)
         return out

@@ -132,7 +132,7 @@ static void lookup_tuning(Index &ix);
 static size_t estimate_index_bytes(const Params &p, int64_t n, int W, int64_t nnz, int dir_bits) {
     const size_t L = size_t(p.L());
     size_t b = p.sparse ? size_t(n + 1) * 8 + size_t(nnz) * 4 : size_t(n) * W * 8;  // point copy
-    b += 2 * L * size_t(n) * 4;                          // table keys + ids
+    b += L * size_t(n) * (4 + size_t(table_key_bytes(dir_bits)));  // table ids + keys
     b += L * ((size_t(1) << dir_bits) + 1) * 4;          // directories
     b += 3 * L * size_t(n) * 4;                          // build scratch: keys + 2 partition buffers
     b += table_build_scratch_bytes(int64_t(L), n, dir_bits);  // histograms, group starts, lists
@@ -246,6 +246,7 @@ static fclsh_status build_common(const uint64_t *d_points, const CsrRows *rows, 
     ix.W = words_of(ix.prm.d);
     ix.n = n;
     ix.dir_bits = table_dir_bits(n);
+    ix.key_bytes = table_key_bytes(ix.dir_bits);
     ix.budget = budget;
     (void)hipGetDevice(&ix.device);
     {
@@ -277,7 +278,7 @@ static fclsh_status build_common(const uint64_t *d_points, const CsrRows *rows, 
     } else if ((s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.pts), size_t(n) * ix.W * 8, "points"))) {
         return bail(s);
     }
-    if ((s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tkeys), size_t(L * n) * 4, "table keys")) ||
+    if ((s = dev_alloc(&ix, &ix.tkeys, size_t(L * n) * size_t(ix.key_bytes), "table keys")) ||
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.tids), size_t(L * n) * 4, "table ids")) ||
         (s = dev_alloc(&ix, reinterpret_cast<void **>(&ix.dir),
                        size_t(L) * ((size_t(1) << ix.dir_bits) + 1) * 4, "directory")) ||
@@ -593,15 +594,25 @@ fclsh_status fclsh_hash_sparse(fclsh_index idx, const int64_t *d_ptr, const int3
                               reinterpret_cast<hipStream_t>(stream));
 }
 
-fclsh_status fclsh_index_tables(fclsh_index idx, const uint32_t **d_tkeys, const uint32_t **d_tids,
+fclsh_status fclsh_index_tables(fclsh_index idx, const void **d_tkeys, int32_t *key_bytes, const uint32_t **d_tids,
                                 const uint32_t **d_dir, const uint64_t **d_points) {
     if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
     const Index &ix = handle(idx)->ix;
     if (d_tkeys) *d_tkeys = ix.tkeys;
+    if (key_bytes) *key_bytes = ix.key_bytes;
     if (d_tids) *d_tids = ix.tids;
     if (d_dir) *d_dir = ix.dir;
     if (d_points) *d_points = ix.pts;
     return FCLSH_OK;
+}
+
+fclsh_status fclsh_index_table_keys(fclsh_index idx, int32_t T0, int32_t T1, uint32_t *d_keys, void *stream) {
+    if (!usable(idx)) return fail(FCLSH_EINVAL, "null or released index");
+    const Index &ix = handle(idx)->ix;
+    if (T0 < 0 || T1 < T0 || T1 > ix.prm.L() || (T1 > T0 && !d_keys))
+        return fail(FCLSH_EINVAL, "tables [%d, %d) outside [0, %d) or null output", T0, T1, ix.prm.L());
+    return expand_table_keys(ix.tkeys, ix.key_bytes, ix.dir, ix.n, ix.dir_bits, T0, T1, d_keys,
+                             reinterpret_cast<hipStream_t>(stream));
 }
 
 fclsh_status fclsh_index_rebuild(fclsh_index idx, void *stream) {

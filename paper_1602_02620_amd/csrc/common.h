@@ -133,7 +133,8 @@ struct Index {
     uint64_t budget = 0;
     HashPlan plan;
     uint64_t *pts = nullptr;   // [n][W]
-    uint32_t *tkeys = nullptr; // [L][n]
+    void *tkeys = nullptr;     // [L][n] of key_bytes each (the low 16 bits, or the whole key)
+    int key_bytes = 4;
     uint32_t *tids = nullptr;  // [L][n]
     uint32_t *dir = nullptr;   // [L][2^dir_bits + 1]
     // per-index device copies of part/col for the duplicate-elimination rule
@@ -194,8 +195,16 @@ int table_split_bits(int64_t n, int dir_bits);
 int table_merge_bits(int64_t n, int dir_bits);
 size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits);
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
-                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
+                                uint32_t *scratch, void *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
                                 hipStream_t st, hipEvent_t *marks = nullptr);
+// Bytes per stored table key: 2 when the key bits below the directory bin
+// (31 - dir_bits) fit 16 bits, so that a bin's keys are told apart by their
+// low 16 bits, else 4.
+int table_key_bytes(int dir_bits);
+// Whole 31-bit keys of tables [T0, T1) into out [T1-T0][n] (the bin bits
+// from the directory), on st.
+fclsh_status expand_table_keys(const void *tkeys, int key_bytes, const uint32_t *dir, int64_t n, int dir_bits, int T0,
+                               int T1, uint32_t *out, hipStream_t st);
 // Pass 2's counters in the scratch after a build: [0] groups listed for the
 // second kernel, [1] groups that took the ballot branch.
 const uint32_t *table_build_counts(const uint32_t *scratch, int64_t L, int64_t n, int dir_bits);

@@ -164,7 +164,8 @@ struct VerifyArgs {
     int64_t seen_wpq;
     const int32_t *rq_vec;  // per-query radius, or null: rq for all
     int rq;
-    const uint32_t *tkeys, *tids, *dir;
+    const void *tkeys;  // [L][n] KT: the low 16 bits of the keys, or the keys (key_bytes 2 or 4)
+    const uint32_t *tids, *dir;
     int64_t n;
     int dir_bits;
     const uint32_t *qkeys;  // [L][nq]
@@ -377,13 +378,14 @@ __device__ inline const uint32_t *stage_pc(const VerifyArgs &a, uint32_t *spc) {
 
 // Whole wave, uniform arguments: entries [j0, j1) of table T (absolute
 // positions), a lane per entry.
-template <bool SPARSE>
+template <bool SPARSE, typename KT>
 __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, const uint32_t *spc, int64_t qi,
                                     int T, uint32_t j0, uint32_t j1) {
     const int lane = threadIdx.x & 63;
     const uint32_t qkey = a.qkeys[int64_t(T) * a.nq + qi];
+    const uint32_t qk = uint32_t(KT(qkey));  // the stored part of the key (the bin holds the rest)
     const uint32_t *ids = a.tids + int64_t(T) * a.n;
-    const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
+    const KT *bk = static_cast<const KT *>(a.tkeys) + int64_t(T) * a.n;
     const int rq = query_radius(a, qi);
     // four rounds of 64 entries at a time: their keys and ids are loaded
     // together (independent loads), then the matches are verified
@@ -393,7 +395,7 @@ __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, co
 #pragma unroll
         for (int k = 0; k < R4; ++k) {
             const uint32_t j = b0 + uint32_t(k) * 64u + uint32_t(lane);
-            key[k] = bk[min(j, j1 - 1)];  // clamped, so the loads need no branch
+            key[k] = uint32_t(bk[min(j, j1 - 1)]);  // clamped, so the loads need no branch
             id[k] = ids[min(j, j1 - 1)];
         }
         // the lane's matches among its R4 entries, verified one per round
@@ -401,7 +403,7 @@ __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, co
         uint32_t mm = 0;
 #pragma unroll
         for (int k = 0; k < R4; ++k)
-            mm |= uint32_t(key[k] == qkey && b0 + uint32_t(k) * 64u + uint32_t(lane) < j1) << k;
+            mm |= uint32_t(key[k] == qk && b0 + uint32_t(k) * 64u + uint32_t(lane) < j1) << k;
         while (mm) {
             const int k = __builtin_ctz(mm);
             mm &= mm - 1;
@@ -416,8 +418,9 @@ __device__ inline void verify_range(const VerifyArgs &a, const PairStage &ps, co
 // S2: per (query, table) the query's directory bin [start, start+len) in
 // table T and the number of entries in it whose key equals the query's key
 // (the bucket size, i.e. this table's share of #Collisions).
+template <typename KT>
 __global__ void lookup_kernel(const uint32_t *__restrict__ qkeys, int64_t nq, int L,
-                              const uint32_t *__restrict__ tkeys, const uint32_t *__restrict__ dir, int64_t n,
+                              const KT *__restrict__ tkeys, const uint32_t *__restrict__ dir, int64_t n,
                               int dir_bits, uint32_t *__restrict__ rstart, uint32_t *__restrict__ rlen,
                               uint32_t *__restrict__ rmatch) {
     const int64_t total = nq * L;
@@ -427,12 +430,12 @@ __global__ void lookup_kernel(const uint32_t *__restrict__ qkeys, int64_t nq, in
         const int T = int(g / nq);
         const int64_t qi = g - int64_t(T) * nq;
         const uint32_t key = qkeys[g];
-        const uint32_t *tk = tkeys + int64_t(T) * n;
+        const KT *tk = tkeys + int64_t(T) * n;
         const uint32_t *dr = dir + int64_t(T) * (nb + 1);
         const uint32_t bin = key >> (31 - dir_bits);
         const uint32_t lo = dr[bin], hi = dr[bin + 1];
         uint32_t m = 0;
-        for (uint32_t j = lo; j < hi; ++j) m += tk[j] == key;
+        for (uint32_t j = lo; j < hi; ++j) m += tk[j] == KT(key);
         rstart[qi * L + T] = lo;
         rlen[qi * L + T] = hi - lo;
         rmatch[qi * L + T] = m;
@@ -469,7 +472,7 @@ __global__ void reset_kernel(QueryCtrl *ctrl, uint32_t *qcount, uint32_t *qfill,
 // probes the directory; a bin of at most kLaneBin entries is scanned and
 // verified by the lane alone, a larger one is cut into `tile`-entry chunks on
 // the spill queue.
-template <bool SPARSE>
+template <bool SPARSE, typename KT>
 __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyArgs a) {
     __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
     extern __shared__ uint32_t dyn_pc[];
@@ -532,7 +535,8 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
                 }
         }
         if (!valid || nch) continue;
-        const uint32_t *bk = a.tkeys + int64_t(T) * a.n;
+        const KT *bk = static_cast<const KT *>(a.tkeys) + int64_t(T) * a.n;
+        const uint32_t qk = uint32_t(KT(qkey));  // the stored part of the key (the bin holds the rest)
         const uint32_t *ids = a.tids + int64_t(T) * a.n;
         const int rq = query_radius(a, qi);
         // the bin's keys in chunks of 8 independent loads, giving the mask of
@@ -544,10 +548,10 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
             // masked below
             uint32_t kk[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) kk[c] = bk[min(j0 + uint32_t(c), hi - 1)];
+            for (int c = 0; c < 8; ++c) kk[c] = uint32_t(bk[min(j0 + uint32_t(c), hi - 1)]);
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                mm |= uint32_t(kk[c] == qkey && j0 + uint32_t(c) < hi) << (j0 - lo + uint32_t(c));
+                mm |= uint32_t(kk[c] == qk && j0 + uint32_t(c) < hi) << (j0 - lo + uint32_t(c));
         }
         // then the matches, one per lane at a time: the lanes verify their
         // k-th matches together, so the wave runs as many rounds of the
@@ -568,7 +572,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_items_kernel(VerifyA
 // batch number up to the hundreds of thousands: a shared claim counter would
 // serialise that many atomics on one address, while the fixed stride spreads
 // the chunks' uneven costs over tens of chunks per wave.
-template <bool SPARSE>
+template <bool SPARSE, typename KT>
 __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyArgs a) {
     __shared__ uint32_t stq[kVerifyWaves][kPairBuf], sti[kVerifyWaves][kPairBuf], stc[kVerifyWaves];
     extern __shared__ uint32_t dyn_pc[];
@@ -590,7 +594,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyA
                 int64_t qi;
                 int T;
                 item_coords(a, r.x, qi, T);
-                verify_range<SPARSE>(a, ps, spc, qi, T, r.y, r.z);
+                verify_range<SPARSE, KT>(a, ps, spc, qi, T, r.y, r.z);
             }
         }
     } else {
@@ -599,7 +603,7 @@ __global__ __launch_bounds__(64 * kVerifyWaves) void verify_spill_kernel(VerifyA
             int64_t qi;
             int T;
             item_coords(a, r.x, qi, T);
-            verify_range<SPARSE>(a, ps, spc, qi, T, r.y, r.z);
+            verify_range<SPARSE, KT>(a, ps, spc, qi, T, r.y, r.z);
         }
     }
     flush_pairs(a, ps, stage_count(ps));
@@ -929,8 +933,14 @@ void ws_release(QueryWorkspace &ws) {
 fclsh_status query_lookup(Index &ix, QueryWorkspace &ws, const uint64_t *queries, int64_t nq, hipStream_t st) {
     const int L = ix.prm.L();
     FCLSH_TRY(launch_hash(ix, queries, nq, ws.qkeys, nq, st));
-    hipLaunchKernelGGL(lookup_kernel, dim3(grid_for(nq * L, 256)), dim3(256), 0, st, ws.qkeys, nq, L, ix.tkeys,
-                       ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rlen, ws.rmatch);
+    if (ix.key_bytes == 2)
+        hipLaunchKernelGGL(lookup_kernel<uint16_t>, dim3(grid_for(nq * L, 256)), dim3(256), 0, st, ws.qkeys, nq, L,
+                           static_cast<const uint16_t *>(ix.tkeys), ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rlen,
+                           ws.rmatch);
+    else
+        hipLaunchKernelGGL(lookup_kernel<uint32_t>, dim3(grid_for(nq * L, 256)), dim3(256), 0, st, ws.qkeys, nq, L,
+                           static_cast<const uint32_t *>(ix.tkeys), ix.dir, ix.n, ix.dir_bits, ws.rstart, ws.rlen,
+                           ws.rmatch);
     FCLSH_HIP(hipGetLastError());
     return FCLSH_OK;
 }
@@ -954,8 +964,9 @@ namespace {
 // (query-major, so a query's tables share its bitmap in cache); the lanes
 // stride over the item's directory bin and keep the entries whose key equals
 // the query's.  Wave totals go to the per-query counters with one atomic each.
+template <typename KT>
 __global__ __launch_bounds__(256) void cost_kernel(const uint32_t *__restrict__ qkeys, int64_t qn, int L,
-                                                   const uint32_t *__restrict__ tkeys,
+                                                   const KT *__restrict__ tkeys,
                                                    const uint32_t *__restrict__ tids,
                                                    const uint32_t *__restrict__ dir, int64_t n, int dir_bits,
                                                    uint32_t *__restrict__ bitmap, int64_t bm_words,
@@ -972,12 +983,12 @@ __global__ __launch_bounds__(256) void cost_kernel(const uint32_t *__restrict__ 
         const uint32_t *dr = dir + int64_t(T) * (nb + 1);
         const uint32_t bin = key >> (31 - dir_bits);
         const uint32_t lo = dr[bin], hi = dr[bin + 1];
-        const uint32_t *tk = tkeys + int64_t(T) * n;
+        const KT *tk = tkeys + int64_t(T) * n;
         const uint32_t *ti = tids + int64_t(T) * n;
         uint32_t *bm = bitmap + ql * bm_words;
         uint32_t nc = 0, nd = 0;
         for (uint32_t j = lo + uint32_t(lane); j < hi; j += 64) {
-            if (tk[j] != key) continue;
+            if (tk[j] != KT(key)) continue;
             const uint32_t id = ti[j];
             const uint32_t bit = 1u << (id & 31u);
             ++nc;
@@ -1032,8 +1043,14 @@ fclsh_status query_cost(Index &ix, QueryWorkspace &ws, const uint64_t *queries, 
         s = sq ? launch_hash_sparse(ix, CsrRows{sq->ptr + q0, sq->cols, sq->nnz}, qn, ws.qkeys, qn, st)
                : launch_hash(ix, queries + q0 * ix.W, qn, ws.qkeys, qn, st);
         if (s != FCLSH_OK) break;
-        hipLaunchKernelGGL(cost_kernel, dim3(grid_for(qn * L, 4, 1u << 16)), dim3(256), 0, st, ws.qkeys, qn, L,
-                           ix.tkeys, ix.tids, ix.dir, ix.n, ix.dir_bits, bitmap, bm_words, c0, d0);
+        if (ix.key_bytes == 2)
+            hipLaunchKernelGGL(cost_kernel<uint16_t>, dim3(grid_for(qn * L, 4, 1u << 16)), dim3(256), 0, st, ws.qkeys,
+                               qn, L, static_cast<const uint16_t *>(ix.tkeys), ix.tids, ix.dir, ix.n, ix.dir_bits,
+                               bitmap, bm_words, c0, d0);
+        else
+            hipLaunchKernelGGL(cost_kernel<uint32_t>, dim3(grid_for(qn * L, 4, 1u << 16)), dim3(256), 0, st, ws.qkeys,
+                               qn, L, static_cast<const uint32_t *>(ix.tkeys), ix.tids, ix.dir, ix.n, ix.dir_bits,
+                               bitmap, bm_words, c0, d0);
         if (hipGetLastError() != hipSuccess) s = fail(FCLSH_EDEVICE, "cost kernel launch failed");
     }
     const hipError_t e = hipStreamSynchronize(st);
@@ -1055,6 +1072,18 @@ __global__ void rearm_scatter_kernel(QueryCtrl *ctrl, uint32_t *qfill, int64_t n
     const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i0 == 0) ctrl->status &= ~kQueryIdsOverflow;
     for (int64_t i = i0; i < nq; i += int64_t(gridDim.x) * blockDim.x) qfill[i] = 0;
+}
+
+// The two verification passes of a batch.
+template <bool SPARSE, typename KT>
+fclsh_status launch_verify(const VerifyArgs &a, unsigned iblocks, unsigned vblocks, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(verify_items_kernel<SPARSE, KT>), dim3(iblocks), dim3(64 * kVerifyWaves), lds,
+                       st, a);
+    FCLSH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(verify_spill_kernel<SPARSE, KT>), dim3(vblocks), dim3(64 * kVerifyWaves), lds,
+                       st, a);
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
 }
 
 // Pairs into the per-query segments of ids, then each segment sorted (the
@@ -1167,18 +1196,14 @@ fclsh_status query_batch_async(Index &ix, QueryWorkspace &ws, const uint64_t *qu
     if (nq > 0) {
         // the item pass needs no more waves than rounds of 64 items
         const unsigned iblocks = std::min<unsigned>(vblocks, grid_for(nq * L, 64 * kVerifyWaves));
-        if (sparse) {
-            hipLaunchKernelGGL(verify_items_kernel<true>, dim3(iblocks), dim3(64 * kVerifyWaves), 0, st, a);
-            FCLSH_HIP(hipGetLastError());
-            hipLaunchKernelGGL(verify_spill_kernel<true>, dim3(vblocks), dim3(64 * kVerifyWaves), 0, st, a);
-            FCLSH_HIP(hipGetLastError());
-        } else {
-            const size_t pc_lds = size_t(ix.prm.dd()) * 4;  // staged (part, column) words, at most 4096
-            hipLaunchKernelGGL(verify_items_kernel<false>, dim3(iblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
-            FCLSH_HIP(hipGetLastError());
-            hipLaunchKernelGGL(verify_spill_kernel<false>, dim3(vblocks), dim3(64 * kVerifyWaves), pc_lds, st, a);
-            FCLSH_HIP(hipGetLastError());
-        }
+        if (sparse && ix.key_bytes == 2)
+            FCLSH_TRY((launch_verify<true, uint16_t>(a, iblocks, vblocks, 0, st)));
+        else if (sparse)
+            FCLSH_TRY((launch_verify<true, uint32_t>(a, iblocks, vblocks, 0, st)));
+        else if (ix.key_bytes == 2)  // staged (part, column) words, at most 4096
+            FCLSH_TRY((launch_verify<false, uint16_t>(a, iblocks, vblocks, size_t(ix.prm.dd()) * 4, st)));
+        else
+            FCLSH_TRY((launch_verify<false, uint32_t>(a, iblocks, vblocks, size_t(ix.prm.dd()) * 4, st)));
     }
     hipLaunchKernelGGL(widen_counts_kernel, dim3(grid_for(nq, 256)), dim3(256), 0, st, ws.qcount, nq, ws.qcount64);
     FCLSH_HIP(hipGetLastError());

@@ -406,10 +406,15 @@ __host__ __device__ constexpr int p2_region_a(int lo_bits) {
 
 // Pass 2 works on groups: the entries of a table that share their top gbits
 // key bits (gbits = 8, or 8 + S after the pass-1b split), a contiguous run
-// after the previous passes.
+// after the previous passes.  The final table keys are KT: uint32_t, or
+// uint16_t when the key bits below the directory bin fit 16 bits (the bin,
+// known from the directory, holds the rest), which saves 2 of pass 2's 16
+// bytes per entry and of a query's bytes per bucket entry.
+template <typename KT>
 struct P2Args {
     const uint32_t *kin, *vin;  // the group's input run (table offset applied)
-    uint32_t *okey, *oid;       // the group's output run
+    KT *okey;                   // the group's output run
+    uint32_t *oid;
     uint32_t *dr;               // directory entries of the group's bins
     uint32_t count;             // entries in the group
     uint32_t bs;                // group start within the table
@@ -441,8 +446,8 @@ constexpr int kGroupLeft = 0, kGroupSlot = 1, kGroupBallot = 2;
 // ANY_BIN (with SLOT_ONLY): the slot branch takes every group of at most
 // kFastTile entries without looking at its bin sizes (its ranking is right
 // for any bin, only slower on a large one), which saves a block reduction.
-template <bool SLOT_ONLY, bool ANY_BIN = false>
-__device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+template <typename KT, bool SLOT_ONLY, bool ANY_BIN = false>
+__device__ int p2_group(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // region A: keys and ids in slot (fast) or final (stable) order; in the
@@ -499,7 +504,7 @@ __device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
                 r += uint32_t(x0 < v) + uint32_t(x1 < v) + uint32_t(x2 < v) + uint32_t(x3 < v);
             }
             for (; q < b1; ++q) r += bv[q] < v ? 1u : 0u;
-            a.okey[r] = k;
+            a.okey[r] = KT(k);
             a.oid[r] = v;
         }
         return kGroupSlot;
@@ -529,14 +534,15 @@ __device__ int p2_group(const P2Args &a, uint32_t *lds, uint32_t *sh) {
         }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
-        a.okey[j] = bk[j];
+        a.okey[j] = KT(bk[j]);
         a.oid[j] = bv[j];
     }
     return kGroupBallot;
 }
 
 // Stable path for a group of at most kTile entries.
-__device__ void p2_stable_single(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+template <typename KT>
+__device__ void p2_stable_single(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     // region A (kTile*2 words): first the per-wave counters [kWaves][R], then
     // the reordered keys and ids; region B: start[R], tot[R]
@@ -578,13 +584,14 @@ __device__ void p2_stable_single(const P2Args &a, uint32_t *lds, uint32_t *sh) {
         }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
-        a.okey[j] = rkey[j];
+        a.okey[j] = KT(rkey[j]);
         a.oid[j] = rid[j];
     }
 }
 
 // Stable path for a group of more than kTile entries.
-__device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) {
+template <typename KT>
+__device__ void p2_stable_chunked(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     uint32_t *wc = lds;
     uint32_t *start = lds + 2 * kTile;
@@ -616,7 +623,7 @@ __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) 
             if (ok[it]) {
                 const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
                 const uint32_t dst = start[dg[it]] + wc[wave * R + dg[it]] + rank[it];
-                a.okey[dst] = a.kin[e];
+                a.okey[dst] = KT(a.kin[e]);
                 a.oid[dst] = a.vin[e];
             }
         __syncthreads();
@@ -628,9 +635,10 @@ __device__ void p2_stable_chunked(const P2Args &a, uint32_t *lds, uint32_t *sh) 
 // Pass-2 group g is groups [g << gk, (g + 1) << gk) of the earlier passes:
 // gk > 0 merges small neighbouring groups (their keys already in order), and
 // gbits + lo_bits = dir_bits either way.
-__device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *gstart,
-                                 int gbits, int lo_bits, int gk, uint32_t *tkeys, uint32_t *tids, uint32_t *dir,
-                                 int T, int g) {
+template <typename KT>
+__device__ inline P2Args<KT> p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *gstart,
+                                     int gbits, int lo_bits, int gk, KT *tkeys, uint32_t *tids, uint32_t *dir,
+                                     int T, int g) {
     const int64_t toff = int64_t(T) * n;
     // group starts per table: 2^(gbits + gk) + 1 (<= 4097), so the index
     // fits 32 bits and stays in scalar registers (a 64-bit product lands in
@@ -640,7 +648,7 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
     const uint32_t gi = uint32_t(T) * gs + (uint32_t(g) << gk);
     const uint32_t bs = gstart[gi];
     const uint32_t be = gstart[gi + (1u << gk)];
-    P2Args a;
+    P2Args<KT> a;
     a.kin = ikeys + toff + bs;
     a.vin = iids + toff + bs;
     a.okey = tkeys + toff + bs;
@@ -663,10 +671,10 @@ __device__ inline P2Args p2_args(const uint32_t *ikeys, const uint32_t *iids, in
 // when it sent none; the full form needs 68 VGPRs (3 per CU).
 // (iids and tids may be the same array: the ids are then reordered in place,
 // each group reading its whole run into registers before writing it.)
-template <bool SLOT_ONLY, bool ANY_BIN = false>
+template <typename KT, bool SLOT_ONLY, bool ANY_BIN = false>
 __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const uint32_t *__restrict__ ikeys, const uint32_t *iids, int64_t n, const uint32_t *__restrict__ gstart,
-    int gbits, int lo_bits, int gk, uint32_t *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
+    int gbits, int lo_bits, int gk, KT *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
     uint32_t *__restrict__ rest, uint32_t *__restrict__ counts, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
@@ -675,8 +683,8 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
-    const P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
-    const int how = a.count <= uint32_t(kFastTile) ? p2_group<SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
+    const P2Args<KT> a = p2_args<KT>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
+    const int how = a.count <= uint32_t(kFastTile) ? p2_group<KT, SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
     if (threadIdx.x == 0) {
         if (how == kGroupLeft) rest[atomicAdd(counts, 1u)] = uint32_t(w);
         if (how == kGroupBallot) atomicAdd(counts + 1, 1u);
@@ -687,9 +695,10 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
 // works through the list (empty on uniform keys).  When the input ids are the
 // output id array (after the pass-1b split), a group taking the chunked
 // path first copies its ids to spare, which that path then reads.
+template <typename KT>
 __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
                                                          int64_t n, const uint32_t *__restrict__ gstart, int gbits,
-                                                         int lo_bits, int gk, uint32_t *__restrict__ tkeys,
+                                                         int lo_bits, int gk, KT *__restrict__ tkeys,
                                                          uint32_t *tids,
                                                          uint32_t *__restrict__ dir, const uint32_t *__restrict__ rest,
                                                          const uint32_t *__restrict__ rest_count,
@@ -700,7 +709,7 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
     for (uint32_t i = blockIdx.x; i < nrest; i += gridDim.x) {
         const int64_t w = rest[i];
         const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
-        P2Args a = p2_args(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
+        P2Args<KT> a = p2_args<KT>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
         if (a.count > uint32_t(kTile)) {
             if (iids == tids) {
                 uint32_t *copy = spare + int64_t(T) * n + a.bs;
@@ -708,9 +717,9 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
                 __syncthreads();
                 a.vin = copy;
             }
-            p2_stable_chunked(a, lds, sh);
+            p2_stable_chunked<KT>(a, lds, sh);
         } else {
-            p2_stable_single(a, lds, sh);
+            p2_stable_single<KT>(a, lds, sh);
         }
         __syncthreads();  // LDS reuse by the next item
     }
@@ -889,8 +898,75 @@ const uint32_t *table_build_counts(const uint32_t *scratch, int64_t L, int64_t n
            (S ? size_t(L) * ((size_t(kHiBins) << S) + 1) : 0);
 }
 
+namespace {
+
+template <typename KT>
+fclsh_status launch_pass2(const uint32_t *p2k, const uint32_t *p2v, int64_t L, int64_t n, const uint32_t *gstart,
+                          int gbits2, int lo_bits2, int gk, KT *tkeys, uint32_t *tids, uint32_t *dir, uint32_t *rest,
+                          uint32_t *rest_count, uint32_t *tmpv, BuildMode mode, hipStream_t st, hipEvent_t *marks) {
+    const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits2)) * 4;
+    const size_t lds_fast = (size_t(p2_region_a(lo_bits2)) + (size_t(1) << lo_bits2) + 1) * 4;
+    const int64_t nitems2 = int64_t(L) << gbits2;  // (table, group) items, a multiple of kXcds
+    if (mode == BuildMode::kSlotAll)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, true, true>), dim3(unsigned(nitems2)), dim3(kNT),
+                           lds_fast, st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count,
+                           nitems2);
+    else if (mode == BuildMode::kSlotOnly)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st,
+                           p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, false>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
+                           st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
+    FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
+    hipLaunchKernelGGL(p2_rest_kernel<KT>, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2,
+                       st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, tmpv);
+    FCLSH_HIP(hipGetLastError());
+    if (marks) FCLSH_HIP(hipEventRecord(marks[5], st));
+    return FCLSH_OK;
+}
+
+}  // namespace
+
+int table_key_bytes(int dir_bits) { return 31 - dir_bits <= 16 ? 2 : 4; }
+
+namespace {
+
+// Whole keys of tables [T0, T1) from 16-bit stored keys: a thread per
+// (table, bin) writes (bin << (31 - dir_bits)) | low for the bin's entries.
+__global__ void expand_keys_kernel(const uint16_t *__restrict__ tk, const uint32_t *__restrict__ dir, int64_t n,
+                                   int dir_bits, int T0, int64_t ntab, uint32_t *__restrict__ out) {
+    const int64_t nb = int64_t(1) << dir_bits;
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < ntab * nb;
+         g += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t t = g / nb, b = g - t * nb;
+        const int64_t T = T0 + t;
+        const uint32_t *dr = dir + T * (nb + 1);
+        const uint32_t hi = uint32_t(b) << (31 - dir_bits);
+        for (uint32_t j = dr[b]; j < dr[b + 1]; ++j) out[t * n + j] = hi | tk[T * n + j];
+    }
+}
+
+}  // namespace
+
+fclsh_status expand_table_keys(const void *tkeys, int key_bytes, const uint32_t *dir, int64_t n, int dir_bits, int T0,
+                               int T1, uint32_t *out, hipStream_t st) {
+    const int64_t ntab = T1 - T0;
+    if (ntab <= 0) return FCLSH_OK;
+    if (key_bytes == 4) {
+        FCLSH_HIP(hipMemcpyAsync(out, static_cast<const uint32_t *>(tkeys) + int64_t(T0) * n, size_t(ntab * n) * 4,
+                                 hipMemcpyDeviceToDevice, st));
+        return FCLSH_OK;
+    }
+    const int64_t work = ntab << dir_bits;
+    hipLaunchKernelGGL(expand_keys_kernel, dim3(unsigned(std::min<int64_t>((work + 255) / 256, 1 << 16))), dim3(256), 0,
+                       st, static_cast<const uint16_t *>(tkeys), dir, n, dir_bits, T0, ntab, out);
+    FCLSH_HIP(hipGetLastError());
+    return FCLSH_OK;
+}
+
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
-                                uint32_t *scratch, uint32_t *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
+                                uint32_t *scratch, void *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
                                 hipStream_t st, hipEvent_t *marks) {
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
@@ -935,25 +1011,11 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
         p2v = tids;
     }
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
-    const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits2)) * 4;
-    const size_t lds_fast = (size_t(p2_region_a(lo_bits2)) + (size_t(1) << lo_bits2) + 1) * 4;
-    const int64_t nitems2 = int64_t(L) << gbits2;  // (table, group) items, a multiple of kXcds
-    if (mode == BuildMode::kSlotAll)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<true, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
-                           st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
-    else if (mode == BuildMode::kSlotOnly)
-        hipLaunchKernelGGL(p2_fast_kernel<true>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
-                           gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
-    else
-        hipLaunchKernelGGL(p2_fast_kernel<false>, dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st, p2k, p2v, n,
-                           gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
-    FCLSH_HIP(hipGetLastError());
-    if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
-    hipLaunchKernelGGL(p2_rest_kernel, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2, st,
-                       p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, tmpv);
-    FCLSH_HIP(hipGetLastError());
-    if (marks) FCLSH_HIP(hipEventRecord(marks[5], st));
-    return FCLSH_OK;
+    if (table_key_bytes(dir_bits) == 2)
+        return launch_pass2<uint16_t>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk, static_cast<uint16_t *>(tkeys),
+                                      tids, dir, rest, rest_count, tmpv, mode, st, marks);
+    return launch_pass2<uint32_t>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk, static_cast<uint32_t *>(tkeys), tids,
+                                  dir, rest, rest_count, tmpv, mode, st, marks);
 }
 
 }  // namespace fclsh

@@ -327,7 +327,9 @@ def test_index_memory_report():
     idx = fc.Index(dev(w.points), w.d, w.r, seed=6)
     inf = idx.info
     L, n = inf["L"], inf["n"]
-    tables = 2 * 4 * L * n
+    key_bytes = idx.table_pointers()[4]
+    assert key_bytes == (2 if 31 - inf["dir_bits"] <= 16 else 4)
+    tables = (4 + key_bytes) * L * n
     points = 8 * fc.words(w.d) * n
     directory = 4 * L * ((1 << inf["dir_bits"]) + 1)
     m = idx.memory()
@@ -339,3 +341,14 @@ def test_index_memory_report():
     kept = fc.Index(dev(w.points), w.d, w.r, seed=6, keep_build_scratch=True)
     assert kept.memory()["build_scratch_bytes"] >= 3 * 4 * L * n
     kept.close()
+    # a large index stores the key bits below its bin, 16 of them
+    big = synth.uniform_points(200_000, 64, np.random.default_rng(7))
+    idx = fc.Index(dev(big), 64, 3, seed=8)
+    inf = idx.info
+    assert inf["dir_bits"] >= 15 and idx.table_pointers()[4] == 2
+    L, n = inf["L"], inf["n"]
+    directory = 4 * L * ((1 << inf["dir_bits"]) + 1)
+    tables, points = 6 * L * n, 8 * n
+    m = idx.memory()
+    assert tables + points + directory <= m["index_bytes"] <= tables + points + directory + (1 << 20)
+    idx.close()
