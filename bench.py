@@ -167,21 +167,24 @@ def main():
     rest_entries = int(sb_count[rest].sum().item())
     ballot_entries = int(sb_count[~rest & (sb_max > 48)].sum().item())
     dir_bytes = 4 * L * ((1 << dir_bits) + 1)
-    # the tables store a key as its low 16 bits when the bin holds the rest
+    # the tables store a key as its low 16 bits when the bin holds the rest;
+    # with such keys and pass 2 on the 256 super-bins (group_bits 8), pass 1
+    # hands pass 2 6-byte entries instead of 8-byte ones
     kb = idx.table_pointers()[4]
+    mid_bytes = 6 if (kb == 2 and group_bits == 8) else 8
     # bytes each kernel moves itself (its reads and writes, for the counter
     # comparison) ...
     moved_bytes = {
         "fht_hash_kernel": n * (W * 8 + 4 * L),                    # read the point, write its L keys
         "p1_hist_kernel": 4 * entries + 4 * L * nblk * 256,          # read keys, write tile histograms
         "p1_scan_kernel": 8 * L * nblk * 256,                        # read + write the histograms
-        "p1_scatter_kernel": 12 * entries,                           # read key, write key + id
+        "p1_scatter_kernel": (4 + mid_bytes) * entries,              # read key, write the entry
         # split of the super-bins (large n only): read keys twice and ids once, write both
         "p1b_split_kernel": (20 * entries + 4 * L * ((256 << (group_bits - 8)) + 1)) if group_bits > 8 else 0,
-        # pass 2: read key and id, write the stored key (kb bytes) and id of
+        # pass 2: read the entry, write the stored key (kb bytes) and id of
         # each entry it reorders, and its bins' directory entries
-        "p2_fast_kernel": (12 + kb) * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries),
-        "p2_rest_kernel": (12 + kb) * rest_entries + dir_bytes * (rest_entries / entries) + 4,
+        "p2_fast_kernel": (mid_bytes + 4 + kb) * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries),
+        "p2_rest_kernel": (mid_bytes + 4 + kb) * rest_entries + dir_bytes * (rest_entries / entries) + 4,
     }
     # ... and the algorithmic bytes the roofline is priced at: the hash step
     # reads a point and writes its L keys (d/8 + 4L per point); the table

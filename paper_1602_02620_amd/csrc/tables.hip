@@ -22,7 +22,10 @@
 // every pass stages its output in LDS first.
 // Ids are implicit in pass 1 (a point's index), so the keys written by the
 // hash kernel are read twice and each table entry is written twice (three
-// times with pass 1b).
+// times with pass 1b).  Between the passes an entry takes 8 bytes (key, id)
+// or, when pass 2 follows directly on super-bins and stores 16-bit keys, 6
+// bytes: the 23 key bits below the super-bin digit with the id's low 9 bits
+// above them, and the id's remaining bits as 16 bits (ids below 2^25).
 #include "common.h"
 
 namespace fclsh {
@@ -46,6 +49,9 @@ constexpr int kRestBlocks = 1024;          // grid of the stable pass-2 kernel
 constexpr int kHiBits = 8;
 constexpr int kHiBins = 1 << kHiBits;
 constexpr int kMaxLoBits = 11;
+// 6-byte entries between the passes: id bits kept beside the key's low bits
+constexpr int kPkIdLow = 32 - (31 - kHiBits);
+constexpr uint32_t kPkKeyMask = (1u << (31 - kHiBits)) - 1u;
 
 // A wave's LDS operations execute in issue order; this keeps the compiler from
 // moving plain LDS accesses across the atomics between phases.
@@ -294,10 +300,27 @@ __global__ __launch_bounds__(kHiBins * kScanSeg) void p1_scan_kernel(uint32_t *_
 }
 
 
-__global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__restrict__ keys, int64_t n,
+// One pass-1 output entry: 8 bytes (key, id) or, with PK, 6 bytes (the
+// key's bits below the super-bin digit with the id's low bits above them;
+// the id's high bits as 16 bits).
+template <bool PK>
+__device__ inline void p1_put(uint32_t *ok, void *oi, uint32_t o, uint32_t key, uint32_t id) {
+    if constexpr (PK) {
+        ok[o] = (key & kPkKeyMask) | (id << (32 - kPkIdLow));
+        static_cast<uint16_t *>(oi)[o] = uint16_t(id >> kPkIdLow);
+    } else {
+        ok[o] = key;
+        static_cast<uint32_t *>(oi)[o] = id;
+    }
+}
+
+// (4 waves per SIMD, i.e. 2 workgroups per CU: the 6-byte form's stores
+// would otherwise take it to 132 VGPRs and 1 workgroup.)
+template <bool PK>
+__global__ __launch_bounds__(kP1NT) __attribute__((amdgpu_waves_per_eu(4))) void p1_scatter_kernel(const uint32_t *__restrict__ keys, int64_t n,
                                                          const uint32_t *__restrict__ offs, int nblk,
                                                          int64_t nitems, uint32_t *__restrict__ okeys,
-                                                         uint32_t *__restrict__ oids) {
+                                                         void *__restrict__ oids) {
     __shared__ uint32_t wc[kP1Waves * kHiBins];
     __shared__ uint32_t tot[kHiBins];
     __shared__ uint32_t gpos[kHiBins];
@@ -345,7 +368,9 @@ __global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__res
     // so the entry at tile position j goes to gpos[d] + j (mod 2^32, < n)
     for (int d = threadIdx.x; d < kHiBins; d += kP1NT) gpos[d] -= tot[d];
     __syncthreads();
-    uint32_t *okt = okeys + toff, *oit = oids + toff;
+    uint32_t *okt = okeys + toff;
+    void *oit = PK ? static_cast<void *>(static_cast<uint16_t *>(oids) + toff)
+                   : static_cast<void *>(static_cast<uint32_t *>(oids) + toff);
     const uint32_t b32 = uint32_t(beg);
     if (cnt == kP1Tile) {
         // full tile: all LDS reads first, then the stores
@@ -358,15 +383,13 @@ __global__ __launch_bounds__(kP1NT) void p1_scatter_kernel(const uint32_t *__res
 #pragma unroll
         for (int k = 0; k < kP1Items; ++k) {
             const uint32_t o = gpos[kk[k] >> (31 - kHiBits)] + uint32_t(k * kP1NT + threadIdx.x);
-            okt[o] = kk[k];
-            oit[o] = b32 + ii[k];
+            p1_put<PK>(okt, oit, o, kk[k], b32 + ii[k]);
         }
     } else {
         for (int j = threadIdx.x; j < cnt; j += kP1NT) {
             const uint32_t key = sk[j];
             const uint32_t o = gpos[key >> (31 - kHiBits)] + uint32_t(j);
-            okt[o] = key;
-            oit[o] = b32 + si[j];
+            p1_put<PK>(okt, oit, o, key, b32 + si[j]);
         }
     }
 }
@@ -410,9 +433,15 @@ __host__ __device__ constexpr int p2_region_a(int lo_bits) {
 // uint16_t when the key bits below the directory bin fit 16 bits (the bin,
 // known from the directory, holds the rest), which saves 2 of pass 2's 16
 // bytes per entry and of a query's bytes per bucket entry.
-template <typename KT>
+//
+// PK: the input entries are pass 1's 6-byte form.  Their key word holds the
+// key bits pass 2 uses (the bin digit below the super-bin and the stored
+// low bits; pass 2 then runs on super-bins, gbits = 8) and the id's low bits
+// on top, which the digit mask and the 16-bit store both leave out.
+template <typename KT, bool PK>
 struct P2Args {
-    const uint32_t *kin, *vin;  // the group's input run (table offset applied)
+    const uint32_t *kin;        // the group's input run (table offset applied)
+    const void *vin;            // its ids: uint32, or with PK the id's high bits as uint16
     KT *okey;                   // the group's output run
     uint32_t *oid;
     uint32_t *dr;               // directory entries of the group's bins
@@ -420,6 +449,22 @@ struct P2Args {
     uint32_t bs;                // group start within the table
     int shift, lo_bits;
     uint32_t mask;
+    // the id word of input entry e, and the id from it and the entry's key
+    // word k (apart, so that a thread's loads are all issued before any of
+    // them is waited for)
+    __device__ uint32_t id_word(uint32_t e) const {
+        if constexpr (PK)
+            return static_cast<const uint16_t *>(vin)[e];
+        else
+            return static_cast<const uint32_t *>(vin)[e];
+    }
+    __device__ uint32_t id_of(uint32_t w, uint32_t k) const {
+        if constexpr (PK)
+            return (w << kPkIdLow) | (k >> (32 - kPkIdLow));
+        else
+            return w;
+    }
+    __device__ uint32_t id(uint32_t e, uint32_t k) const { return id_of(id_word(e), k); }
 };
 
 // Block-wide maximum of one value per thread.
@@ -446,8 +491,8 @@ constexpr int kGroupLeft = 0, kGroupSlot = 1, kGroupBallot = 2;
 // ANY_BIN (with SLOT_ONLY): the slot branch takes every group of at most
 // kFastTile entries without looking at its bin sizes (its ranking is right
 // for any bin, only slower on a large one), which saves a block reduction.
-template <typename KT, bool SLOT_ONLY, bool ANY_BIN = false>
-__device__ int p2_group(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
+template <typename KT, bool PK, bool SLOT_ONLY, bool ANY_BIN = false>
+__device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // region A: keys and ids in slot (fast) or final (stable) order; in the
@@ -466,8 +511,10 @@ __device__ int p2_group(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
     for (int it = 0; it < kFastItems; ++it) {
         const uint32_t e = wbase + uint32_t(it) * 64u;
         rk[it] = ok(it) ? a.kin[e] : 0u;
-        rv[it] = ok(it) ? a.vin[e] : 0u;
+        rv[it] = ok(it) ? a.id_word(e) : 0u;
     }
+#pragma unroll
+    for (int it = 0; it < kFastItems; ++it) rv[it] = a.id_of(rv[it], rk[it]);
 #pragma unroll
     for (int it = 0; it < kFastItems; ++it)
         pos[it] = ok(it) ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
@@ -541,8 +588,8 @@ __device__ int p2_group(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
 }
 
 // Stable path for a group of at most kTile entries.
-template <typename KT>
-__device__ void p2_stable_single(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
+template <typename KT, bool PK>
+__device__ void p2_stable_single(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     // region A (kTile*2 words): first the per-wave counters [kWaves][R], then
     // the reordered keys and ids; region B: start[R], tot[R]
@@ -561,7 +608,11 @@ __device__ void p2_stable_single(const P2Args<KT> &a, uint32_t *lds, uint32_t *s
         const uint32_t e = uint32_t(wave * (64 * kItems) + it * 64 + lane);
         ok[it] = e < a.count;
         rk[it] = ok[it] ? a.kin[e] : 0u;
-        rv[it] = ok[it] ? a.vin[e] : 0u;
+        rv[it] = ok[it] ? a.id_word(e) : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        rv[it] = a.id_of(rv[it], rk[it]);
         dg[it] = (rk[it] >> a.shift) & a.mask;
     }
     wave_stable_ranks<kItems>(dg, ok, a.lo_bits, wc + wave * R, rank);
@@ -590,8 +641,8 @@ __device__ void p2_stable_single(const P2Args<KT> &a, uint32_t *lds, uint32_t *s
 }
 
 // Stable path for a group of more than kTile entries.
-template <typename KT>
-__device__ void p2_stable_chunked(const P2Args<KT> &a, uint32_t *lds, uint32_t *sh) {
+template <typename KT, bool PK>
+__device__ void p2_stable_chunked(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     uint32_t *wc = lds;
     uint32_t *start = lds + 2 * kTile;
@@ -623,8 +674,9 @@ __device__ void p2_stable_chunked(const P2Args<KT> &a, uint32_t *lds, uint32_t *
             if (ok[it]) {
                 const uint32_t e = c0 + uint32_t(wave * (64 * kItems) + it * 64 + lane);
                 const uint32_t dst = start[dg[it]] + wc[wave * R + dg[it]] + rank[it];
-                a.okey[dst] = KT(a.kin[e]);
-                a.oid[dst] = a.vin[e];
+                const uint32_t k = a.kin[e];
+                a.okey[dst] = KT(k);
+                a.oid[dst] = a.id(e, k);
             }
         __syncthreads();
         for (int d = threadIdx.x; d < R; d += kNT) start[d] += tot[d];
@@ -635,10 +687,10 @@ __device__ void p2_stable_chunked(const P2Args<KT> &a, uint32_t *lds, uint32_t *
 // Pass-2 group g is groups [g << gk, (g + 1) << gk) of the earlier passes:
 // gk > 0 merges small neighbouring groups (their keys already in order), and
 // gbits + lo_bits = dir_bits either way.
-template <typename KT>
-__device__ inline P2Args<KT> p2_args(const uint32_t *ikeys, const uint32_t *iids, int64_t n, const uint32_t *gstart,
-                                     int gbits, int lo_bits, int gk, KT *tkeys, uint32_t *tids, uint32_t *dir,
-                                     int T, int g) {
+template <typename KT, bool PK>
+__device__ inline P2Args<KT, PK> p2_args(const uint32_t *ikeys, const void *iids, int64_t n,
+                                         const uint32_t *gstart, int gbits, int lo_bits, int gk, KT *tkeys,
+                                         uint32_t *tids, uint32_t *dir, int T, int g) {
     const int64_t toff = int64_t(T) * n;
     // group starts per table: 2^(gbits + gk) + 1 (<= 4097), so the index
     // fits 32 bits and stays in scalar registers (a 64-bit product lands in
@@ -648,9 +700,12 @@ __device__ inline P2Args<KT> p2_args(const uint32_t *ikeys, const uint32_t *iids
     const uint32_t gi = uint32_t(T) * gs + (uint32_t(g) << gk);
     const uint32_t bs = gstart[gi];
     const uint32_t be = gstart[gi + (1u << gk)];
-    P2Args<KT> a;
+    P2Args<KT, PK> a;
     a.kin = ikeys + toff + bs;
-    a.vin = iids + toff + bs;
+    if constexpr (PK)
+        a.vin = static_cast<const uint16_t *>(iids) + toff + bs;
+    else
+        a.vin = static_cast<const uint32_t *>(iids) + toff + bs;
     a.okey = tkeys + toff + bs;
     a.oid = tids + toff + bs;
     a.dr = dir + int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(g) << lo_bits);
@@ -671,9 +726,9 @@ __device__ inline P2Args<KT> p2_args(const uint32_t *ikeys, const uint32_t *iids
 // when it sent none; the full form needs 68 VGPRs (3 per CU).
 // (iids and tids may be the same array: the ids are then reordered in place,
 // each group reading its whole run into registers before writing it.)
-template <typename KT, bool SLOT_ONLY, bool ANY_BIN = false>
+template <typename KT, bool PK, bool SLOT_ONLY, bool ANY_BIN = false>
 __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
-    const uint32_t *__restrict__ ikeys, const uint32_t *iids, int64_t n, const uint32_t *__restrict__ gstart,
+    const uint32_t *__restrict__ ikeys, const void *iids, int64_t n, const uint32_t *__restrict__ gstart,
     int gbits, int lo_bits, int gk, KT *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
     uint32_t *__restrict__ rest, uint32_t *__restrict__ counts, int64_t nitems) {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -683,8 +738,8 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
-    const P2Args<KT> a = p2_args<KT>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
-    const int how = a.count <= uint32_t(kFastTile) ? p2_group<KT, SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
+    const P2Args<KT, PK> a = p2_args<KT, PK>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
+    const int how = a.count <= uint32_t(kFastTile) ? p2_group<KT, PK, SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
     if (threadIdx.x == 0) {
         if (how == kGroupLeft) rest[atomicAdd(counts, 1u)] = uint32_t(w);
         if (how == kGroupBallot) atomicAdd(counts + 1, 1u);
@@ -695,8 +750,8 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
 // works through the list (empty on uniform keys).  When the input ids are the
 // output id array (after the pass-1b split), a group taking the chunked
 // path first copies its ids to spare, which that path then reads.
-template <typename KT>
-__global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys, const uint32_t *iids,
+template <typename KT, bool PK>
+__global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restrict__ ikeys, const void *iids,
                                                          int64_t n, const uint32_t *__restrict__ gstart, int gbits,
                                                          int lo_bits, int gk, KT *__restrict__ tkeys,
                                                          uint32_t *tids,
@@ -709,17 +764,19 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
     for (uint32_t i = blockIdx.x; i < nrest; i += gridDim.x) {
         const int64_t w = rest[i];
         const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
-        P2Args<KT> a = p2_args<KT>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
+        P2Args<KT, PK> a = p2_args<KT, PK>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
         if (a.count > uint32_t(kTile)) {
-            if (iids == tids) {
-                uint32_t *copy = spare + int64_t(T) * n + a.bs;
-                for (uint32_t e = threadIdx.x; e < a.count; e += kNT) copy[e] = a.vin[e];
-                __syncthreads();
-                a.vin = copy;
+            if constexpr (!PK) {
+                if (iids == tids) {
+                    uint32_t *copy = spare + int64_t(T) * n + a.bs;
+                    for (uint32_t e = threadIdx.x; e < a.count; e += kNT) copy[e] = a.id(e, 0u);
+                    __syncthreads();
+                    a.vin = copy;
+                }
             }
-            p2_stable_chunked<KT>(a, lds, sh);
+            p2_stable_chunked<KT, PK>(a, lds, sh);
         } else {
-            p2_stable_single<KT>(a, lds, sh);
+            p2_stable_single<KT, PK>(a, lds, sh);
         }
         __syncthreads();  // LDS reuse by the next item
     }
@@ -900,26 +957,26 @@ const uint32_t *table_build_counts(const uint32_t *scratch, int64_t L, int64_t n
 
 namespace {
 
-template <typename KT>
-fclsh_status launch_pass2(const uint32_t *p2k, const uint32_t *p2v, int64_t L, int64_t n, const uint32_t *gstart,
+template <typename KT, bool PK>
+fclsh_status launch_pass2(const uint32_t *p2k, const void *p2v, int64_t L, int64_t n, const uint32_t *gstart,
                           int gbits2, int lo_bits2, int gk, KT *tkeys, uint32_t *tids, uint32_t *dir, uint32_t *rest,
                           uint32_t *rest_count, uint32_t *tmpv, BuildMode mode, hipStream_t st, hipEvent_t *marks) {
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits2)) * 4;
     const size_t lds_fast = (size_t(p2_region_a(lo_bits2)) + (size_t(1) << lo_bits2) + 1) * 4;
     const int64_t nitems2 = int64_t(L) << gbits2;  // (table, group) items, a multiple of kXcds
     if (mode == BuildMode::kSlotAll)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, true, true>), dim3(unsigned(nitems2)), dim3(kNT),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, PK, true, true>), dim3(unsigned(nitems2)), dim3(kNT),
                            lds_fast, st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count,
                            nitems2);
     else if (mode == BuildMode::kSlotOnly)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, PK, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st,
                            p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, false>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, PK, false>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
                            st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
-    hipLaunchKernelGGL(p2_rest_kernel<KT>, dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_rest_kernel<KT, PK>), dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2,
                        st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, tmpv);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[5], st));
@@ -929,6 +986,11 @@ fclsh_status launch_pass2(const uint32_t *p2k, const uint32_t *p2v, int64_t L, i
 }  // namespace
 
 int table_key_bytes(int dir_bits) { return 31 - dir_bits <= 16 ? 2 : 4; }
+
+bool table_packed_pass1(int64_t n, int dir_bits) {
+    return table_key_bytes(dir_bits) == 2 && table_split_bits(n, dir_bits) == 0 && table_merge_bits(n, dir_bits) == 0 &&
+           n <= (int64_t(1) << (kPkIdLow + 16));
+}
 
 namespace {
 
@@ -991,8 +1053,15 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     const int64_t nitems = int64_t(nblk) * L;
     const int64_t grid1 = xcd_grid(nitems);
     if (grid1 > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "too many table tiles");
-    hipLaunchKernelGGL(p1_scatter_kernel, dim3(unsigned(grid1)), dim3(kP1NT), 0, st, keys, n, hist, nblk, nitems,
-                       tmpk, tmpv);
+    // 6-byte entries between the passes when pass 2 follows on super-bins
+    // and stores 16-bit keys (ids then stay below 2^25)
+    const bool packed = table_packed_pass1(n, dir_bits);
+    if (packed)
+        hipLaunchKernelGGL(p1_scatter_kernel<true>, dim3(unsigned(grid1)), dim3(kP1NT), 0, st, keys, n, hist, nblk,
+                           nitems, tmpk, static_cast<void *>(tmpv));
+    else
+        hipLaunchKernelGGL(p1_scatter_kernel<false>, dim3(unsigned(grid1)), dim3(kP1NT), 0, st, keys, n, hist, nblk,
+                           nitems, tmpk, static_cast<void *>(tmpv));
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[2], st));
     // pass 2 input: the pass-1 output, or after the split the hash-key buffer
@@ -1011,11 +1080,16 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
         p2v = tids;
     }
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
+    if (packed)
+        return launch_pass2<uint16_t, true>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk,
+                                            static_cast<uint16_t *>(tkeys), tids, dir, rest, rest_count, tmpv, mode, st,
+                                            marks);
     if (table_key_bytes(dir_bits) == 2)
-        return launch_pass2<uint16_t>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk, static_cast<uint16_t *>(tkeys),
-                                      tids, dir, rest, rest_count, tmpv, mode, st, marks);
-    return launch_pass2<uint32_t>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk, static_cast<uint32_t *>(tkeys), tids,
-                                  dir, rest, rest_count, tmpv, mode, st, marks);
+        return launch_pass2<uint16_t, false>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk,
+                                             static_cast<uint16_t *>(tkeys), tids, dir, rest, rest_count, tmpv, mode,
+                                             st, marks);
+    return launch_pass2<uint32_t, false>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk, static_cast<uint32_t *>(tkeys),
+                                         tids, dir, rest, rest_count, tmpv, mode, st, marks);
 }
 
 }  // namespace fclsh

@@ -240,17 +240,22 @@ def test_duplicates_and_heavy_buckets():
     idx.close()
 
 
-def test_all_points_identical():
+@pytest.mark.parametrize("n", [20011, 300_007], ids=["8byte_entries", "6byte_entries"])
+def test_all_points_identical(n):
     # every table is one bucket of n entries: the pass-2 workgroup walks it in
-    # many chunks
+    # many chunks; at 300,007 points pass 1 hands pass 2 its 6-byte entries
+    # (16-bit stored keys, pass 2 on super-bins)
     rng = np.random.default_rng(8)
-    n = 20011
     pts = np.repeat(synth.uniform_points(1, 64, rng), n, axis=0)
     pr = oracle.derive_params(64, 3, 78)
     orc = OracleIndex(pts, pr, with_tables=False)
     idx = fc.Index(dev(pts), 64, 3, seed=78)
+    _say(f"[identical] n={n}")
+    inf = idx.info
+    assert idx.table_pointers()[4] == (2 if n > 2 ** 18 else 4)
+    assert n < 2 ** 18 or inf["group_bits"] == 8
     tk, ti = idx.tables()
-    wk, wi = orc.binned_tables(idx.info["dir_bits"])
+    wk, wi = orc.binned_tables(inf["dir_bits"])
     assert np.array_equal(as_u32(tk), wk) and np.array_equal(as_u32(ti), wi)
     offs, ids = idx.query(dev(pts[:1]), 3)
     assert np.array_equal(csr_lists(offs, ids)[0], np.arange(n, dtype=np.uint32))
