@@ -43,15 +43,16 @@ constexpr double kTwo52 = 4503599627370496.0;
 constexpr uint32_t kHiWord52 = 0x43300000u;  // high word of 2^52 as a double
 
 // A coordinate c as the gather table holds it: the byte offset of its dword
-// in the staged point (4 * (c >> 5)) times 32, plus its bit (c & 31).  The
-// dword's address is then one shift from the entry, and the bit field
-// extract reads the entry as its offset (the hardware uses its low 5 bits).
-__host__ __device__ constexpr uint32_t coord_entry(uint32_t c) { return ((c >> 5) << 7) | (c & 31u); }
+// in the staged point (4 * (c >> 5), below 2^16) in the high half, its bit
+// (c & 31) in the low bits.  The dword's address is then one add with a
+// word-select operand (SDWA), and the bit field extract reads the entry as
+// its offset (the hardware uses its low 5 bits).
+__host__ __device__ constexpr uint32_t coord_entry(uint32_t c) { return ((c >> 5) << 18) | (c & 31u); }
 
 // All ones if the coordinate of entry e is set in the staged point x, else
 // zero.
 __device__ inline uint32_t coord_mask(const uint32_t *x, uint32_t e) {
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(x) + (e >> 5));
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(x) + (e >> 16));
     return uint32_t(__builtin_amdgcn_sbfe(int32_t(w), e, 1u));
 }
 
@@ -67,11 +68,11 @@ struct Shape {
     static constexpr int U = 1 << LOGU;
     static_assert(LOGG >= 0 && LOGG <= 6, "G must divide a wave");
     // Cross-lane stage b (lane bit LOGU + b, partner distance U << b) is a
-    // "swap" stage when the distance is 16 or 32: a permlane swap of register
+    // "swap" stage when the distance is 32: a permlane swap of register
     // pairs (k, k ^ 2^q), q = LOGV - LOGG + b, moves index bit LOGV + b into
     // register bit q and the (already transformed) index bit q into the lane
     // bit; the butterfly then runs inside each lane.
-    static constexpr bool swap_stage(int b) { return LOGU + b >= 4; }
+    static constexpr bool swap_stage(int b) { return LOGU + b >= 5; }
     static constexpr int swap_reg(int b) { return LOGV - LOGG + b; }
     // Index bit held by register bit r after all stages.
     static constexpr int reg_bit_index(int r) {
@@ -88,13 +89,15 @@ struct Shape {
     }
 };
 
-// The value of lane ^ DIST (DIST in 1, 2, 4, 8): a ds_swizzle in bit mode
-// (and-mask 0x1F, xor-mask DIST within each 32 lanes) per dword.  The
+// The value of lane ^ DIST (DIST in 1, 2, 4, 8, 16): a ds_swizzle in bit
+// mode (and-mask 0x1F, xor-mask DIST within each 32 lanes) per dword.  The
 // swizzle runs in the LDS pipe, so these stages leave the VALU to the
-// butterflies (a DPP move would take a VALU slot per dword).
+// butterflies: a DPP move would take a VALU slot per dword, and a permlane16
+// swap stage a VALU slot per dword plus an in-lane butterfly (hash on mid
+// 0.644 -> 0.622 ms with distance 16 as a swizzle stage).
 template <int DIST>
 __device__ inline double xor_lane_f64(double x) {
-    static_assert(DIST == 1 || DIST == 2 || DIST == 4 || DIST == 8, "swizzle distance");
+    static_assert(DIST == 1 || DIST == 2 || DIST == 4 || DIST == 8 || DIST == 16, "swizzle distance");
     const uint64_t u = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_ds_swizzle(int(uint32_t(u)), (DIST << 10) | 0x1F);
     const int hi = __builtin_amdgcn_ds_swizzle(int(uint32_t(u >> 32)), (DIST << 10) | 0x1F);
@@ -102,45 +105,29 @@ __device__ inline double xor_lane_f64(double x) {
 }
 
 // After the swap, a holds the partner-pair element with the partner-lane
-// index bit 0 and b the one with it 1, in every lane (dist 16 or 32).
-template <int DIST>
-__device__ inline void swap_f64(double &a, double &b) {
+// index bit 0 and b the one with it 1, in every lane (distance 32).
+__device__ inline void swap32_f64(double &a, double &b) {
     const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
     uint32_t alo = uint32_t(ua), ahi = uint32_t(ua >> 32), blo = uint32_t(ub), bhi = uint32_t(ub >> 32);
-    if constexpr (DIST == 32) {
-        auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
-        auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
-        alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
-    } else {
-        auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
-        auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
-        alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
-    }
+    auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
     a = __longlong_as_double((int64_t(ahi) << 32) | alo);
     b = __longlong_as_double((int64_t(bhi) << 32) | blo);
 }
 
+// Cross-lane stages B .. LOGG - 2 (distances U << B below 32, swizzles);
+// the last one (distance 32, a swap stage) is fused with the key
+// extraction's subtraction in fht_unit.
 template <int LOGD, int LOGV, int B>
 __device__ inline void cross_stages(double (&t)[1 << LOGV], int lane) {
     using S = Shape<LOGD, LOGV>;
-    if constexpr (B < S::LOGG) {
+    if constexpr (B < S::LOGG - 1) {
         constexpr int dist = S::U << B;
-        if constexpr (S::swap_stage(B)) {
-            constexpr int q = S::swap_reg(B);
+        static_assert(!S::swap_stage(B), "only the last cross-lane stage swaps");
+        const double sgn = (lane & dist) ? -1.0 : 1.0;
 #pragma unroll
-            for (int k = 0; k < S::V; ++k) {
-                if (!(k & (1 << q))) {
-                    double a = t[k], b = t[k | (1 << q)];
-                    swap_f64<dist>(a, b);
-                    t[k] = a + b;
-                    t[k | (1 << q)] = a - b;
-                }
-            }
-        } else {
-            const double sgn = (lane & dist) ? -1.0 : 1.0;
-#pragma unroll
-            for (int k = 0; k < S::V; ++k) t[k] = fma(sgn, t[k], xor_lane_f64<dist>(t[k]));
-        }
+        for (int k = 0; k < S::V; ++k) t[k] = fma(sgn, t[k], xor_lane_f64<dist>(t[k]));
         cross_stages<LOGD, LOGV, B + 1>(t, lane);
     }
 }
@@ -199,11 +186,11 @@ __device__ inline int lane_rows(int lane) {
     return vlane;
 }
 
-// The FHT of a unit's sketch (Alg. 2), in place; returns S'' + 2^52 (S'' =
-// F''_0 sits in register 0 of the unit's lane with s = 0).  t holds the
-// lane's V sketch entries.
+// The FHT of a unit's sketch (Alg. 2), then z_v = S'' + 2^52 - F''_v in
+// place of each transform value F''_v (S'' = F''_0).  t holds the lane's V
+// sketch entries.
 template <int LOGD, int LOGV>
-__device__ inline double fht_unit(double (&t)[1 << LOGV], int lane) {
+__device__ inline void fht_unit(double (&t)[1 << LOGV], int lane) {
     using S = Shape<LOGD, LOGV>;
     constexpr int V = S::V, U = S::U;
     // Fast Hadamard transform (Alg. 2): in-register stages ...
@@ -222,18 +209,46 @@ __device__ inline double fht_unit(double (&t)[1 << LOGV], int lane) {
     // first (the stages commute; this order keeps the register pressure of
     // the DPP stages away from the key extraction)
     cross_stages<LOGD, LOGV, 0>(t, lane);
-    return __shfl(t[0], lane & (U - 1), 64) + kTwo52;
+    if constexpr (S::LOGG == 0) {
+        const double Sm = t[0] + kTwo52;
+#pragma unroll
+        for (int k = 0; k < V; ++k) t[k] = Sm - t[k];
+    } else {
+        // the last stage (distance 32: LOGU + LOGG - 1 = 5), fused with the
+        // subtraction: with c = Sm - a, the pair's z values are c - b and
+        // c + b (integers below 2^53: exact).  F''_0 = a + b of register
+        // pair 0 in the unit's lane with s = 0.
+        static_assert(S::swap_stage(S::LOGG - 1), "the last cross-lane stage is a swap stage");
+        constexpr int q = S::swap_reg(S::LOGG - 1);
+        double a0 = t[0], b0 = t[1 << q];
+        swap32_f64(a0, b0);
+        const double Sm = __shfl(a0 + b0, lane & (U - 1), 64) + kTwo52;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (!(k & (1 << q))) {
+                double a = a0, b = b0;
+                if (k != 0) {
+                    a = t[k];
+                    b = t[k | (1 << q)];
+                    swap32_f64(a, b);
+                }
+                const double c = Sm - a;
+                t[k] = c - b;
+                t[k | (1 << q)] = c + b;
+            }
+        }
+    }
 }
 
-// The unit's keys from its transform: y[k] = h_v of the row held in
+// The unit's keys from z = S'' + 2^52 - F'': y[k] = h_v of the row held in
 // register k (z = 2^52 + 2y exactly, 2y < 2^44: the high word is the
 // exponent word kHiWord52 plus 2y >> 32, so y mod P (2^31 = 1) is
 // (lo >> 1) + hi - kHiWord52, below 2P).
 template <int LOGV>
-__device__ inline void extract_keys(const double (&t)[1 << LOGV], double Sm, uint32_t (&y)[1 << LOGV]) {
+__device__ inline void extract_keys(const double (&z)[1 << LOGV], uint32_t (&y)[1 << LOGV]) {
 #pragma unroll
     for (int k = 0; k < (1 << LOGV); ++k) {
-        const uint64_t zb = __double_as_longlong(Sm - t[k]);
+        const uint64_t zb = __double_as_longlong(z[k]);
         const uint32_t half = uint32_t(zb) >> 1, hi = uint32_t(zb >> 32);
         uint32_t y2;  // half + hi - kHiWord52, below 2P, in one three-operand add
         __asm__("v_add3_u32 %0, %1, %2, %3" : "=v"(y2) : "v"(half), "v"(hi), "s"(0u - kHiWord52));
@@ -382,7 +397,8 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
             __asm__ volatile("" ::: "memory");
             __builtin_amdgcn_wave_barrier();
             uint32_t y[V];
-            extract_keys<LOGV>(t, fht_unit<LOGD, LOGV>(t, lane), y);
+            fht_unit<LOGD, LOGV>(t, lane);
+            extract_keys<LOGV>(t, y);
             stage_keys<LOGD, LOGV, NW>(y, lane, wave, stage);
         }
         __syncthreads();
@@ -472,7 +488,8 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_sparse_kernel(
     uint32_t *stage = reinterpret_cast<uint32_t *>(lds64);
     if (grp < ngroups) {
         uint32_t y[V];
-        extract_keys<LOGV>(t, fht_unit<LOGD, LOGV>(t, lane), y);
+        fht_unit<LOGD, LOGV>(t, lane);
+        extract_keys<LOGV>(t, y);
         stage_keys<LOGD, LOGV, NW>(y, lane, wave, stage);
     }
     __syncthreads();
