@@ -201,8 +201,8 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
 // (31 - dir_bits) fit 16 bits, so that a bin's keys are told apart by their
 // low 16 bits, else 4.
 int table_key_bytes(int dir_bits);
-// Whether pass 1 hands pass 2 6-byte entries (16-bit stored keys, pass 2 on
-// super-bins, ids below 2^25) instead of 8-byte ones.
+// Whether the passes hand on 6-byte entries (16-bit stored keys, no merged
+// pass-2 groups, ids below 2^25) instead of 8-byte ones.
 bool table_packed_pass1(int64_t n, int dir_bits);
 // Whole 31-bit keys of tables [T0, T1) into out [T1-T0][n] (the bin bits
 // from the directory), on st.

@@ -23,9 +23,11 @@
 // Ids are implicit in pass 1 (a point's index), so the keys written by the
 // hash kernel are read twice and each table entry is written twice (three
 // times with pass 1b).  Between the passes an entry takes 8 bytes (key, id)
-// or, when pass 2 follows directly on super-bins and stores 16-bit keys, 6
+// or, when the tables store 16-bit keys and pass 2 merges no groups, 6
 // bytes: the 23 key bits below the super-bin digit with the id's low 9 bits
 // above them, and the id's remaining bits as 16 bits (ids below 2^25).
+#include <type_traits>
+
 #include "common.h"
 
 namespace fclsh {
@@ -434,10 +436,11 @@ __host__ __device__ constexpr int p2_region_a(int lo_bits) {
 // known from the directory, holds the rest), which saves 2 of pass 2's 16
 // bytes per entry and of a query's bytes per bucket entry.
 //
-// PK: the input entries are pass 1's 6-byte form.  Their key word holds the
-// key bits pass 2 uses (the bin digit below the super-bin and the stored
-// low bits; pass 2 then runs on super-bins, gbits = 8) and the id's low bits
-// on top, which the digit mask and the 16-bit store both leave out.
+// PK: the input entries are the 6-byte form.  Their key word holds the key
+// bits pass 2 uses (the bin digit below the group's bits and the stored low
+// bits, all below the super-bin digit when no groups are merged) and the
+// id's low bits on top, which the digit mask and the 16-bit store both leave
+// out.
 template <typename KT, bool PK>
 struct P2Args {
     const uint32_t *kin;        // the group's input run (table offset applied)
@@ -793,12 +796,16 @@ __global__ __launch_bounds__(kNT, 4) void p2_rest_kernel(const uint32_t *__restr
 // keeps every chunk's runs at 512 entries or more.
 constexpr int kMaxSplitBits = 4;
 
-template <int ITEMS>
+// PK: 6-byte entries (pass 1's packed form, kept): the split reads its
+// sub-digit from the key word's low bits and moves the 16-bit id word along
+// unchanged; the id itself is assembled only by pass 2.
+template <int ITEMS, bool PK>
 __global__ __launch_bounds__(kNT, ITEMS <= 8 ? 6 : 4) void p1b_split_kernel(const uint32_t *__restrict__ ikeys,
-                                                           const uint32_t *__restrict__ iids, int64_t n,
+                                                           const void *__restrict__ iids, int64_t n,
                                                            const uint32_t *__restrict__ bstart, int sbits,
-                                                           uint32_t *__restrict__ okeys, uint32_t *__restrict__ oids,
+                                                           uint32_t *__restrict__ okeys, void *__restrict__ oids,
                                                            uint32_t *__restrict__ gstart, int64_t nitems) {
+    using VT = typename std::conditional<PK, uint16_t, uint32_t>::type;
     constexpr int MS = 1 << kMaxSplitBits;
     constexpr int CHUNK = kNT * ITEMS;
     __shared__ uint32_t sk[CHUNK];
@@ -815,8 +822,10 @@ __global__ __launch_bounds__(kNT, ITEMS <= 8 ? 6 : 4) void p1b_split_kernel(cons
     const uint32_t bs = bstart[int64_t(T) * (kHiBins + 1) + sb];
     const uint32_t count = bstart[int64_t(T) * (kHiBins + 1) + sb + 1] - bs;
     const int64_t off = int64_t(T) * n + bs;
-    const uint32_t *kin = ikeys + off, *vin = iids + off;
-    uint32_t *okey = okeys + off, *oid = oids + off;
+    const uint32_t *kin = ikeys + off;
+    const VT *vin = static_cast<const VT *>(iids) + off;
+    uint32_t *okey = okeys + off;
+    VT *oid = static_cast<VT *>(oids) + off;
     if (threadIdx.x < MS) cnt[threadIdx.x] = 0;
     __syncthreads();
     {
@@ -890,7 +899,7 @@ __global__ __launch_bounds__(kNT, ITEMS <= 8 ? 6 : 4) void p1b_split_kernel(cons
                 const uint32_t d = (kk[k] >> shift) & mask;
                 const uint32_t dst = run[d] + (uint32_t(k * kNT) + threadIdx.x - cst[d]);
                 okey[dst] = kk[k];
-                oid[dst] = vv[k];
+                oid[dst] = VT(vv[k]);
             }
         } else {
             for (uint32_t j = threadIdx.x; j < chunk; j += kNT) {
@@ -898,7 +907,7 @@ __global__ __launch_bounds__(kNT, ITEMS <= 8 ? 6 : 4) void p1b_split_kernel(cons
                 const uint32_t d = (key >> shift) & mask;
                 const uint32_t dst = run[d] + (j - cst[d]);
                 okey[dst] = key;
-                oid[dst] = sv[j];
+                oid[dst] = VT(sv[j]);
             }
         }
         __syncthreads();
@@ -988,8 +997,7 @@ fclsh_status launch_pass2(const uint32_t *p2k, const void *p2v, int64_t L, int64
 int table_key_bytes(int dir_bits) { return 31 - dir_bits <= 16 ? 2 : 4; }
 
 bool table_packed_pass1(int64_t n, int dir_bits) {
-    return table_key_bytes(dir_bits) == 2 && table_split_bits(n, dir_bits) == 0 && table_merge_bits(n, dir_bits) == 0 &&
-           n <= (int64_t(1) << (kPkIdLow + 16));
+    return table_key_bytes(dir_bits) == 2 && table_merge_bits(n, dir_bits) == 0 && n <= (int64_t(1) << (kPkIdLow + 16));
 }
 
 namespace {
@@ -1053,8 +1061,8 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     const int64_t nitems = int64_t(nblk) * L;
     const int64_t grid1 = xcd_grid(nitems);
     if (grid1 > 0x7FFFFFFF) return fail(FCLSH_EUNSUPPORTED, "too many table tiles");
-    // 6-byte entries between the passes when pass 2 follows on super-bins
-    // and stores 16-bit keys (ids then stay below 2^25)
+    // 6-byte entries between the passes when the tables store 16-bit keys
+    // and pass 2 merges no groups
     const bool packed = table_packed_pass1(n, dir_bits);
     if (packed)
         hipLaunchKernelGGL(p1_scatter_kernel<true>, dim3(unsigned(grid1)), dim3(kP1NT), 0, st, keys, n, hist, nblk,
@@ -1065,19 +1073,28 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[2], st));
     // pass 2 input: the pass-1 output, or after the split the hash-key buffer
-    // (keys) and the table id array (ids reordered in place)
-    const uint32_t *p2k = tmpk, *p2v = tmpv;
+    // (keys) and the table id array (ids reordered in place); with 6-byte
+    // entries the split's 16-bit id words go to the second half of tmpv
+    const uint32_t *p2k = tmpk;
+    const void *p2v = tmpv;
     if (S) {
         const int64_t nsb = int64_t(kHiBins) * L;
-        if (S <= 3)
-            hipLaunchKernelGGL(p1b_split_kernel<8>, dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk, tmpv, n, bstart, S,
-                               keys, tids, gstart, nsb);
+        void *sv = packed ? static_cast<void *>(reinterpret_cast<uint16_t *>(tmpv) + L * n) : static_cast<void *>(tids);
+        if (S <= 3 && packed)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(p1b_split_kernel<8, true>), dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk,
+                               tmpv, n, bstart, S, keys, sv, gstart, nsb);
+        else if (S <= 3)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(p1b_split_kernel<8, false>), dim3(unsigned(nsb)), dim3(kNT), 0, st,
+                               tmpk, tmpv, n, bstart, S, keys, sv, gstart, nsb);
+        else if (packed)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(p1b_split_kernel<16, true>), dim3(unsigned(nsb)), dim3(kNT), 0, st,
+                               tmpk, tmpv, n, bstart, S, keys, sv, gstart, nsb);
         else
-            hipLaunchKernelGGL(p1b_split_kernel<16>, dim3(unsigned(nsb)), dim3(kNT), 0, st, tmpk, tmpv, n, bstart, S,
-                               keys, tids, gstart, nsb);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(p1b_split_kernel<16, false>), dim3(unsigned(nsb)), dim3(kNT), 0, st,
+                               tmpk, tmpv, n, bstart, S, keys, sv, gstart, nsb);
         FCLSH_HIP(hipGetLastError());
         p2k = keys;
-        p2v = tids;
+        p2v = sv;
     }
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
     if (packed)

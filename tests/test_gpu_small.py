@@ -539,6 +539,46 @@ def test_timed_rebuild_reports_every_kernel():
     idx.close()
 
 
+def test_split_pass_8byte_entries():
+    """Above 2^25 points ids no longer fit the 6-byte entries, so the passes
+    hand on 8-byte ones through the split (4 bits here).  33.6 million
+    points of 32 bits, r = 2 (7 tables): the oracle checks the keys of
+    sampled points; two whole tables are checked against the library's
+    keys of every point (themselves pinned by the samples): grouped by bin,
+    ids ascending in a bin, a permutation, the directory, each point under
+    its own key; then sampled answers against the linear scan."""
+    rng = np.random.default_rng(47)
+    n, d, r, seed = (1 << 25) + 4099, 32, 2, 97
+    pts = synth.uniform_points(n, d, rng)
+    _say(f"[split8] n={n}")
+    pts_d = dev(pts)
+    idx = fc.Index(pts_d, d, r, seed=seed)
+    inf = idx.info
+    assert inf["group_bits"] == 12 and idx.table_pointers()[4] == 2
+    pr = oracle.derive_params(d, r, seed)
+    which = np.sort(rng.choice(n, size=64, replace=False))
+    want = oracle.keys(pts, pr, which=which)
+    keys = idx.hash(pts_d)
+    assert np.array_equal(as_u32(keys[:, torch.from_numpy(which).cuda()]), want)
+    db = inf["dir_bits"]
+    dr_all = as_u32(idx.directory())
+    for T in (0, pr.L - 1):
+        _say(f"[split8] table {T}")
+        tk, ti = (as_u32(x)[0] for x in idx.tables(T, T + 1))
+        kt = as_u32(keys[T])
+        bins = tk >> np.uint32(31 - db)
+        assert np.all(np.diff(bins.astype(np.int64)) >= 0)
+        same = np.diff(bins.astype(np.int64)) == 0
+        assert np.all(np.diff(ti.astype(np.int64))[same] > 0)
+        assert np.array_equal(np.sort(ti), np.arange(n, dtype=np.uint32))
+        assert np.array_equal(tk, kt[ti])
+        assert np.array_equal(dr_all[T], np.searchsorted(bins, np.arange((1 << db) + 1)).astype(np.uint32))
+    del keys
+    qs = pts[rng.choice(n, size=4, replace=False)]
+    assert_same_lists(csr_lists(*idx.query(dev(qs), r)), oracle.brute_force(pts, d, qs, r).ids)
+    idx.close()
+
+
 @pytest.mark.parametrize("n,dup,split", [(1_200_000, False, 1), (1_200_000, True, 1), (4_500_000, False, 3)],
                          ids=["uniform", "heavy", "three_bits"])
 def test_split_pass_for_large_n(n, dup, split):
