@@ -168,10 +168,10 @@ def main():
     ballot_entries = int(sb_count[~rest & (sb_max > 48)].sum().item())
     dir_bytes = 4 * L * ((1 << dir_bits) + 1)
     # the tables store a key as its low 16 bits when the bin holds the rest;
-    # with such keys and pass 2 on the 256 super-bins (group_bits 8), pass 1
-    # hands pass 2 6-byte entries instead of 8-byte ones
+    # with such keys, no merged pass-2 groups (group_bits >= 8) and ids below
+    # 2^25, the passes hand on 6-byte entries instead of 8-byte ones
     kb = idx.table_pointers()[4]
-    mid_bytes = 6 if (kb == 2 and group_bits == 8) else 8
+    mid_bytes = 6 if (kb == 2 and group_bits >= 8 and n <= 1 << 25) else 8
     # bytes each kernel moves itself (its reads and writes, for the counter
     # comparison) ...
     moved_bytes = {
@@ -179,8 +179,10 @@ def main():
         "p1_hist_kernel": 4 * entries + 4 * L * nblk * 256,          # read keys, write tile histograms
         "p1_scan_kernel": 8 * L * nblk * 256,                        # read + write the histograms
         "p1_scatter_kernel": (4 + mid_bytes) * entries,              # read key, write the entry
-        # split of the super-bins (large n only): read keys twice and ids once, write both
-        "p1b_split_kernel": (20 * entries + 4 * L * ((256 << (group_bits - 8)) + 1)) if group_bits > 8 else 0,
+        # split of the super-bins (large n only): read the key words twice and
+        # the id words once, write both
+        "p1b_split_kernel": ((8 + 2 * mid_bytes) * entries + 4 * L * ((256 << (group_bits - 8)) + 1))
+        if group_bits > 8 else 0,
         # pass 2: read the entry, write the stored key (kb bytes) and id of
         # each entry it reorders, and its bins' directory entries
         "p2_fast_kernel": (mid_bytes + 4 + kb) * (entries - rest_entries) + dir_bytes * (1 - rest_entries / entries),
