@@ -181,7 +181,7 @@ def main():
         "p1_scatter_kernel": (4 + mid_bytes) * entries,              # read key, write the entry
         # split of the super-bins (large n only): read the key words twice and
         # the id words once, write both
-        "p1b_split_kernel": ((8 + 2 * mid_bytes) * entries + 4 * L * ((256 << (group_bits - 8)) + 1))
+        "p1b_split_kernel": ((4 + 2 * mid_bytes) * entries + 4 * L * ((256 << (group_bits - 8)) + 1))
         if group_bits > 8 else 0,
         # pass 2: read the entry, write the stored key (kb bytes) and id of
         # each entry it reorders, and its bins' directory entries
