@@ -174,3 +174,27 @@ def test_header_struct_layout_matches_binding():
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     want = [fc.ctypes.sizeof(fc.BuildOpts)] + [getattr(fc.BuildOpts, f).offset for f, _ in fc.BuildOpts._fields_]
     assert [int(x) for x in out] == want
+
+
+HANDLE_CALLS = [
+    "fclsh_hash_sparse", "fclsh_query_batch_sparse", "fclsh_query_cost_sparse", "fclsh_query_batch",
+    "fclsh_index_info", "fclsh_index_memory", "fclsh_index_params", "fclsh_hash", "fclsh_index_tables",
+    "fclsh_index_table_keys", "fclsh_index_rebuild", "fclsh_index_rebuild_async", "fclsh_index_rebuild_timed",
+    "fclsh_index_build_mode", "fclsh_query_collisions", "fclsh_query_cost", "fclsh_query_plain",
+    "fclsh_query_batch_finish", "fclsh_query_batch_radii", "fclsh_query_reserve", "fclsh_query_batch_async",
+    "fclsh_query_batch_noalloc", "fclsh_query_graph_create", "fclsh_index_set_tuning", "fclsh_index_get_tuning",
+    "fclsh_index_set_schedule", "fclsh_index_get_schedule", "fclsh_autotune",
+]
+
+
+@pytest.mark.parametrize("name", HANDLE_CALLS)
+def test_null_index_is_rejected(name):
+    """Every call on an index checks its handle before any device work: a
+    null handle gives FCLSH_EINVAL (here, with no GPU, nothing else runs)."""
+    import ctypes
+
+    fn = getattr(fc.lib(), name)
+    assert fn.argtypes, f"{name}: no signature in the binding"
+    scalars = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float, ctypes.c_double)
+    args = [0 if t in scalars else None for t in fn.argtypes]  # pointers null
+    assert fn(*args) == fc.FCLSH_EINVAL, name
