@@ -646,24 +646,30 @@ __global__ void scatter_pairs_kernel(const uint32_t *__restrict__ pq, const uint
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t tot = int64_t(min((unsigned long long)pair_cap, ctrl->pairs));
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    // whole waves step together, so that every lane takes part in the ballots
+    // whole waves step together, so that every lane takes part in the
+    // ballots.  A run of lanes with the same query takes one fill atomic,
+    // issued by its first lane; all runs of a wave issue theirs together.
     for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); i0 < tot; i0 += stride) {
         const int64_t i = i0 + lane;
-        const bool valid = i < tot;
+        const bool valid = i < tot;  // the valid lanes are a prefix of the wave
         const uint32_t q = valid ? pq[i] : 0u;
         const uint32_t id = valid ? pid[i] : 0u;
-        for (uint64_t rem = __ballot(valid); rem;) {
-            const int l = __builtin_ctzll(rem);
-            const uint32_t q0 = uint32_t(__shfl(int(q), l, 64));
-            const uint64_t same = __ballot(valid && q == q0) & rem;
-            uint32_t base = 0;
-            if (lane == l) base = atomicAdd(&qfill[q0], uint32_t(__popcll(same)));
-            base = uint32_t(__shfl(int(base), l, 64));
-            if ((same >> lane) & 1) {
-                const uint64_t slot = offsets[q0] + base + uint32_t(__popcll(same & lt));
-                if (slot < uint64_t(ids_cap)) ids[slot] = id;
-            }
-            rem &= ~same;
+        const uint32_t qprev = uint32_t(__shfl_up(int(q), 1, 64));
+        const bool head = valid && (lane == 0 || qprev != q);
+        const uint64_t heads = __ballot(head);
+        const int nvalid = __popcll(__ballot(valid));
+        const uint64_t upto = heads & (lt | (1ull << lane));  // heads at or below this lane
+        const int h = upto ? 63 - __builtin_clzll(upto) : 0;  // this lane's run head
+        uint32_t base = 0;
+        if (head) {
+            const uint64_t above = heads & ~(lt | (1ull << lane));
+            const int next = above ? __builtin_ctzll(above) : nvalid;
+            base = atomicAdd(&qfill[q], uint32_t(next - lane));
+        }
+        base = uint32_t(__shfl(int(base), h, 64));
+        if (valid) {
+            const uint64_t slot = offsets[q] + base + uint32_t(lane - h);
+            if (slot < uint64_t(ids_cap)) ids[slot] = id;
         }
     }
 }
