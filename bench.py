@@ -118,6 +118,14 @@ def main():
     # (fclsh_index_rebuild_async, fclsh_query_batch_async) into buffers sized
     # from one synchronous batch; every step's status is checked after the
     # timed block
+    # the verification launch shape for this index and batch, picked once by
+    # the autotuner before anything is timed (the 4M-point skewed index keeps
+    # the default shape, as its batched block stays off)
+    if args.workload == "batched":
+        step_tuning = dict(idx.get_tuning(), autotuned=False)
+    else:
+        stage("autotuning the query launch shape")
+        step_tuning = dict(idx.autotune(qs, r), autotuned=True)
     stage("sizing the step's buffers from a synchronous batch")
     offs0, _ = idx.query(qs, r)
     total0 = int(offs0[-1].item())
@@ -289,7 +297,7 @@ def main():
             "build_GBps_at_min_bytes": build_bytes / (ms_build * 1e-3) / 1e9, "build_bytes_per_entry": per_entry,
             "kernel_ms": phase_ms,
             "pass2_ballot_share": ballot_entries / entries, "pass2_rest_share": rest_entries / entries,
-            "pass2_form": idx.build_mode,
+            "pass2_form": idx.build_mode, "query_tuning": step_tuning,
             "query_batch_ms": ms_query, "queries_per_s": nq / (ms_query * 1e-3),
             "reported_ids": total_ids, "collisions_per_query": coll_per_query,
             "candidates_per_query": cand_per_query,
