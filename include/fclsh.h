@@ -90,8 +90,13 @@ typedef struct {
                                   build, for rebuilds; 0 = release it when the
                                   build ends (a later rebuild allocates it again
                                   and keeps it)                                    */
-    int32_t reserved;          /* must be 0                                        */
+    int32_t test_flags;        /* 0; for tests only, bit 0 (FCLSH_TEST_P2_FALLBACK):
+                                  the table build treats the id-order check of
+                                  every pass-2 group as failed, so that its
+                                  fallbacks run; other bits are FCLSH_EINVAL      */
 } fclsh_build_opts;
+
+#define FCLSH_TEST_P2_FALLBACK 1
 
 #define FCLSH_BUILD_OPTS_INIT {(uint32_t)sizeof(fclsh_build_opts), 0, 0, 0, 0, 0, 0, 0}
 

@@ -61,13 +61,13 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("partitions", ctypes.c_int32),
                 ("replicate", ctypes.c_int32), ("exclude_column0", ctypes.c_int32),
                 ("prime", ctypes.c_uint64), ("mem_budget_bytes", ctypes.c_uint64),
-                ("keep_build_scratch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("keep_build_scratch", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
 
     @classmethod
     def make(cls, partitions=0, replicate=0, exclude_column0=False, mem_budget_bytes=0,
-             keep_build_scratch=False):
+             keep_build_scratch=False, test_flags=0):
         return cls(ctypes.sizeof(cls), partitions, replicate, int(bool(exclude_column0)), 0,
-                   mem_budget_bytes, int(bool(keep_build_scratch)), 0)
+                   mem_budget_bytes, int(bool(keep_build_scratch)), int(test_flags))
 
 
 _lib = None
@@ -223,14 +223,16 @@ class Index:
 
     def __init__(self, points, d: int, r: int, seed: int = 0, partitions: int = 0,
                  mem_budget_bytes: int = 0, stream=None, *, replicate: int = 0,
-                 exclude_column0: bool = False, keep_build_scratch: bool = False, _params=None):
+                 exclude_column0: bool = False, keep_build_scratch: bool = False, _params=None,
+                 _test_flags: int = 0):
         torch = _torch()
         pts = _dev_words(points, d, "points")
         n = pts.shape[0]
         h = ctypes.c_void_p()
         st = _stream_ptr(stream)
         if _params is None:
-            opts = BuildOpts.make(partitions, replicate, exclude_column0, mem_budget_bytes, keep_build_scratch)
+            opts = BuildOpts.make(partitions, replicate, exclude_column0, mem_budget_bytes, keep_build_scratch,
+                                  _test_flags)
             _check(lib().fclsh_build_index(ctypes.c_void_p(pts.data_ptr()), n, d, r, seed & (2**64 - 1),
                                            ctypes.byref(opts), st, ctypes.byref(h)))
         else:

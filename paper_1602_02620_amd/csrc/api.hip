@@ -190,7 +190,7 @@ static fclsh_status hash_and_bucket(IndexHandle *h, hipStream_t st, hipEvent_t *
         FCLSH_TRY(launch_hash(ix, ix.pts, ix.n, h->keys, ix.n, st));
     if (marks) FCLSH_HIP(hipEventRecord(marks[1], st));
     FCLSH_TRY(build_tables_2pass(h->keys, L, ix.n, ix.dir_bits, h->tk, h->tv, h->aux, ix.tkeys, ix.tids, ix.dir,
-                                 ix.build_mode, st, marks ? marks + 2 : nullptr));
+                                 ix.build_mode, ix.p2_fallback, st, marks ? marks + 2 : nullptr));
     h->cnt_mode = ix.build_mode;
     FCLSH_HIP(hipMemcpyAsync(h->host_cnt, table_build_counts(h->aux, L, ix.n, ix.dir_bits), 2 * sizeof(uint32_t),
                              hipMemcpyDeviceToHost, st));
@@ -229,7 +229,8 @@ static fclsh_status check_rows(const CsrRows &rows, int64_t m, int d, hipStream_
 
 // d_points (dense [n][W] words) or rows (sparse; prm.sparse) is the input.
 static fclsh_status build_common(const uint64_t *d_points, const CsrRows *rows, int64_t n, Params &&prm,
-                                 uint64_t budget, bool keep_scratch, hipStream_t st, fclsh_index *out) {
+                                 uint64_t budget, bool keep_scratch, int32_t test_flags, hipStream_t st,
+                                 fclsh_index *out) {
     if (!out) return fail(FCLSH_EINVAL, "out is null");
     *out = nullptr;
     if (prm.sparse != (rows != nullptr)) return fail(FCLSH_EINVAL, "point format does not match the parameters");
@@ -256,6 +257,7 @@ static fclsh_status build_common(const uint64_t *d_points, const CsrRows *rows, 
         (void)hipGetLastError();
     }
     lookup_tuning(ix);
+    ix.p2_fallback = (test_flags & FCLSH_TEST_P2_FALLBACK) != 0;
     h->keep_scratch = keep_scratch;
     auto bail = [&](fclsh_status s) {
         destroy_handle(h);
@@ -415,7 +417,7 @@ static fclsh_status read_opts(const fclsh_build_opts *in, fclsh_build_opts *out)
     std::memcpy(reinterpret_cast<char *>(out) + sizeof(uint32_t), reinterpret_cast<const char *>(in) + sizeof(uint32_t),
                 in->struct_size - sizeof(uint32_t));
     out->struct_size = sizeof(fclsh_build_opts);
-    if (out->reserved != 0) return fail(FCLSH_EINVAL, "opts->reserved must be 0");
+    if (out->test_flags & ~FCLSH_TEST_P2_FALLBACK) return fail(FCLSH_EINVAL, "unknown opts->test_flags bits");
     return FCLSH_OK;
 }
 
@@ -482,7 +484,7 @@ fclsh_status fclsh_build_index(const uint64_t *d_points, int64_t n, int32_t d, i
     Params p;
     FCLSH_TRY(derive_params(d, r, seed, &o, &p));
     return build_common(d_points, nullptr, n, std::move(p), o.mem_budget_bytes, o.keep_build_scratch != 0,
-                        reinterpret_cast<hipStream_t>(stream), out);
+                        o.test_flags, reinterpret_cast<hipStream_t>(stream), out);
 }
 
 fclsh_status fclsh_build_index_sparse(const int64_t *d_ptr, const int32_t *d_cols, int64_t n, int64_t nnz, int32_t d,
@@ -496,7 +498,7 @@ fclsh_status fclsh_build_index_sparse(const int64_t *d_ptr, const int32_t *d_col
     FCLSH_TRY(derive_params(d, r, seed, &o, &p, true));
     const CsrRows rows{d_ptr, d_cols, nnz};
     return build_common(nullptr, &rows, n, std::move(p), o.mem_budget_bytes, o.keep_build_scratch != 0,
-                        reinterpret_cast<hipStream_t>(stream), out);
+                        o.test_flags, reinterpret_cast<hipStream_t>(stream), out);
 }
 
 fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, int64_t n, int32_t d, int32_t r, int32_t t,
@@ -514,7 +516,7 @@ fclsh_status fclsh_build_index_with_params(const uint64_t *d_points, int64_t n, 
     p.part.assign(part, part + d);
     p.col.assign(col, col + d);
     p.b.assign(b, b + d);
-    return build_common(d_points, nullptr, n, std::move(p), 0, false, reinterpret_cast<hipStream_t>(stream), out);
+    return build_common(d_points, nullptr, n, std::move(p), 0, false, 0, reinterpret_cast<hipStream_t>(stream), out);
 }
 
 void fclsh_index_free(fclsh_index idx) {

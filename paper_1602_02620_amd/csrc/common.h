@@ -135,6 +135,7 @@ struct Index {
     uint64_t *pts = nullptr;   // [n][W]
     void *tkeys = nullptr;     // [L][n] of key_bytes each (the low 16 bits, or the whole key)
     int key_bytes = 4;
+    bool p2_fallback = false;  // tests: pass 2 takes its fallbacks (FCLSH_TEST_P2_FALLBACK)
     uint32_t *tids = nullptr;  // [L][n]
     uint32_t *dir = nullptr;   // [L][2^dir_bits + 1]
     // per-index device copies of part/col for the duplicate-elimination rule
@@ -196,7 +197,7 @@ int table_merge_bits(int64_t n, int dir_bits);
 size_t table_build_scratch_bytes(int64_t L, int64_t n, int dir_bits);
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
                                 uint32_t *scratch, void *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
-                                hipStream_t st, hipEvent_t *marks = nullptr);
+                                bool p2_fallback, hipStream_t st, hipEvent_t *marks = nullptr);
 // Bytes per stored table key: 2 when the key bits below the directory bin
 // (31 - dir_bits) fit 16 bits, so that a bin's keys are told apart by their
 // low 16 bits, else 4.

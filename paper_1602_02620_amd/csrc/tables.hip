@@ -452,6 +452,7 @@ struct P2Args {
     uint32_t bs;                // group start within the table
     int shift, lo_bits;
     uint32_t mask;
+    bool fallback;  // tests: treat the id-order check as failed
     // the id word of input entry e, and the id from it and the entry's key
     // word k (apart, so that a thread's loads are all issued before any of
     // them is waited for)
@@ -500,10 +501,21 @@ __device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // region A: keys and ids in slot (fast) or final (stable) order; in the
     // stable branch first the per-wave digit counters [kWaves][R]
+    // With 16-bit stored keys (WS) the slot branch counts bins per wave.  A
+    // wave's LDS atomics run in issue order, so its entries of a bin receive
+    // slots in input order when the lanes of one atomic that hit the same
+    // counter are served in lane order, which is what the hardware does.
+    // The branch does not rely on it: it places every entry at bin start +
+    // the bin's entries of earlier waves + its slot, checks that ids ascend
+    // within every bin (input order is id order), and writes the group out
+    // contiguously; a group where they do not falls back to the id walk.
+    constexpr bool WS = sizeof(KT) == 2;
     uint32_t *bk = lds;
     uint32_t *bv = lds + kFastTile;
     uint32_t *cnt = lds + p2_region_a(a.lo_bits);  // R + 1 words: bin counts, then bin starts and the end
     for (int i = threadIdx.x; i < R; i += kNT) cnt[i] = 0;
+    if constexpr (WS)
+        for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // per-wave bin counters
     if (threadIdx.x == 0) cnt[R] = a.count;
     __syncthreads();
     const uint32_t ipw = (a.count + kNT - 1) / kNT;  // rounds per wave, at most kFastItems
@@ -518,9 +530,26 @@ __device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     }
 #pragma unroll
     for (int it = 0; it < kFastItems; ++it) rv[it] = a.id_of(rv[it], rk[it]);
+    if constexpr (WS) {
 #pragma unroll
-    for (int it = 0; it < kFastItems; ++it)
-        pos[it] = ok(it) ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
+        for (int it = 0; it < kFastItems; ++it)
+            pos[it] = ok(it) ? atomicAdd(&lds[wave * R + ((rk[it] >> a.shift) & a.mask)], 1u) : 0u;
+        __syncthreads();
+        // per bin: the per-wave counts become per-wave starts, the total its count
+        for (int d = threadIdx.x; d < R; d += kNT) {
+            uint32_t run = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = lds[w * R + d];
+                lds[w * R + d] = run;
+                run += c;
+            }
+            cnt[d] = run;
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < kFastItems; ++it)
+            pos[it] = ok(it) ? atomicAdd(&cnt[(rk[it] >> a.shift) & a.mask], 1u) : 0u;
+    }
     __syncthreads();
     bool fast = true;
     if constexpr (!ANY_BIN) {
@@ -528,21 +557,9 @@ __device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
         for (int i = threadIdx.x; i < R; i += kNT) mx = max(mx, cnt[i]);
         fast = block_max_u32(mx, sh) <= kMaxFastBin;
     }
-    if (SLOT_ONLY && !fast) return kGroupLeft;
-    if (!fast) {
-        for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // per-wave counters
-    }
-    digit_starts<kNT>(cnt, R, 0u, sh);  // ends with a barrier
-    for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + cnt[i];
-    if (fast) {
-#pragma unroll
-        for (int it = 0; it < kFastItems; ++it)
-            if (ok(it)) {
-                const uint32_t q = cnt[(rk[it] >> a.shift) & a.mask] + pos[it];
-                bk[q] = rk[it];
-                bv[q] = rv[it];
-            }
-        __syncthreads();
+    // the slot walk: each entry's final place is its bin start plus the ids
+    // of its bin smaller than its own (bk, bv hold the group by bin)
+    const auto walk_out = [&]() {
         for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
             const uint32_t k = bk[j], v = bv[j];
             const uint32_t dg = (k >> a.shift) & a.mask;
@@ -557,7 +574,61 @@ __device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
             a.okey[r] = KT(k);
             a.oid[r] = v;
         }
-        return kGroupSlot;
+    };
+    if constexpr (WS) {
+        // every group: the per-wave slots, then the check of the id order
+        digit_starts<kNT>(cnt, R, 0u, sh);  // ends with a barrier
+        for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + cnt[i];
+#pragma unroll
+        for (int it = 0; it < kFastItems; ++it)
+            if (ok(it)) {
+                const uint32_t d = (rk[it] >> a.shift) & a.mask;
+                pos[it] += cnt[d] + lds[wave * R + d];  // bin start + the bin's entries in earlier waves
+            }
+        __syncthreads();  // the counters' space becomes the slot buffer
+#pragma unroll
+        for (int it = 0; it < kFastItems; ++it)
+            if (ok(it)) {
+                bk[pos[it]] = rk[it];
+                bv[pos[it]] = rv[it];
+            }
+        __syncthreads();
+        bool bad = false;
+        for (uint32_t j = threadIdx.x + 1; j < a.count; j += kNT)
+            bad |= ((bk[j] ^ bk[j - 1]) >> a.shift & a.mask) == 0 && bv[j - 1] > bv[j];
+        if (!__syncthreads_or(bad || a.fallback)) {
+            for (uint32_t j = threadIdx.x; j < a.count; j += kNT) {
+                a.okey[j] = KT(bk[j]);
+                a.oid[j] = bv[j];
+            }
+            return kGroupSlot;
+        }
+        if (SLOT_ONLY && !fast) return kGroupLeft;  // the second kernel redoes the group
+        if (fast) {
+            walk_out();
+            return kGroupSlot;
+        }
+        for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // ballot counters
+        __syncthreads();
+    } else {
+        if (SLOT_ONLY && !fast) return kGroupLeft;
+        if (!fast) {
+            for (int i = threadIdx.x; i < kWaves * R; i += kNT) lds[i] = 0;  // per-wave counters
+        }
+        digit_starts<kNT>(cnt, R, 0u, sh);  // ends with a barrier
+        for (int i = threadIdx.x; i < R; i += kNT) a.dr[i] = a.bs + cnt[i];
+        if (fast) {
+#pragma unroll
+            for (int it = 0; it < kFastItems; ++it)
+                if (ok(it)) {
+                    const uint32_t q = cnt[(rk[it] >> a.shift) & a.mask] + pos[it];
+                    bk[q] = rk[it];
+                    bv[q] = rv[it];
+                }
+            __syncthreads();
+            walk_out();
+            return kGroupSlot;
+        }
     }
     // stable branch: input order is id order; rank = bin start + entries of
     // the bin in earlier waves + earlier entries of this wave
@@ -693,7 +764,7 @@ __device__ void p2_stable_chunked(const P2Args<KT, PK> &a, uint32_t *lds, uint32
 template <typename KT, bool PK>
 __device__ inline P2Args<KT, PK> p2_args(const uint32_t *ikeys, const void *iids, int64_t n,
                                          const uint32_t *gstart, int gbits, int lo_bits, int gk, KT *tkeys,
-                                         uint32_t *tids, uint32_t *dir, int T, int g) {
+                                         uint32_t *tids, uint32_t *dir, int T, int g, bool fallback = false) {
     const int64_t toff = int64_t(T) * n;
     // group starts per table: 2^(gbits + gk) + 1 (<= 4097), so the index
     // fits 32 bits and stays in scalar registers (a 64-bit product lands in
@@ -717,6 +788,7 @@ __device__ inline P2Args<KT, PK> p2_args(const uint32_t *ikeys, const void *iids
     a.lo_bits = lo_bits;
     a.shift = 31 - gbits - lo_bits;
     a.mask = (1u << lo_bits) - 1u;
+    a.fallback = fallback;
     return a;
 }
 
@@ -733,7 +805,7 @@ template <typename KT, bool PK, bool SLOT_ONLY, bool ANY_BIN = false>
 __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const uint32_t *__restrict__ ikeys, const void *iids, int64_t n, const uint32_t *__restrict__ gstart,
     int gbits, int lo_bits, int gk, KT *__restrict__ tkeys, uint32_t *tids, uint32_t *__restrict__ dir,
-    uint32_t *__restrict__ rest, uint32_t *__restrict__ counts, int64_t nitems) {
+    uint32_t *__restrict__ rest, uint32_t *__restrict__ counts, int64_t nitems, int fallback) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t sh[kWaves + 1];
     const int64_t w = xcd_contiguous_item(blockIdx.x, gridDim.x);
@@ -741,7 +813,8 @@ __global__ __launch_bounds__(kNT, SLOT_ONLY ? 8 : 6) void p2_fast_kernel(
     const int T = int(w >> gbits), g = int(w & ((int64_t(1) << gbits) - 1));
     if (g == (1 << gbits) - 1 && threadIdx.x == 0)
         dir[int64_t(T) * ((int64_t(1) << (gbits + lo_bits)) + 1) + (int64_t(1) << (gbits + lo_bits))] = uint32_t(n);
-    const P2Args<KT, PK> a = p2_args<KT, PK>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g);
+    const P2Args<KT, PK> a =
+        p2_args<KT, PK>(ikeys, iids, n, gstart, gbits, lo_bits, gk, tkeys, tids, dir, T, g, fallback != 0);
     const int how = a.count <= uint32_t(kFastTile) ? p2_group<KT, PK, SLOT_ONLY, ANY_BIN>(a, lds, sh) : kGroupLeft;
     if (threadIdx.x == 0) {
         if (how == kGroupLeft) rest[atomicAdd(counts, 1u)] = uint32_t(w);
@@ -969,20 +1042,23 @@ namespace {
 template <typename KT, bool PK>
 fclsh_status launch_pass2(const uint32_t *p2k, const void *p2v, int64_t L, int64_t n, const uint32_t *gstart,
                           int gbits2, int lo_bits2, int gk, KT *tkeys, uint32_t *tids, uint32_t *dir, uint32_t *rest,
-                          uint32_t *rest_count, uint32_t *tmpv, BuildMode mode, hipStream_t st, hipEvent_t *marks) {
+                          uint32_t *rest_count, uint32_t *tmpv, BuildMode mode, bool fallback, hipStream_t st,
+                          hipEvent_t *marks) {
+    const int fb = fallback ? 1 : 0;
     const size_t lds2 = (size_t(2) * kTile + 2 * (size_t(1) << lo_bits2)) * 4;
     const size_t lds_fast = (size_t(p2_region_a(lo_bits2)) + (size_t(1) << lo_bits2) + 1) * 4;
     const int64_t nitems2 = int64_t(L) << gbits2;  // (table, group) items, a multiple of kXcds
     if (mode == BuildMode::kSlotAll)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, PK, true, true>), dim3(unsigned(nitems2)), dim3(kNT),
                            lds_fast, st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count,
-                           nitems2);
+                           nitems2, fb);
     else if (mode == BuildMode::kSlotOnly)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, PK, true>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast, st,
-                           p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
+                           p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2, fb);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_fast_kernel<KT, PK, false>), dim3(unsigned(nitems2)), dim3(kNT), lds_fast,
-                           st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2);
+                           st, p2k, p2v, n, gstart, gbits2, lo_bits2, gk, tkeys, tids, dir, rest, rest_count, nitems2,
+                           fb);
     FCLSH_HIP(hipGetLastError());
     if (marks) FCLSH_HIP(hipEventRecord(marks[4], st));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(p2_rest_kernel<KT, PK>), dim3(unsigned(std::min<int64_t>(nitems2, kRestBlocks))), dim3(kNT), lds2,
@@ -1037,7 +1113,7 @@ fclsh_status expand_table_keys(const void *tkeys, int key_bytes, const uint32_t 
 
 fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bits, uint32_t *tmpk, uint32_t *tmpv,
                                 uint32_t *scratch, void *tkeys, uint32_t *tids, uint32_t *dir, BuildMode mode,
-                                hipStream_t st, hipEvent_t *marks) {
+                                bool p2_fallback, hipStream_t st, hipEvent_t *marks) {
     if (L == 0 || n == 0) return FCLSH_OK;
     if (L > 65535) return fail(FCLSH_EUNSUPPORTED, "too many tables");
     if (dir_bits < kHiBits || dir_bits > kHiBits + kMaxLoBits) return fail(FCLSH_EINVAL, "bad directory bits");
@@ -1099,14 +1175,14 @@ fclsh_status build_tables_2pass(uint32_t *keys, int64_t L, int64_t n, int dir_bi
     if (marks) FCLSH_HIP(hipEventRecord(marks[3], st));
     if (packed)
         return launch_pass2<uint16_t, true>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk,
-                                            static_cast<uint16_t *>(tkeys), tids, dir, rest, rest_count, tmpv, mode, st,
-                                            marks);
+                                            static_cast<uint16_t *>(tkeys), tids, dir, rest, rest_count, tmpv, mode,
+                                            p2_fallback, st, marks);
     if (table_key_bytes(dir_bits) == 2)
         return launch_pass2<uint16_t, false>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk,
                                              static_cast<uint16_t *>(tkeys), tids, dir, rest, rest_count, tmpv, mode,
-                                             st, marks);
+                                             p2_fallback, st, marks);
     return launch_pass2<uint32_t, false>(p2k, p2v, L, n, gstart, gbits2, lo_bits2, gk, static_cast<uint32_t *>(tkeys),
-                                         tids, dir, rest, rest_count, tmpv, mode, st, marks);
+                                         tids, dir, rest, rest_count, tmpv, mode, p2_fallback, st, marks);
 }
 
 }  // namespace fclsh

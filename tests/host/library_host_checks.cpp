@@ -135,7 +135,7 @@ static void entry_point_arguments() {
             CHECK(s == FCLSH_OK && t == (sz >= 8 ? 2 : 2));  // r >= 10: two parts either way
     }
     big.o.struct_size = sizeof(fclsh_build_opts);
-    big.o.reserved = 1;
+    big.o.test_flags = 2;  // unknown test flag bit
     CHECK(fclsh_derive_params(300, 12, 5, &big.o, &t, &rp, part.data(), col.data(), b.data()) == FCLSH_EINVAL);
     CHECK(fclsh_derive_params(300, 12, 5, nullptr, nullptr, &rp, part.data(), col.data(), b.data()) == FCLSH_EINVAL);
     std::vector<int32_t> sp(140214), sc(140214);

@@ -155,8 +155,10 @@ def test_build_opts_struct_size():
         st, _ = _derive_with(o)
         assert st == fc.FCLSH_EINVAL
     o = fc.BuildOpts.make()
-    o.reserved = 1
+    o.test_flags = 2  # bit 0 is the only test flag
     assert _derive_with(o)[0] == fc.FCLSH_EINVAL
+    o.test_flags = 1
+    assert _derive_with(o)[0] == fc.FCLSH_OK
 
 
 def test_header_struct_layout_matches_binding():

@@ -280,21 +280,28 @@ def test_radius_and_capacity_errors():
     idx.close()
 
 
-@pytest.mark.parametrize("n,group_bits,mode", [(300000, 8, "slot_only"), (20000, 4, "full")])
-def test_rebuild_slot_only_with_large_bins(n, group_bits, mode):
-    """A first build takes pass 2's full group kernel; when it sent at most
-    1 % of the groups off the slot branch, a rebuild takes the slot-only form,
-    which leaves the groups with a large bin to the second kernel.  Here 60
-    copies of one point put one large bin in every table: at 300000 points
-    that is 1 of 256 groups, so the rebuilds exercise that fallback; at 20000
-    points pass 2 merges 16 super-bins per group, one group in 16 holds the
-    bin, and the rebuilds keep the full form (its ballot branch then takes
-    that group).  Every build equals the oracle."""
+@pytest.mark.parametrize("n,group_bits,mode,flags", [(300000, 8, "slot_all", 0), (300000, 8, "slot_only", 1),
+                                                     (20000, 4, "full", 0)],
+                         ids=["ordered_slots", "forced_fallbacks", "u32_keys"])
+def test_rebuild_slot_only_with_large_bins(n, group_bits, mode, flags):
+    """Here 60 copies of one point put one large bin in every table: at
+    300000 points that is 1 of 256 groups, at 20000 points (32-bit stored
+    keys, 16 super-bins merged per group) one group in 16.
+    With 16-bit stored keys the group kernel places every group by per-wave
+    slots and checks the id order, which holds, so every group stays on the
+    slot branch and rebuilds take the slot-all form.  With the check forced
+    to fail (a test flag), the first build's group with the large bin takes
+    the ballot branch; a first build that sent at most 1 % of the groups off
+    the slot branch makes the rebuilds take the slot-only form, which leaves
+    those groups to the second kernel.  With 32-bit stored keys the group
+    kernel ranks by slot and id walk, the bin's group takes the ballot
+    branch, and the rebuilds keep the full form.  Every build equals the
+    oracle."""
     rng = np.random.default_rng(41)
     d, r = 64, 4
     pts = synth.uniform_points(n, d, rng)
     pts[1:61] = pts[0]  # 61 equal points: equal keys in every table
-    idx = fc.Index(dev(pts), d, r, seed=41)
+    idx = fc.Index(dev(pts), d, r, seed=41, _test_flags=flags)
     orc = OracleIndex(pts, oracle.derive_params(d, r, 41), with_tables=False)
     db = idx.info["dir_bits"]
     assert idx.info["group_bits"] == group_bits
@@ -320,16 +327,19 @@ def test_rebuild_slot_only_with_large_bins(n, group_bits, mode):
     idx.close()
 
 
-@pytest.mark.parametrize("n", [300_000, 8192 * 3 + 77], ids=["many_tiles", "ragged"])
-def test_rebuild_slot_all(n):
+@pytest.mark.parametrize("n,flags", [(300_000, 0), (300_000, 1), (8192 * 3 + 77, 0)],
+                         ids=["many_tiles", "many_tiles_forced_walk", "ragged"])
+def test_rebuild_slot_all(n, flags):
     """Uniform keys: the first build sends no group off the slot branch, so
     rebuilds take pass 2's slot branch for every group without checking bin
-    sizes.  Tables and directory equal the oracle's after each of them,
-    synchronous or not, and so do query answers."""
+    sizes (with the test flag, every group's id-order check counts as
+    failed and the id walk places it).  Tables and directory equal the
+    oracle's after each of them, synchronous or not, and so do query
+    answers."""
     rng = np.random.default_rng(43 + n % 5)
     d, r, seed = 64, 4, 43
     pts = synth.uniform_points(n, d, rng)
-    idx = fc.Index(dev(pts), d, r, seed=seed)
+    idx = fc.Index(dev(pts), d, r, seed=seed, _test_flags=flags)
     pr = oracle.derive_params(d, r, seed)
     orc = OracleIndex(pts, pr, with_tables=False)
     db = idx.info["dir_bits"]
