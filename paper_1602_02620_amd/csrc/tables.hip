@@ -416,6 +416,10 @@ __global__ __launch_bounds__(kP1NT) __attribute__((amdgpu_waves_per_eu(4))) void
 // wave ballots in input order (passes 1 and 1b are stable, so input order is
 // id order), per-wave digit counters, and an LDS reorder.
 //
+// With 16-bit stored keys both branches give way to ordered per-wave slots
+// with a check of the id order (see p2_group); the two branches above are
+// then its fallbacks.
+//
 // Either way the result equals the stable reorder exactly.  Groups over
 // kFastTile entries go to a second kernel: the same ballot ranks over a tile
 // of kTile entries, or for larger groups a histogram read first and a
@@ -500,7 +504,8 @@ __device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     const int R = 1 << a.lo_bits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // region A: keys and ids in slot (fast) or final (stable) order; in the
-    // stable branch first the per-wave digit counters [kWaves][R]
+    // stable branch first the per-wave digit counters [kWaves][R].
+    //
     // With 16-bit stored keys (WS) the slot branch counts bins per wave.  A
     // wave's LDS atomics run in issue order, so its entries of a bin receive
     // slots in input order when the lanes of one atomic that hit the same
@@ -508,7 +513,9 @@ __device__ int p2_group(const P2Args<KT, PK> &a, uint32_t *lds, uint32_t *sh) {
     // The branch does not rely on it: it places every entry at bin start +
     // the bin's entries of earlier waves + its slot, checks that ids ascend
     // within every bin (input order is id order), and writes the group out
-    // contiguously; a group where they do not falls back to the id walk.
+    // contiguously; a group where they do not falls back to the id walk
+    // (bins of at most kMaxFastBin), the ballot branch, or in the slot-only
+    // form to the second kernel.
     constexpr bool WS = sizeof(KT) == 2;
     uint32_t *bk = lds;
     uint32_t *bv = lds + kFastTile;
