@@ -1085,18 +1085,27 @@ bool table_packed_pass1(int64_t n, int dir_bits) {
 
 namespace {
 
-// Whole keys of tables [T0, T1) from 16-bit stored keys: a thread per
-// (table, bin) writes (bin << (31 - dir_bits)) | low for the bin's entries.
+// Whole keys of tables [T0, T1) from 16-bit stored keys: a thread per entry
+// finds its bin by a binary search of the table's directory (the largest b
+// with dir[b] <= j) and writes (b << (31 - dir_bits)) | low.  The work is
+// n log 2^dir_bits per table whatever the bin sizes.
 __global__ void expand_keys_kernel(const uint16_t *__restrict__ tk, const uint32_t *__restrict__ dir, int64_t n,
                                    int dir_bits, int T0, int64_t ntab, uint32_t *__restrict__ out) {
-    const int64_t nb = int64_t(1) << dir_bits;
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < ntab * nb;
+    const uint32_t nb = 1u << dir_bits;
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < ntab * n;
          g += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t t = g / nb, b = g - t * nb;
+        const int64_t t = g / n, j = g - t * n;
         const int64_t T = T0 + t;
-        const uint32_t *dr = dir + T * (nb + 1);
-        const uint32_t hi = uint32_t(b) << (31 - dir_bits);
-        for (uint32_t j = dr[b]; j < dr[b + 1]; ++j) out[t * n + j] = hi | tk[T * n + j];
+        const uint32_t *dr = dir + T * (int64_t(nb) + 1);
+        uint32_t lo = 0, hi = nb;  // dr[lo] <= j < dr[hi] (dr[0] = 0, dr[nb] = n)
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (dr[mid] <= uint32_t(j))
+                lo = mid;
+            else
+                hi = mid;
+        }
+        out[g] = (lo << (31 - dir_bits)) | tk[T * n + j];
     }
 }
 
@@ -1111,7 +1120,7 @@ fclsh_status expand_table_keys(const void *tkeys, int key_bytes, const uint32_t 
                                  hipMemcpyDeviceToDevice, st));
         return FCLSH_OK;
     }
-    const int64_t work = ntab << dir_bits;
+    const int64_t work = ntab * n;
     hipLaunchKernelGGL(expand_keys_kernel, dim3(unsigned(std::min<int64_t>((work + 255) / 256, 1 << 16))), dim3(256), 0,
                        st, static_cast<const uint16_t *>(tkeys), dir, n, dir_bits, T0, ntab, out);
     FCLSH_HIP(hipGetLastError());
