@@ -216,6 +216,12 @@ static void table_sizing() {
         CHECK(db >= 8 && db <= 19);
         const int sb = table_split_bits(n, db), mb = table_merge_bits(n, db);
         CHECK(sb >= 0 && mb >= 0 && sb + 8 - mb >= 1);
+        // 6-byte entries only where 16-bit keys are stored, no groups are
+        // merged (the key word then holds every key bit pass 2 reads) and the
+        // ids fit 9 + 16 bits
+        const bool pk = table_packed_pass1(n, db);
+        CHECK(!pk || (table_key_bytes(db) == 2 && 31 - db <= 16 && mb == 0 && n <= (int64_t(1) << 25)));
+        CHECK(pk == (table_key_bytes(db) == 2 && mb == 0 && n <= (int64_t(1) << 25)));
         for (int64_t L : {int64_t(1), int64_t(254), int64_t(4094), int64_t(65535)}) {
             const size_t s = table_build_scratch_bytes(L, n, db);
             CHECK(s > 0 && s < (size_t(1) << 62));
