@@ -380,14 +380,26 @@ __global__ __launch_bounds__(64 * NW) void fht_hash_kernel(const uint64_t *__res
                     t[k] = double(en.x & coord_mask(myx, en.y));
                 }
             } else {
-                // integer sums (at most d terms below 2^31: exact in 64
+                // integer sums (at most d terms below 2^32: exact in 64
                 // bits), one conversion per column
                 const int32_t *sg = seg + p * (V + 1);
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
                     uint64_t acc = 0;
                     const int e1 = sg[k + 1];
-                    for (int e = sg[k]; e < e1; ++e) {
+                    int e = sg[k];
+                    // four entries at a time: their table reads, then their
+                    // point reads, are in flight together (one at a time, an
+                    // entry took two dependent LDS round trips; batched hash
+                    // 1.83 -> 1.76 ms)
+                    for (; e + 4 <= e1; e += 4) {
+                        const uint2 a0 = tab[e * G + s], a1 = tab[(e + 1) * G + s];
+                        const uint2 a2 = tab[(e + 2) * G + s], a3 = tab[(e + 3) * G + s];
+                        const uint32_t m0 = coord_mask(myx, a0.y), m1 = coord_mask(myx, a1.y);
+                        const uint32_t m2 = coord_mask(myx, a2.y), m3 = coord_mask(myx, a3.y);
+                        acc += uint64_t(a0.x & m0) + uint64_t(a1.x & m1) + uint64_t(a2.x & m2) + uint64_t(a3.x & m3);
+                    }
+                    for (; e < e1; ++e) {
                         const uint2 en = tab[e * G + s];
                         acc += en.x & coord_mask(myx, en.y);
                     }
