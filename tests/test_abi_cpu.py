@@ -200,3 +200,17 @@ def test_null_index_is_rejected(name):
     scalars = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float, ctypes.c_double)
     args = [0 if t in scalars else None for t in fn.argtypes]  # pointers null
     assert fn(*args) == fc.FCLSH_EINVAL, name
+
+
+@pytest.mark.parametrize("flag", ["--batched", "--served"])
+def test_bench_refuses_the_switched_off_sections(flag):
+    # the two sections stay off the GPU: the benchmark exits with an error
+    # before it imports torch or touches a device
+    import json
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), flag], capture_output=True, text=True,
+                       timeout=60)
+    assert p.returncode == 2
+    assert "switched off" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
