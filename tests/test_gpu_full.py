@@ -94,7 +94,19 @@ def test_full_small():
 
 
 def test_full_mid():
-    idx = check_index(synth.mid(), 3002)
+    w = synth.mid()
+    idx = check_index(w, 3002)
+    # the launch shape the benchmark times (the autotuner's pick on this
+    # batch), then the same tile under the claim schedule: every answer of
+    # the batch equals the default shape's (sampled ones of which matched
+    # the linear scan above)
+    qd = fc.to_device_words(w.queries)
+    tune = idx.autotune(qd, w.r)
+    _say(f"[full] mid: autotuned {tune}")
+    assert_same_lists(csr_lists(*idx.query(qd, w.r)), idx._full_answers)
+    other = "claim" if tune["schedule"] == "static" else "static"
+    idx.set_schedule(other)
+    assert_same_lists(csr_lists(*idx.query(qd, w.r)), idx._full_answers)
     idx.close()
 
 
