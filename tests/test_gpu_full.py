@@ -111,7 +111,13 @@ def test_full_mid():
 
 
 def test_full_learned_code():
-    idx = check_index(synth.learned_code(), 3003, n_queries=12)
+    w = synth.learned_code()
+    idx = check_index(w, 3003, n_queries=12)
+    # the shape the benchmark times on this workload: the autotuner's pick
+    # answers the whole 10,000-query batch as the default shape does
+    qd = fc.to_device_words(w.queries)
+    _say(f"[full] learned_code: autotuned {idx.autotune(qd, w.r)}")
+    assert_same_lists(csr_lists(*idx.query(qd, w.r)), idx._full_answers)
     idx.close()
 
 
