@@ -202,6 +202,19 @@ def test_null_index_is_rejected(name):
     assert fn(*args) == fc.FCLSH_EINVAL, name
 
 
+def test_bench_runs_on_one_gpu_only():
+    # a multi-GPU request exits with a message before anything is set up
+    import json
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert p.returncode == 2
+    out = json.loads(p.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "exactly one GPU" in out["error"]
+
+
 @pytest.mark.parametrize("flag", ["--batched", "--served"])
 def test_bench_refuses_the_switched_off_sections(flag):
     # the two sections stay off the GPU: the benchmark exits with an error
